@@ -1,0 +1,179 @@
+/*
+ * ks.h -- C ABI of the MI355X real-time TDDFT hot path (libks).
+ *
+ * The method is the one of arXiv:1912.07921 ("Octopus, a computational
+ * framework for exploring light-driven phenomena and quantum dynamics in
+ * extended and finite systems"): the time-dependent Kohn-Sham equations as a
+ * first-order ODE, d(phi_i)/dt = -i H[n(t),t] phi_i (section "New propagators
+ * for real-time TDDFT"), integrated with the enforced-time-reversal-symmetry
+ * (ETRS) propagator (same section; used for the absorption run of section
+ * "van der Waals"), with H applied on a uniform real-space grid by finite
+ * differences (section "Periodic systems") to batches of states kept resident
+ * in GPU memory (section "GPUs", "Memory layout").
+ *
+ * Conventions shared by every call
+ *  - Units: Hartree atomic units (bohr, Hartree, hbar = 1).
+ *  - Grid point (x, y, z), 0 <= x < nx etc., has linear index
+ *    g = (z * ny + y) * nx + x (x fastest).  Coordinates: r_a = (i - (n-1)/2) h
+ *    on a zero-boundary axis, r_a = i h on a periodic axis (cell L = n h).
+ *  - States: complex128 (interleaved re, im), layout [nk][nstates][nz][ny][nx]
+ *    contiguous; "state j" of a call means the j-th n-point block.
+ *  - Pointers named d_* are DEVICE pointers owned by the caller (for instance
+ *    torch tensors) and borrowed for the call; every call is stream-ordered on
+ *    the grid's stream and returns before the device finishes unless noted,
+ *    so the caller keeps d_* buffers alive until the stream has drained.
+ *    Host pointers (no d_ prefix) are read during the call only.
+ *  - Every call returns 0 (KS_OK) or a negative ks_status; nothing throws
+ *    across the ABI.  ks_last_error() gives a message for the calling thread.
+ *  - A ks_grid is not thread-safe: one grid per host thread / stream.
+ *
+ * The Hamiltonian (fixed by these readings of the paper):
+ *   H = -1/2 Lap + v(r) + V_NL + [-i A(t).grad + |A(t)|^2/2]
+ *  - Lap, grad: half-width-4 central finite differences (25-point star),
+ *    weights {-205/72, 8/5, -1/5, 8/315, -1/560} and {4/5, -1/5, 4/105,
+ *    -1/280}; zero outside a non-periodic axis, Bloch phase
+ *    psi(i + n) = exp(i k_a L_a) psi(i) along a periodic axis (k-points,
+ *    section "Periodic systems").
+ *  - v = v_ion + v_x[n]; v_x = -(3 n / pi)^(1/3) (LDA exchange, section
+ *    "Local domains", E_xc^LDA; Dirac/Slater form).
+ *  - V_NL: Kleinman-Bylander projectors on atom spheres |r - R_a| < rc_a
+ *    (non-local pseudopotentials, section "Magneto-optics"):
+ *    p_lm(r) = P_lm(r) exp(-r^2 / (2 sigma^2)) (1 - r^2/rc^2)^2 with real
+ *    solid harmonics s; x, y, z; xy, yz, zx, x^2-y^2, 3z^2-r^2, normalised
+ *    so that h^3 sum p^2 = 1; C = h^3 sum p~ psi with p~ = p e^{i k.T} for
+ *    the lattice shift T that brings the point into the sphere;
+ *    V_NL psi = sum conj(p~) E_{a,l} C.
+ *  - Velocity gauge for a uniform vector potential (dipole approximation,
+ *    section "t-SURFF", Volkov Hamiltonian; section "Thermoelectric"):
+ *    A(t) = A0 sin^2(pi t / T) cos(w t) pol for 0 <= t <= T, 0 otherwise.
+ */
+#ifndef KS_H
+#define KS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ks_grid ks_grid;
+
+typedef enum {
+    KS_OK = 0,
+    KS_E_ARG = -1,          /* invalid argument, size or layout */
+    KS_E_OOM = -2,          /* a device allocation failed / workspace short */
+    KS_E_HIP = -3,          /* a HIP runtime call failed */
+    KS_E_UNSUPPORTED = -4,  /* valid input this library does not handle */
+    KS_E_STATE = -5,        /* call out of order (no potential, no workspace) */
+    KS_E_NONFINITE = -6     /* a norm became NaN or Inf */
+} ks_status;
+
+typedef enum {
+    KS_FP64 = 0,   /* everything in FP64 */
+    KS_MIXED = 1   /* H.psi terms in complex FP32 with FP32 accumulation;
+                      psi update sum, norms, density, dipole in FP64 */
+} ks_precision;
+
+typedef struct {
+    int n[3];            /* nx, ny, nz >= 1; nx <= 256 */
+    double h[3];         /* grid spacing per axis (bohr), > 0 */
+    int periodic[3];     /* 1: Bloch-periodic axis, 0: zero boundary */
+    int fd_half_width;   /* must be 4 (25-point star); else KS_E_UNSUPPORTED */
+    int nk;              /* k-points >= 1 (all zero for a finite system) */
+    const double *kpts;  /* host, nk*3, bohr^-1; NULL: all zero */
+    const double *kw;    /* host, nk weights; NULL: 1/nk each */
+    int nstates;         /* states per k-point >= 1 */
+    const double *occ;   /* host, nstates occupations; NULL: 2 each */
+    int natoms;          /* >= 0 */
+    const double *pos;   /* host, natoms*3 (bohr) */
+    const int *lmax;     /* host, natoms, 0 (s), 1 (s+p) or 2 (s+p+d) */
+    const double *rc;    /* host, natoms; periodic axes need rc < L/2 */
+    const double *sigma; /* host, natoms */
+    const double *E;     /* host, natoms*3: E[a*3 + l] (Hartree) */
+    int xc;              /* 0: v = v_ion; 1: v = v_ion + LDA exchange */
+    double laser[6];     /* A0, omega, T, pol_x, pol_y, pol_z; A0 = 0: off */
+    int precision;       /* ks_precision */
+    void *stream;        /* hipStream_t the calls are ordered on (NULL:
+                            the default stream) */
+} ks_grid_desc;
+
+/* Create a grid object: copies the description, builds the projector
+ * spheres and tables and uploads them (device memory owned by the object).
+ * Synchronous.  *out is NULL on error. */
+int ks_grid_create(const ks_grid_desc *desc, ks_grid **out);
+
+/* Free the object and its device tables; waits for its stream first. */
+int ks_grid_destroy(ks_grid *g);
+
+/* Change the stream later calls are ordered on. */
+int ks_set_stream(ks_grid *g, void *stream);
+
+/* Bytes of device scratch ks_propagate_etrs and ks_apply_h need (t-terms,
+ * the half-step state, density partials, projector coefficients). */
+size_t ks_workspace_bytes(const ks_grid *g);
+
+/* Lend the object a caller-owned device workspace of at least
+ * ks_workspace_bytes() bytes, 256-byte aligned; KS_E_OOM if too small. */
+int ks_set_workspace(ks_grid *g, void *d_ws, size_t bytes);
+
+/* v = v_ion + v_x[rho] into the object's local potential (N doubles);
+ * d_rho NULL (or xc == 0): v = v_ion.  (One-body potential of
+ * eq. Hamiltonian_dipole; LDA of section "Local domains".) */
+int ks_update_vlocal(ks_grid *g, const double *d_vion, const double *d_rho);
+
+/* d_hpsi = H(t) d_psi for ns states (each n points, complex128) of k-point
+ * k, using the object's current local potential and A(t).  s0 is the index
+ * of the first state within the k-point (it selects occupations only).
+ * In KS_MIXED the arithmetic is FP32 (input and output stay complex128).
+ * Needs a workspace.  d_psi and d_hpsi must not overlap. */
+int ks_apply_h(ks_grid *g, const void *d_psi, void *d_hpsi, int k, int s0,
+               int ns, double t);
+
+/* Propagate all nk*nstates states in d_psi, in place, by nsteps ETRS steps
+ * of dt from t0.  Each step: H_t^j psi, j = 1..4 (Taylor-4, H frozen);
+ * psi_half = sum (-i dt/2)^j H^j psi / j!; predictor
+ * sum (-i dt)^j H^j psi / j! (same powers) gives n_pred and
+ * v(t+dt) = v_ion + v_x[n_pred]; psi(t+dt) = T4(dt/2, H_{t+dt}) psi_half;
+ * v is rebuilt from n(psi(t+dt)).  v(t0) is built from n(psi(t0)) first.
+ * d_dipole: device (nsteps+1)*3 doubles, d(t_i) = h^3 sum r n (zero-boundary
+ * grids only; NULL to skip).  d_norms: device (nsteps+1)*nk*nstates doubles,
+ * h^3 sum |psi|^2 per state (NULL to skip).  d_vion must stay valid until
+ * the stream drains.  Needs a workspace. */
+int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
+                      int nsteps, double dt, double t0, double *d_dipole,
+                      double *d_norms);
+
+/* d_rho[g] = sum_k w_k sum_s f_s |psi_ks(g)|^2 over all nk*nstates states
+ * (section "Local domains", n = sum of densities). */
+int ks_density(ks_grid *g, const void *d_psi, double *d_rho);
+
+/* out_host = h^3 sum_g r_g rho_g (dipole equation of section "Local
+ * domains").  Synchronises the stream.  KS_E_UNSUPPORTED on a grid with a
+ * periodic axis (the dipole of a periodic system is not defined). */
+int ks_dipole(ks_grid *g, const double *d_rho, double out_host[3]);
+
+/* psi <- exp(i kappa z) psi for all states (delta kick along z, the
+ * perturbation of the absorption run in section "van der Waals"). */
+int ks_kick(ks_grid *g, void *d_psi, double kappa);
+
+/* d_norms[j] = h^3 sum_g |psi_j(g)|^2 for all nk*nstates states. */
+int ks_norms(ks_grid *g, const void *d_psi, double *d_norms);
+
+/* d_gram[k][i][j] = h^3 sum_g conj(psi_ki(g)) psi_kj(g), complex128,
+ * nk*nstates*nstates entries (orthonormality check). */
+int ks_gram(ks_grid *g, const void *d_psi, void *d_gram);
+
+/* Total energy sum_k w_k sum_s f_s <psi|T + v_ion + V_NL + gauge(t)|psi>
+ * + E_x[n], E_x = -(3/4)(3/pi)^(1/3) h^3 sum n^(4/3) when xc == 1.
+ * Synchronises the stream.  Needs a workspace. */
+int ks_energy(ks_grid *g, const void *d_psi, const double *d_vion, double t,
+              double *out_host);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *ks_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KS_H */

@@ -1,0 +1,879 @@
+// C ABI of libks: argument checks, projector set-up, workspace layout and the
+// sequencing of the ETRS step (section "New propagators for real-time TDDFT")
+// over the gfx950 kernels of ks_kernels.hip.
+#include "../../include/ks.h"
+#include "ks_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace ks;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define KS_HIP(call)                                                         \
+    do {                                                                     \
+        hipError_t e_ = (call);                                              \
+        if (e_ != hipSuccess)                                                \
+            return fail(KS_E_HIP, "%s: %s", #call, hipGetErrorString(e_));   \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct ks_grid {
+    Geo geo;
+    int nk = 1, ns = 1, stot = 1;
+    std::vector<double> kpts, kw, occ, wocc, kL;
+    int xc = 0;
+    double laser[6] = {0, 0, 0, 0, 0, 0};
+    bool mixed = false;
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    // owned device memory
+    std::vector<void *> owned;
+    double *d_v = nullptr;       // current local potential
+    double *d_kL = nullptr;
+    double *d_wocc = nullptr;
+    bool vloc_set = false;
+
+    // projectors
+    ProjDev pj;
+    int natoms = 0;
+    long total_pts = 0;
+    std::vector<int> h_npts, h_nproj;
+
+    // launch shape
+    int TY = 1, zchunk = 1, ntile_y = 1, nzc = 1;
+
+    // workspace
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    struct {
+        size_t t1, t2, t3, half, npart, normpart, D, rho, vpred, dpart,
+            gpart, dotpart, xpart, total;
+    } lay{};
+    int ntiles_max = 64;
+    int gram_ksplit = 16;
+    int norm_chunks = 64;
+};
+
+namespace {
+
+template <class T> int dev_alloc(ks_grid *g, T **p, size_t count)
+{
+    void *q = nullptr;
+    size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess)
+        return fail(KS_E_OOM, "hipMalloc(%zu): %s", bytes,
+                    hipGetErrorString(e));
+    g->owned.push_back(q);
+    *p = static_cast<T *>(q);
+    return KS_OK;
+}
+
+template <class T>
+int dev_upload(ks_grid *g, T **p, const std::vector<T> &host)
+{
+    int rc = dev_alloc(g, p, host.size());
+    if (rc)
+        return rc;
+    if (!host.empty())
+        KS_HIP(hipMemcpy(*p, host.data(), host.size() * sizeof(T),
+                         hipMemcpyHostToDevice));
+    return KS_OK;
+}
+
+double axis_coord(const Geo &G, int axis, int i)
+{
+    int n = axis == 0 ? G.nx : (axis == 1 ? G.ny : G.nz);
+    return G.per[axis] ? i * G.h[axis] : (i - 0.5 * (n - 1)) * G.h[axis];
+}
+
+double solid_harm(int j, double x, double y, double z)
+{
+    switch (j) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return y;
+    case 3: return z;
+    case 4: return x * y;
+    case 5: return y * z;
+    case 6: return z * x;
+    case 7: return x * x - y * y;
+    default: return 3.0 * z * z - (x * x + y * y + z * z);
+    }
+}
+
+// Build sphere point lists, normalised projector tables, the grid-point
+// scatter CSR, and upload them.
+int build_projectors(ks_grid *g, const ks_grid_desc *d)
+{
+    const Geo &G = g->geo;
+    const int na = d->natoms;
+    g->natoms = na;
+    g->pj.natoms = na;
+    if (na == 0)
+        return KS_OK;
+    const int n3[3] = {G.nx, G.ny, G.nz};
+    std::vector<int> nproj(na), npts(na);
+    std::vector<long> ioff(na), poff(na);
+    std::vector<int> sidx, sshift;
+    std::vector<double> ptab, Ej((size_t)na * kMaxProj, 0.0);
+    const double h3 = G.h[0] * G.h[1] * G.h[2];
+    for (int a = 0; a < na; ++a) {
+        const int lmax = d->lmax[a];
+        const double rc = d->rc[a], sg = d->sigma[a];
+        const double X[3] = {d->pos[3 * a], d->pos[3 * a + 1],
+                             d->pos[3 * a + 2]};
+        if (lmax < 0 || lmax > 2)
+            return fail(KS_E_ARG, "atom %d: lmax %d not in 0..2", a, lmax);
+        if (!(rc > 0.0) || !(sg > 0.0))
+            return fail(KS_E_ARG, "atom %d: rc and sigma must be > 0", a);
+        for (int ax = 0; ax < 3; ++ax)
+            if (G.per[ax] && !(rc < 0.5 * n3[ax] * G.h[ax]))
+                return fail(KS_E_UNSUPPORTED,
+                            "atom %d: rc must be below half the cell", a);
+        nproj[a] = (lmax + 1) * (lmax + 1);
+        for (int j = 0; j < nproj[a]; ++j) {
+            int l = j == 0 ? 0 : (j < 4 ? 1 : 2);
+            Ej[(size_t)a * kMaxProj + j] = h3 * d->E[3 * a + l];
+        }
+        // index ranges (unwrapped) of the bounding box of the sphere
+        int lo[3], hi[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            double o = axis_coord(G, ax, 0);
+            lo[ax] = (int)std::floor((X[ax] - rc - o) / G.h[ax]) - 1;
+            hi[ax] = (int)std::ceil((X[ax] + rc - o) / G.h[ax]) + 1;
+            if (!G.per[ax]) {
+                lo[ax] = std::max(lo[ax], 0);
+                hi[ax] = std::min(hi[ax], n3[ax] - 1);
+            }
+        }
+        ioff[a] = (long)sidx.size();
+        std::vector<double> disp;  // 3 per point
+        std::vector<int> gidx, code;
+        for (int iz = lo[2]; iz <= hi[2]; ++iz)
+            for (int iy = lo[1]; iy <= hi[1]; ++iy)
+                for (int ix = lo[0]; ix <= hi[0]; ++ix) {
+                    const int ii[3] = {ix, iy, iz};
+                    int w[3], wr[3];
+                    double r[3], r2 = 0.0;
+                    for (int ax = 0; ax < 3; ++ax) {
+                        int n = n3[ax];
+                        int q = ii[ax];
+                        int ww = q >= 0 ? q / n : -((-q + n - 1) / n);
+                        w[ax] = ww;
+                        wr[ax] = q - ww * n;
+                        r[ax] = axis_coord(G, ax, wr[ax]) +
+                                ww * n * G.h[ax] - X[ax];
+                        r2 += r[ax] * r[ax];
+                    }
+                    if (!(r2 < rc * rc))
+                        continue;
+                    gidx.push_back((wr[2] * G.ny + wr[1]) * G.nx + wr[0]);
+                    int c = (w[0] & 0xff) | ((w[1] & 0xff) << 8) |
+                            ((w[2] & 0xff) << 16);
+                    code.push_back(c);
+                    disp.push_back(r[0]);
+                    disp.push_back(r[1]);
+                    disp.push_back(r[2]);
+                }
+        const int np = (int)gidx.size();
+        npts[a] = np;
+        poff[a] = (long)ptab.size();
+        ptab.resize(ptab.size() + (size_t)nproj[a] * np);
+        double *pa = ptab.data() + poff[a];
+        for (int i = 0; i < np; ++i) {
+            const double *r = &disp[3 * i];
+            double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            double win = 1.0 - rr / (rc * rc);
+            double rad = std::exp(-rr / (2.0 * sg * sg)) * win * win;
+            for (int j = 0; j < nproj[a]; ++j)
+                pa[(size_t)j * np + i] = solid_harm(j, r[0], r[1], r[2]) * rad;
+        }
+        for (int j = 0; j < nproj[a]; ++j) {
+            double s = 0.0;
+            for (int i = 0; i < np; ++i)
+                s += pa[(size_t)j * np + i] * pa[(size_t)j * np + i];
+            s *= h3;
+            double f = s > 0.0 ? 1.0 / std::sqrt(s) : 0.0;
+            for (int i = 0; i < np; ++i)
+                pa[(size_t)j * np + i] *= f;
+        }
+        sidx.insert(sidx.end(), gidx.begin(), gidx.end());
+        sshift.insert(sshift.end(), code.begin(), code.end());
+    }
+    g->total_pts = (long)sidx.size();
+    g->h_npts = npts;
+    g->h_nproj = nproj;
+    // scatter CSR over grid points
+    const long N = G.N;
+    std::vector<int> soff(N + 1, 0);
+    for (int a = 0; a < na; ++a)
+        for (int i = 0; i < npts[a]; ++i)
+            soff[sidx[ioff[a] + i] + 1]++;
+    for (long i = 0; i < N; ++i)
+        soff[i + 1] += soff[i];
+    std::vector<int2> sent(std::max(1, soff[N]));
+    std::vector<int> fillp(soff.begin(), soff.end() - 1);
+    for (int a = 0; a < na; ++a)
+        for (int i = 0; i < npts[a]; ++i) {
+            int gg = sidx[ioff[a] + i];
+            sent[fillp[gg]++] = make_int2(a, i);
+        }
+    std::vector<unsigned char> rowhit((size_t)G.nz * G.ny, 0);
+    for (long i = 0; i < N; ++i)
+        if (soff[i + 1] > soff[i])
+            rowhit[i / G.nx] = 1;
+    std::vector<float> ptabf(ptab.begin(), ptab.end());
+
+    int *d_nproj, *d_npts, *d_sidx, *d_sshift, *d_soff;
+    long *d_ioff, *d_poff;
+    double *d_ptab, *d_Ej;
+    float *d_ptabf;
+    int2 *d_sent;
+    unsigned char *d_rowhit;
+    int rc;
+    if ((rc = dev_upload(g, &d_nproj, nproj)) ||
+        (rc = dev_upload(g, &d_npts, npts)) ||
+        (rc = dev_upload(g, &d_ioff, ioff)) ||
+        (rc = dev_upload(g, &d_poff, poff)) ||
+        (rc = dev_upload(g, &d_sidx, sidx)) ||
+        (rc = dev_upload(g, &d_sshift, sshift)) ||
+        (rc = dev_upload(g, &d_ptab, ptab)) ||
+        (rc = dev_upload(g, &d_ptabf, ptabf)) ||
+        (rc = dev_upload(g, &d_Ej, Ej)) ||
+        (rc = dev_upload(g, &d_soff, soff)) ||
+        (rc = dev_upload(g, &d_sent, sent)) ||
+        (rc = dev_upload(g, &d_rowhit, rowhit)))
+        return rc;
+    g->pj.nproj = d_nproj;
+    g->pj.npts = d_npts;
+    g->pj.ioff = d_ioff;
+    g->pj.poff = d_poff;
+    g->pj.sidx = d_sidx;
+    g->pj.sshift = d_sshift;
+    g->pj.ptab = d_ptab;
+    g->pj.ptabf = d_ptabf;
+    g->pj.Ej = d_Ej;
+    g->pj.soff = d_soff;
+    g->pj.sent = d_sent;
+    g->pj.rowhit = d_rowhit;
+    return KS_OK;
+}
+
+void choose_tiles(ks_grid *g)
+{
+    const Geo &G = g->geo;
+    // nx <= 256, so TY >= 2 and a workgroup has at most 512 threads
+    int TY = std::max(1, std::min(G.ny, 512 / G.nx));
+    g->TY = TY;
+    g->ntile_y = (G.ny + TY - 1) / TY;
+    // enough workgroups to fill 256 CUs several times over
+    long per_state = g->ntile_y;
+    int nzc = (int)std::max<long>(1, 2048 / std::max<long>(1, per_state *
+                                                                 g->stot));
+    nzc = std::min(nzc, std::max(1, G.nz / 8));
+    g->zchunk = (G.nz + nzc - 1) / nzc;
+    g->nzc = (G.nz + g->zchunk - 1) / g->zchunk;
+}
+
+void layout(ks_grid *g)
+{
+    const size_t N = g->geo.N, S = g->stot;
+    const size_t tb = S * N * (g->mixed ? 8 : 16);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(std::max<size_t>(bytes, 16));
+        return o;
+    };
+    g->ntiles_max = std::max(g->ntile_y * g->nzc, g->norm_chunks);
+    const size_t ndb = density_blocks((long)N);
+    g->lay.t1 = take(tb);
+    g->lay.t2 = take(tb);
+    g->lay.t3 = take(tb);
+    g->lay.half = take(S * N * 16);
+    g->lay.npart = take(S * N * 8);
+    g->lay.normpart = take(S * g->ntiles_max * 8);
+    g->lay.D = take(S * std::max(1, g->natoms) * kMaxProj * 16);
+    g->lay.rho = take(N * 8);
+    g->lay.vpred = take(N * 8);
+    g->lay.dpart = take(ndb * 3 * 8);
+    g->lay.gpart = take((size_t)g->gram_ksplit * g->nk * g->ns * g->ns * 16);
+    g->lay.dotpart = take(S * g->norm_chunks * 16);
+    g->lay.xpart = take(ndb * 8);
+    g->lay.total = off;
+}
+
+template <class T> T *wsp(ks_grid *g, size_t off)
+{
+    return reinterpret_cast<T *>(g->ws + off);
+}
+
+void laser_A(const ks_grid *g, double t, double A[3])
+{
+    const double *L = g->laser;
+    double a = 0.0;
+    if (L[0] != 0.0 && t >= 0.0 && t <= L[2]) {
+        double s = std::sin(M_PI * t / L[2]);
+        a = L[0] * s * s * std::cos(L[1] * t);
+    }
+    A[0] = a * L[3];
+    A[1] = a * L[4];
+    A[2] = a * L[5];
+}
+
+HArgs base_hargs(ks_grid *g)
+{
+    HArgs a;
+    a.geo = g->geo;
+    a.kL = g->d_kL;
+    a.nstates = g->ns;
+    a.wocc = g->d_wocc;
+    a.pj = g->pj;
+    a.TY = g->TY;
+    a.zchunk = g->zchunk;
+    a.ntile_y = g->ntile_y;
+    a.nzc = g->nzc;
+    return a;
+}
+
+GArgs base_gargs(ks_grid *g)
+{
+    GArgs a;
+    a.geo = g->geo;
+    a.kL = g->d_kL;
+    a.nstates = g->ns;
+    a.pj = g->pj;
+    return a;
+}
+
+int need_ws(const ks_grid *g)
+{
+    if (!g->ws)
+        return fail(KS_E_STATE, "no workspace set (ks_set_workspace)");
+    return KS_OK;
+}
+
+// One Taylor-4 exponential of H (potential v, vector potential A) with
+// step tau applied to all states in `in`: t_j = (-i tau / j) H t_{j-1};
+// the last pass writes out = in + t1 + t2 + t3 + t4 (mode kFinal) or also the
+// predictor density (kFinalPred).
+int taylor_exponential(ks_grid *g, const double2 *in, double2 *out,
+                       const double *v, const double A[3], double tau,
+                       int final_mode, double *npart, double *normpart)
+{
+    const int S = g->stot;
+    const bool mx = g->mixed;
+    void *tb[3] = {g->ws + g->lay.t1, g->ws + g->lay.t2, g->ws + g->lay.t3};
+    void *D = g->ws + g->lay.D;
+    HArgs a = base_hargs(g);
+    a.v = v;
+    a.A[0] = A[0];
+    a.A[1] = A[1];
+    a.A[2] = A[2];
+    a.a2half = 0.5 * (A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+    a.D = D;
+    GArgs ga = base_gargs(g);
+    ga.D = D;
+    const void *cur = in;
+    for (int j = 1; j <= 4; ++j) {
+        const bool f64 = (j == 1) || !mx;
+        ga.in = cur;
+        KS_HIP(launch_gather(mx, f64, ga, S, g->stream));
+        a.in = cur;
+        a.cre = 0.0;
+        a.cim = -tau / j;
+        if (j < 4) {
+            a.out = tb[j - 1];
+            KS_HIP(launch_hpsi(kTerm, mx, f64, a, S, g->stream));
+            cur = tb[j - 1];
+        } else {
+            a.out = out;
+            a.base = in;
+            a.t1 = tb[0];
+            a.t2 = tb[1];
+            a.npart = npart;
+            a.normpart = normpart;
+            KS_HIP(launch_hpsi(final_mode, mx, false, a, S, g->stream));
+        }
+    }
+    return KS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *ks_last_error(void) { return g_err.c_str(); }
+
+int ks_grid_create(const ks_grid_desc *d, ks_grid **out)
+{
+    if (!out)
+        return fail(KS_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!d)
+        return fail(KS_E_ARG, "desc is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (d->n[a] < 1)
+            return fail(KS_E_ARG, "n[%d] = %d must be >= 1", a, d->n[a]);
+        if (!(d->h[a] > 0.0))
+            return fail(KS_E_ARG, "h[%d] must be > 0", a);
+    }
+    if (d->n[0] > 256)
+        return fail(KS_E_UNSUPPORTED, "nx = %d > 256", d->n[0]);
+    if (d->fd_half_width != 4)
+        return fail(KS_E_UNSUPPORTED, "fd_half_width %d (only 4)",
+                    d->fd_half_width);
+    const long N = (long)d->n[0] * d->n[1] * d->n[2];
+    if (N >= (1L << 31))
+        return fail(KS_E_UNSUPPORTED, "grid of %ld points exceeds 2^31", N);
+    if (d->nk < 1 || d->nstates < 1 || d->natoms < 0)
+        return fail(KS_E_ARG, "nk, nstates must be >= 1, natoms >= 0");
+    if ((long)d->nk * d->nstates > 65535)
+        return fail(KS_E_UNSUPPORTED, "nk*nstates > 65535");
+    if (d->natoms > 0 && (!d->pos || !d->lmax || !d->rc || !d->sigma || !d->E))
+        return fail(KS_E_ARG, "atom arrays missing");
+    if (d->xc != 0 && d->xc != 1)
+        return fail(KS_E_ARG, "xc must be 0 or 1");
+    if (d->precision != KS_FP64 && d->precision != KS_MIXED)
+        return fail(KS_E_ARG, "precision must be KS_FP64 or KS_MIXED");
+    if (d->laser[0] != 0.0 && !(d->laser[2] > 0.0))
+        return fail(KS_E_ARG, "laser duration must be > 0");
+
+    ks_grid *g = new ks_grid;
+    g->geo.nx = d->n[0];
+    g->geo.ny = d->n[1];
+    g->geo.nz = d->n[2];
+    g->geo.N = N;
+    for (int a = 0; a < 3; ++a) {
+        g->geo.per[a] = d->periodic[a] ? 1 : 0;
+        g->geo.h[a] = d->h[a];
+    }
+    g->nk = d->nk;
+    g->ns = d->nstates;
+    g->stot = d->nk * d->nstates;
+    g->xc = d->xc;
+    std::memcpy(g->laser, d->laser, sizeof g->laser);
+    g->mixed = d->precision == KS_MIXED;
+    g->stream = static_cast<hipStream_t>(d->stream);
+    g->kpts.assign(3 * d->nk, 0.0);
+    if (d->kpts)
+        g->kpts.assign(d->kpts, d->kpts + 3 * d->nk);
+    g->kw.assign(d->nk, 1.0 / d->nk);
+    if (d->kw)
+        g->kw.assign(d->kw, d->kw + d->nk);
+    g->occ.assign(d->nstates, 2.0);
+    if (d->occ)
+        g->occ.assign(d->occ, d->occ + d->nstates);
+    g->wocc.resize(g->stot);
+    for (int k = 0; k < d->nk; ++k)
+        for (int s = 0; s < d->nstates; ++s)
+            g->wocc[k * d->nstates + s] = g->kw[k] * g->occ[s];
+    g->kL.resize(3 * d->nk);
+    for (int k = 0; k < d->nk; ++k)
+        for (int a = 0; a < 3; ++a)
+            g->kL[3 * k + a] = g->kpts[3 * k + a] * d->n[a] * d->h[a];
+    hipGetDevice(&g->device);
+    int rc;
+    if ((rc = dev_upload(g, &g->d_kL, g->kL)) ||
+        (rc = dev_upload(g, &g->d_wocc, g->wocc)) ||
+        (rc = dev_alloc(g, &g->d_v, (size_t)N)) ||
+        (rc = build_projectors(g, d))) {
+        ks_grid_destroy(g);
+        return rc;
+    }
+    choose_tiles(g);
+    layout(g);
+    *out = g;
+    return KS_OK;
+}
+
+int ks_grid_destroy(ks_grid *g)
+{
+    if (!g)
+        return KS_OK;
+    hipStreamSynchronize(g->stream);
+    for (void *p : g->owned)
+        hipFree(p);
+    delete g;
+    return KS_OK;
+}
+
+int ks_set_stream(ks_grid *g, void *stream)
+{
+    if (!g)
+        return fail(KS_E_ARG, "grid is NULL");
+    g->stream = static_cast<hipStream_t>(stream);
+    return KS_OK;
+}
+
+size_t ks_workspace_bytes(const ks_grid *g) { return g ? g->lay.total : 0; }
+
+int ks_set_workspace(ks_grid *g, void *d_ws, size_t bytes)
+{
+    if (!g)
+        return fail(KS_E_ARG, "grid is NULL");
+    if (!d_ws)
+        return fail(KS_E_ARG, "workspace pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(d_ws) % 256)
+        return fail(KS_E_ARG, "workspace must be 256-byte aligned");
+    if (bytes < g->lay.total)
+        return fail(KS_E_OOM, "workspace of %zu bytes < %zu needed", bytes,
+                    g->lay.total);
+    g->ws = static_cast<char *>(d_ws);
+    g->ws_bytes = bytes;
+    return KS_OK;
+}
+
+int ks_update_vlocal(ks_grid *g, const double *d_vion, const double *d_rho)
+{
+    if (!g || !d_vion)
+        return fail(KS_E_ARG, "grid or v_ion is NULL");
+    // v = v_ion + v_x(rho): the density kernel with rho itself as the one
+    // source partial (no source at all when rho is not given)
+    DArgs a;
+    a.geo = g->geo;
+    a.vion = d_vion;
+    a.vout = g->d_v;
+    a.xc = (d_rho && g->xc) ? 1 : 0;
+    a.nsrc = d_rho ? 1 : 0;
+    a.npart = d_rho ? d_rho : d_vion;  // not read when nsrc == 0
+    KS_HIP(launch_density(a, g->stream));
+    g->vloc_set = true;
+    return KS_OK;
+}
+
+int ks_apply_h(ks_grid *g, const void *d_psi, void *d_hpsi, int k, int s0,
+               int ns, double t)
+{
+    if (!g || !d_psi || !d_hpsi)
+        return fail(KS_E_ARG, "NULL argument");
+    if (k < 0 || k >= g->nk || s0 < 0 || ns < 0 || s0 + ns > g->ns)
+        return fail(KS_E_ARG, "k=%d s0=%d ns=%d out of range", k, s0, ns);
+    if (d_psi == d_hpsi)
+        return fail(KS_E_ARG, "d_psi and d_hpsi must not overlap");
+    if (!g->vloc_set)
+        return fail(KS_E_STATE, "no local potential (ks_update_vlocal)");
+    int rc = need_ws(g);
+    if (rc)
+        return rc;
+    double A[3];
+    laser_A(g, t, A);
+    void *D = g->ws + g->lay.D;
+    GArgs ga = base_gargs(g);
+    ga.in = d_psi;
+    ga.D = D;
+    ga.sg0 = k * g->ns + s0;
+    KS_HIP(launch_gather(g->mixed, true, ga, ns, g->stream));
+    HArgs a = base_hargs(g);
+    a.in = d_psi;
+    a.out = d_hpsi;
+    a.v = g->d_v;
+    a.A[0] = A[0];
+    a.A[1] = A[1];
+    a.A[2] = A[2];
+    a.a2half = 0.5 * (A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+    a.D = D;
+    a.sg0 = k * g->ns + s0;
+    KS_HIP(launch_hpsi(kApply, g->mixed, true, a, ns, g->stream));
+    return KS_OK;
+}
+
+int ks_density(ks_grid *g, const void *d_psi, double *d_rho)
+{
+    if (!g || !d_psi || !d_rho)
+        return fail(KS_E_ARG, "NULL argument");
+    DArgs a;
+    a.geo = g->geo;
+    a.nsrc = g->stot;
+    a.psi = static_cast<const double2 *>(d_psi);
+    a.wocc = g->d_wocc;
+    a.rho = d_rho;
+    KS_HIP(launch_density(a, g->stream));
+    return KS_OK;
+}
+
+int ks_dipole(ks_grid *g, const double *d_rho, double out_host[3])
+{
+    if (!g || !d_rho || !out_host)
+        return fail(KS_E_ARG, "NULL argument");
+    if (g->geo.per[0] || g->geo.per[1] || g->geo.per[2])
+        return fail(KS_E_UNSUPPORTED, "dipole of a periodic grid");
+    int rc = need_ws(g);
+    if (rc)
+        return rc;
+    // rho -> rho (copy into the workspace) with dipole partials
+    DArgs a;
+    a.geo = g->geo;
+    a.nsrc = 1;
+    a.npart = d_rho;
+    a.dpart = wsp<double>(g, g->lay.dpart);
+    KS_HIP(launch_density(a, g->stream));
+    double *dout = wsp<double>(g, g->lay.xpart);
+    const double h3 = g->geo.h[0] * g->geo.h[1] * g->geo.h[2];
+    KS_HIP(launch_dipole_finalize(a.dpart, density_blocks(g->geo.N), h3, dout,
+                                  g->stream));
+    KS_HIP(hipMemcpyAsync(out_host, dout, 3 * sizeof(double),
+                          hipMemcpyDeviceToHost, g->stream));
+    KS_HIP(hipStreamSynchronize(g->stream));
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(out_host[c]))
+            return fail(KS_E_NONFINITE, "dipole is not finite");
+    return KS_OK;
+}
+
+int ks_kick(ks_grid *g, void *d_psi, double kappa)
+{
+    if (!g || !d_psi)
+        return fail(KS_E_ARG, "NULL argument");
+    KS_HIP(launch_kick(g->geo, static_cast<double2 *>(d_psi), g->stot, kappa,
+                       g->stream));
+    return KS_OK;
+}
+
+int ks_norms(ks_grid *g, const void *d_psi, double *d_norms)
+{
+    if (!g || !d_psi || !d_norms)
+        return fail(KS_E_ARG, "NULL argument");
+    int rc = need_ws(g);
+    if (rc)
+        return rc;
+    double *part = wsp<double>(g, g->lay.normpart);
+    const double h3 = g->geo.h[0] * g->geo.h[1] * g->geo.h[2];
+    KS_HIP(launch_norm_partial(g->geo, static_cast<const double2 *>(d_psi),
+                               g->stot, g->norm_chunks, part, g->stream));
+    KS_HIP(launch_norm_finalize(part, g->stot, g->norm_chunks, h3, d_norms,
+                                g->stream));
+    return KS_OK;
+}
+
+int ks_gram(ks_grid *g, const void *d_psi, void *d_gram)
+{
+    if (!g || !d_psi || !d_gram)
+        return fail(KS_E_ARG, "NULL argument");
+    int rc = need_ws(g);
+    if (rc)
+        return rc;
+    KS_HIP(launch_gram(g->geo, static_cast<const double2 *>(d_psi), g->nk,
+                       g->ns, wsp<double2>(g, g->lay.gpart), g->gram_ksplit,
+                       static_cast<double2 *>(d_gram), g->stream));
+    return KS_OK;
+}
+
+int ks_energy(ks_grid *g, const void *d_psi, const double *d_vion, double t,
+              double *out_host)
+{
+    if (!g || !d_psi || !d_vion || !out_host)
+        return fail(KS_E_ARG, "NULL argument");
+    int rc = need_ws(g);
+    if (rc)
+        return rc;
+    if (g->mixed)
+        return fail(KS_E_UNSUPPORTED, "ks_energy runs on an FP64 grid");
+    // H[v_ion] psi for every k into the half-step buffer
+    double A[3];
+    laser_A(g, t, A);
+    double2 *hp = wsp<double2>(g, g->lay.half);
+    const double2 *psi = static_cast<const double2 *>(d_psi);
+    void *D = g->ws + g->lay.D;
+    const long N = g->geo.N;
+    for (int k = 0; k < g->nk; ++k) {
+        GArgs ga = base_gargs(g);
+        ga.in = psi + (size_t)k * g->ns * N;
+        ga.D = D;
+        ga.sg0 = k * g->ns;
+        KS_HIP(launch_gather(false, true, ga, g->ns, g->stream));
+        HArgs a = base_hargs(g);
+        a.in = ga.in;
+        a.out = hp + (size_t)k * g->ns * N;
+        a.v = d_vion;
+        a.A[0] = A[0];
+        a.A[1] = A[1];
+        a.A[2] = A[2];
+        a.a2half = 0.5 * (A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+        a.D = D;
+        a.sg0 = k * g->ns;
+        KS_HIP(launch_hpsi(kApply, false, true, a, g->ns, g->stream));
+    }
+    double2 *dp = wsp<double2>(g, g->lay.dotpart);
+    KS_HIP(launch_dot_partial(g->geo, psi, hp, g->stot, g->norm_chunks, dp,
+                              g->stream));
+    std::vector<double2> hdp((size_t)g->stot * g->norm_chunks);
+    KS_HIP(hipMemcpyAsync(hdp.data(), dp, hdp.size() * sizeof(double2),
+                          hipMemcpyDeviceToHost, g->stream));
+    double ex = 0.0;
+    const int nb = density_blocks(N);
+    std::vector<double> hx;
+    if (g->xc) {
+        DArgs a;
+        a.geo = g->geo;
+        a.nsrc = g->stot;
+        a.psi = psi;
+        a.wocc = g->d_wocc;
+        a.rho = wsp<double>(g, g->lay.rho);
+        KS_HIP(launch_density(a, g->stream));
+        KS_HIP(launch_exchange_partial(g->geo, a.rho,
+                                       wsp<double>(g, g->lay.xpart),
+                                       g->stream));
+        hx.resize(nb);
+        KS_HIP(hipMemcpyAsync(hx.data(), wsp<double>(g, g->lay.xpart),
+                              nb * sizeof(double), hipMemcpyDeviceToHost,
+                              g->stream));
+    }
+    KS_HIP(hipStreamSynchronize(g->stream));
+    const double h3 = g->geo.h[0] * g->geo.h[1] * g->geo.h[2];
+    double e = 0.0;
+    for (int s = 0; s < g->stot; ++s) {
+        double acc = 0.0;
+        for (int c = 0; c < g->norm_chunks; ++c)
+            acc += hdp[(size_t)s * g->norm_chunks + c].x;
+        e += g->wocc[s] * acc * h3;
+    }
+    if (g->xc) {
+        double sx = 0.0;
+        for (int b = 0; b < nb; ++b)
+            sx += hx[b];
+        ex = -0.75 * std::cbrt(3.0 / M_PI) * h3 * sx;
+    }
+    *out_host = e + ex;
+    if (!std::isfinite(*out_host))
+        return fail(KS_E_NONFINITE, "energy is not finite");
+    return KS_OK;
+}
+
+int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
+                      int nsteps, double dt, double t0, double *d_dipole,
+                      double *d_norms)
+{
+    if (!g || !d_psi || !d_vion)
+        return fail(KS_E_ARG, "NULL argument");
+    if (nsteps < 0)
+        return fail(KS_E_ARG, "nsteps < 0");
+    if (!std::isfinite(dt) || !std::isfinite(t0))
+        return fail(KS_E_ARG, "dt and t0 must be finite");
+    if (d_dipole && (g->geo.per[0] || g->geo.per[1] || g->geo.per[2]))
+        return fail(KS_E_UNSUPPORTED, "dipole of a periodic grid");
+    int rc = need_ws(g);
+    if (rc)
+        return rc;
+    double2 *psi = static_cast<double2 *>(d_psi);
+    double2 *half = wsp<double2>(g, g->lay.half);
+    double *npart = wsp<double>(g, g->lay.npart);
+    double *normpart = wsp<double>(g, g->lay.normpart);
+    double *rho = wsp<double>(g, g->lay.rho);
+    double *vpred = wsp<double>(g, g->lay.vpred);
+    double *dpart = wsp<double>(g, g->lay.dpart);
+    const double h3 = g->geo.h[0] * g->geo.h[1] * g->geo.h[2];
+    const int S = g->stot;
+    const int ntiles = g->ntile_y * g->nzc;
+    const int ndb = density_blocks(g->geo.N);
+
+    // v(t0) from n(psi(t0)); d(t0); norms(t0)
+    {
+        DArgs a;
+        a.geo = g->geo;
+        a.nsrc = S;
+        a.psi = psi;
+        a.wocc = g->d_wocc;
+        a.rho = rho;
+        a.vion = d_vion;
+        a.vout = g->d_v;
+        a.xc = g->xc;
+        a.dpart = d_dipole ? dpart : nullptr;
+        KS_HIP(launch_density(a, g->stream));
+        if (d_dipole)
+            KS_HIP(launch_dipole_finalize(dpart, ndb, h3, d_dipole,
+                                          g->stream));
+        if (d_norms) {
+            KS_HIP(launch_norm_partial(g->geo, psi, S, g->norm_chunks,
+                                       normpart, g->stream));
+            KS_HIP(launch_norm_finalize(normpart, S, g->norm_chunks, h3,
+                                        d_norms, g->stream));
+        }
+        g->vloc_set = true;
+    }
+    const bool want_n_end = g->xc || d_dipole;
+    for (int step = 0; step < nsteps; ++step) {
+        const double t = t0 + step * dt;
+        double At[3], An[3];
+        laser_A(g, t, At);
+        laser_A(g, t + dt, An);
+        // exponential 1: H_t, tau = dt/2; predictor density when xc is on
+        rc = taylor_exponential(g, psi, half, g->d_v, At, 0.5 * dt,
+                                g->xc ? kFinalPred : kFinal,
+                                g->xc ? npart : nullptr, nullptr);
+        if (rc)
+            return rc;
+        const double *vnext = d_vion;
+        if (g->xc) {
+            DArgs a;
+            a.geo = g->geo;
+            a.nsrc = S;
+            a.npart = npart;
+            a.rho = rho;
+            a.vion = d_vion;
+            a.vout = vpred;
+            a.xc = 1;
+            KS_HIP(launch_density(a, g->stream));
+            vnext = vpred;
+        }
+        // exponential 2: H_{t+dt}, tau = dt/2, from psi_half into psi
+        rc = taylor_exponential(g, half, psi, vnext, An, 0.5 * dt, kFinal,
+                                want_n_end ? npart : nullptr,
+                                d_norms ? normpart : nullptr);
+        if (rc)
+            return rc;
+        if (want_n_end) {
+            DArgs a;
+            a.geo = g->geo;
+            a.nsrc = S;
+            a.npart = npart;
+            a.rho = rho;
+            a.vion = d_vion;
+            a.vout = g->d_v;
+            a.xc = g->xc;
+            a.dpart = d_dipole ? dpart : nullptr;
+            KS_HIP(launch_density(a, g->stream));
+            if (d_dipole)
+                KS_HIP(launch_dipole_finalize(dpart, ndb, h3,
+                                              d_dipole + 3 * (step + 1),
+                                              g->stream));
+        }
+        if (d_norms)
+            KS_HIP(launch_norm_finalize(normpart, S, ntiles, h3,
+                                        d_norms + (size_t)(step + 1) * S,
+                                        g->stream));
+    }
+    return KS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,335 @@
+"""Python binding of libks (the C ABI declared in include/ks.h).
+
+Argument marshalling only: every step of the path runs in libks's HIP kernels.
+PyTorch supplies device memory (tensors) and the stream.  The functions carry
+the C names (ks_grid_create, ks_apply_h, ...); ``Grid`` bundles them with a
+workspace tensor.  Importing this module does not load the library; the
+first call does, and raises if libks.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libks.so")
+
+KS_FP64, KS_MIXED = 0, 1
+_STATUS = {0: "KS_OK", -1: "KS_E_ARG", -2: "KS_E_OOM", -3: "KS_E_HIP",
+           -4: "KS_E_UNSUPPORTED", -5: "KS_E_STATE", -6: "KS_E_NONFINITE"}
+
+
+class KSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ks_grid_desc(C.Structure):
+    _fields_ = [
+        ("n", C.c_int * 3),
+        ("h", C.c_double * 3),
+        ("periodic", C.c_int * 3),
+        ("fd_half_width", C.c_int),
+        ("nk", C.c_int),
+        ("kpts", C.POINTER(C.c_double)),
+        ("kw", C.POINTER(C.c_double)),
+        ("nstates", C.c_int),
+        ("occ", C.POINTER(C.c_double)),
+        ("natoms", C.c_int),
+        ("pos", C.POINTER(C.c_double)),
+        ("lmax", C.POINTER(C.c_int)),
+        ("rc", C.POINTER(C.c_double)),
+        ("sigma", C.POINTER(C.c_double)),
+        ("E", C.POINTER(C.c_double)),
+        ("xc", C.c_int),
+        ("laser", C.c_double * 6),
+        ("precision", C.c_int),
+        ("stream", C.c_void_p),
+    ]
+
+
+EXPORTS = {
+    # name: (restype, argtypes)
+    "ks_grid_create": (C.c_int, [C.POINTER(ks_grid_desc),
+                                 C.POINTER(C.c_void_p)]),
+    "ks_grid_destroy": (C.c_int, [C.c_void_p]),
+    "ks_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ks_workspace_bytes": (C.c_size_t, [C.c_void_p]),
+    "ks_set_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "ks_update_vlocal": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ks_apply_h": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                             C.c_int, C.c_int, C.c_double]),
+    "ks_propagate_etrs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_int, C.c_double, C.c_double,
+                                    C.c_void_p, C.c_void_p]),
+    "ks_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ks_dipole": (C.c_int, [C.c_void_p, C.c_void_p,
+                            C.POINTER(C.c_double)]),
+    "ks_kick": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double]),
+    "ks_norms": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ks_gram": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ks_energy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                            C.POINTER(C.c_double)]),
+    "ks_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libks (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise KSError(rc, lib().ks_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, dtype, numel=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return t
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# C-named functions
+# ---------------------------------------------------------------------------
+def ks_grid_create(spec, precision=KS_FP64, stream=None):
+    """Returns (handle, keep-alive host arrays)."""
+    f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    keep = dict(kpts=f64(spec.kpts).reshape(-1), kw=f64(spec.kw),
+                occ=f64(spec.occ), pos=f64(spec.pos).reshape(-1),
+                lmax=np.ascontiguousarray(spec.lmax, dtype=np.int32),
+                rc=f64(spec.rc), sigma=f64(spec.sigma),
+                E=f64(spec.E).reshape(-1))
+    P = lambda a, t=C.c_double: a.ctypes.data_as(C.POINTER(t))
+    d = ks_grid_desc()
+    d.n[:] = list(spec.n)
+    d.h[:] = list(spec.h)
+    d.periodic[:] = list(spec.periodic)
+    d.fd_half_width = 4
+    d.nk = len(keep["kw"])
+    d.kpts = P(keep["kpts"])
+    d.kw = P(keep["kw"])
+    d.nstates = int(spec.nstates)
+    d.occ = P(keep["occ"])
+    d.natoms = int(len(keep["rc"]))
+    d.pos = P(keep["pos"])
+    d.lmax = P(keep["lmax"], C.c_int)
+    d.rc = P(keep["rc"])
+    d.sigma = P(keep["sigma"])
+    d.E = P(keep["E"])
+    d.xc = int(spec.xc)
+    d.laser[:] = list(spec.laser)
+    d.precision = int(precision)
+    d.stream = _stream_handle(stream)
+    h = C.c_void_p()
+    _check(lib().ks_grid_create(C.byref(d), C.byref(h)))
+    return h, keep
+
+
+def ks_grid_destroy(h):
+    return _check(lib().ks_grid_destroy(h))
+
+
+def ks_set_stream(h, stream):
+    return _check(lib().ks_set_stream(h, _stream_handle(stream)))
+
+
+def ks_workspace_bytes(h):
+    return int(lib().ks_workspace_bytes(h))
+
+
+def ks_set_workspace(h, ws):
+    return _check(lib().ks_set_workspace(h, _ptr(ws), ws.numel()))
+
+
+def ks_update_vlocal(h, vion, rho=None):
+    return _check(lib().ks_update_vlocal(h, _ptr(vion), _ptr(rho)))
+
+
+def ks_apply_h(h, psi, hpsi, k, s0, ns, t):
+    return _check(lib().ks_apply_h(h, _ptr(psi), _ptr(hpsi), k, s0, ns, t))
+
+
+def ks_propagate_etrs(h, psi, vion, nsteps, dt, t0, dipole, norms):
+    return _check(lib().ks_propagate_etrs(h, _ptr(psi), _ptr(vion), nsteps,
+                                          dt, t0, _ptr(dipole), _ptr(norms)))
+
+
+def ks_density(h, psi, rho):
+    return _check(lib().ks_density(h, _ptr(psi), _ptr(rho)))
+
+
+def ks_dipole(h, rho):
+    out = (C.c_double * 3)()
+    _check(lib().ks_dipole(h, _ptr(rho), out))
+    return np.array(out[:])
+
+
+def ks_kick(h, psi, kappa):
+    return _check(lib().ks_kick(h, _ptr(psi), kappa))
+
+
+def ks_norms(h, psi, norms):
+    return _check(lib().ks_norms(h, _ptr(psi), _ptr(norms)))
+
+
+def ks_gram(h, psi, gram):
+    return _check(lib().ks_gram(h, _ptr(psi), _ptr(gram)))
+
+
+def ks_energy(h, psi, vion, t):
+    out = C.c_double()
+    _check(lib().ks_energy(h, _ptr(psi), _ptr(vion), t, C.byref(out)))
+    return out.value
+
+
+# ---------------------------------------------------------------------------
+# convenience object
+# ---------------------------------------------------------------------------
+class Grid:
+    """A libks grid object plus its workspace tensor."""
+
+    def __init__(self, spec, precision=KS_FP64, stream=None, device=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device or "cuda")
+        self.spec = spec
+        self.N = spec.n[0] * spec.n[1] * spec.n[2]
+        self.nk = len(spec.kw)
+        self.ns = int(spec.nstates)
+        self.precision = precision
+        self.h, self._keep = ks_grid_create(spec, precision, stream)
+        nbytes = ks_workspace_bytes(self.h)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8,
+                              device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        self._ws_view = self.ws[off:off + nbytes]
+        ks_set_workspace(self.h, self._ws_view)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            ks_grid_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def workspace_bytes(self):
+        return ks_workspace_bytes(self.h)
+
+    def set_stream(self, stream):
+        ks_set_stream(self.h, stream)
+
+    def _psi(self, psi, nstates=None):
+        nst = self.nk * self.ns if nstates is None else nstates
+        return _dev(psi, self.torch.complex128, nst * self.N, "psi")
+
+    def update_vlocal(self, vion, rho=None):
+        _dev(vion, self.torch.float64, self.N, "vion")
+        if rho is not None:
+            _dev(rho, self.torch.float64, self.N, "rho")
+        ks_update_vlocal(self.h, vion, rho)
+
+    def apply_h(self, psi, out=None, k=0, s0=0, t=0.0):
+        _dev(psi, self.torch.complex128, None, "psi")
+        ns = psi.numel() // self.N
+        if ns * self.N != psi.numel():
+            raise ValueError("psi is not a whole number of states")
+        if out is None:
+            out = self.torch.empty_like(psi)
+        _dev(out, self.torch.complex128, psi.numel(), "hpsi")
+        ks_apply_h(self.h, psi, out, int(k), int(s0), ns, float(t))
+        return out
+
+    def propagate_etrs(self, psi, vion, nsteps, dt, t0=0.0, dipole=True,
+                       norms=True):
+        self._psi(psi)
+        _dev(vion, self.torch.float64, self.N, "vion")
+        d = (self.torch.zeros((nsteps + 1, 3), dtype=self.torch.float64,
+                              device=self.device) if dipole else None)
+        n = (self.torch.zeros((nsteps + 1, self.nk * self.ns),
+                              dtype=self.torch.float64, device=self.device)
+             if norms else None)
+        ks_propagate_etrs(self.h, psi, vion, int(nsteps), float(dt),
+                          float(t0), d, n)
+        return d, n
+
+    def density(self, psi, rho=None):
+        self._psi(psi)
+        if rho is None:
+            rho = self.torch.empty(self.N, dtype=self.torch.float64,
+                                   device=self.device)
+        ks_density(self.h, psi, rho)
+        return rho
+
+    def dipole(self, rho):
+        _dev(rho, self.torch.float64, self.N, "rho")
+        return ks_dipole(self.h, rho)
+
+    def kick(self, psi, kappa):
+        self._psi(psi)
+        ks_kick(self.h, psi, float(kappa))
+        return psi
+
+    def norms(self, psi):
+        self._psi(psi)
+        out = self.torch.empty(self.nk * self.ns, dtype=self.torch.float64,
+                               device=self.device)
+        ks_norms(self.h, psi, out)
+        return out
+
+    def gram(self, psi):
+        self._psi(psi)
+        out = self.torch.empty((self.nk, self.ns, self.ns),
+                               dtype=self.torch.complex128,
+                               device=self.device)
+        ks_gram(self.h, psi, out)
+        return out
+
+    def energy(self, psi, vion, t=0.0):
+        self._psi(psi)
+        _dev(vion, self.torch.float64, self.N, "vion")
+        return ks_energy(self.h, psi, vion, float(t))

@@ -1,0 +1,71 @@
+"""CPU-side checks of the boundary: the library loads and exports every entry
+point the public header declares; the binding knows them all; the oracle's
+shared object builds and loads.  No compute call (no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ks.h")
+
+
+def declared_entry_points():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(
+        r"^(?:int|size_t|const char \*)\s*(ks_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_entry_points()
+    for must in ["ks_grid_create", "ks_apply_h", "ks_propagate_etrs",
+                 "ks_density", "ks_update_vlocal", "ks_dipole"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1912_07921_amd import ks
+    if not os.path.exists(ks.LIB_PATH):
+        pytest.fail("libks.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(ks.LIB_PATH)
+    for name in declared_entry_points():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_1912_07921_amd import ks
+    for name in declared_entry_points():
+        assert name in ks.EXPORTS, name
+        assert callable(getattr(ks, name, None)) or name == "ks_last_error"
+
+
+def test_library_refuses_nothing_at_load_and_reports_errors_without_gpu():
+    from paper_1912_07921_amd import ks
+    L = ks.lib()
+    assert L.ks_last_error() is not None
+    # a NULL grid is an argument error, reported without touching the GPU
+    assert L.ks_set_stream(None, None) == -1
+    assert b"NULL" in L.ks_last_error()
+    assert L.ks_workspace_bytes(None) == 0
+    assert L.ks_grid_destroy(None) == 0
+
+
+def test_oracle_builds_and_loads(oracle_mod):
+    lib = oracle_mod._load()
+    for name in ["orc_create", "orc_apply_h", "orc_propagate_etrs",
+                 "orc_density", "orc_dipole", "orc_vlocal", "orc_kick",
+                 "orc_gram", "orc_energy"]:
+        assert hasattr(lib, name)
+
+
+def test_product_does_not_import_the_oracle():
+    """The product package neither imports nor loads anything under oracle/."""
+    pkg = os.path.join(ROOT, "paper_1912_07921_amd")
+    pat = re.compile(r"(^\s*(from|import)\s+oracle)|liboracle|ks_oracle",
+                     re.M)
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not pat.search(text), f

@@ -1,0 +1,271 @@
+"""GPU (libks through its C ABI) against the FP64 CPU oracle, element by
+element on the same seeded inputs.
+
+Tolerances: H.psi in FP64 to 1e-12 relative (max over states of the 2-norm
+of the difference over the 2-norm of the oracle's H.psi); FP64 propagation to
+1e-10 relative on states, dipoles and norms; the mixed form to 1e-5 on H.psi
+and to 1e-6 (absolute, atomic units) on dipole traces.
+"""
+import numpy as np
+import pytest
+
+from paper_1912_07921_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def dev(torch, a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda")
+
+
+def rel_err(got, want):
+    """max over states of ||got - want|| / ||want||"""
+    want = np.atleast_2d(want)
+    got = np.asarray(got).reshape(want.shape)
+    d = np.linalg.norm(got - want, axis=-1)
+    w = np.linalg.norm(want, axis=-1)
+    return float(np.max(d / np.maximum(w, 1e-300)))
+
+
+def grid(spec, prec=0):
+    from paper_1912_07921_amd import ks
+    return ks.Grid(spec, precision=prec)
+
+
+def apply_parity(torch, oracle_mod, spec, v, psi, A_t=0.0, prec=0, tol=1e-12):
+    o = oracle_mod.Oracle(spec)
+    g = grid(spec, prec)
+    g.update_vlocal(dev(torch, v))
+    A = o.laser_A(A_t)
+    worst = 0.0
+    for k in range(spec.nk):
+        want = o.apply_h(v, psi[k], k=k, A=A)
+        got = g.apply_h(dev(torch, psi[k]), k=k, t=A_t).cpu().numpy()
+        worst = max(worst, rel_err(got.reshape(want.shape), want))
+    assert worst < tol, worst
+    return worst
+
+
+# ---------------------------------------------------------------------------
+# H.psi
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("periodic", [(0, 0, 0), (1, 1, 1), (0, 1, 1)])
+def test_apply_h_tiny_all_terms(torch_cuda, oracle_mod, periodic):
+    laser = (0.4, 0.7, 5.0, 0.3, -0.5, 0.8)
+    spec, v, psi = W.tiny(periodic=periodic, nk=2, nstates=3, natoms=2,
+                          lmax=2, laser=laser)
+    apply_parity(torch_cuda, oracle_mod, spec, v, psi, A_t=1.3)
+
+
+def test_apply_h_ragged_tiles_and_chunks(torch_cuda, oracle_mod):
+    """Grid sizes that leave ragged y-tiles, several z-chunks and x rows that
+    are not a multiple of the wavefront."""
+    spec, v, psi = W.tiny(n=(37, 29, 23), h=(0.21, 0.23, 0.25), nstates=5,
+                          natoms=3, lmax=2, rc=1.4, sigma=0.45)
+    apply_parity(torch_cuda, oracle_mod, spec, v, psi)
+
+
+def test_apply_h_ragged_periodic_bloch(torch_cuda, oracle_mod):
+    spec, v, psi = W.tiny(n=(19, 13, 21), h=(0.3, 0.35, 0.28),
+                          periodic=(1, 1, 1), nk=3, nstates=2, natoms=3,
+                          lmax=1, rc=1.1, sigma=0.4,
+                          laser=(0.2, 0.9, 4.0, 0.0, 0.0, 1.0))
+    apply_parity(torch_cuda, oracle_mod, spec, v, psi, A_t=0.8)
+
+
+@pytest.mark.parametrize("n", [(1, 1, 1), (1, 2, 3), (3, 1, 2), (2, 5, 1)])
+@pytest.mark.parametrize("periodic", [(0, 0, 0), (1, 1, 1)])
+def test_apply_h_degenerate_grids(torch_cuda, oracle_mod, n, periodic):
+    """Axes shorter than the stencil: zero padding, or Bloch wraps that go
+    round the cell several times."""
+    spec, v, psi = W.tiny(n=n, h=(0.3, 0.4, 0.5), periodic=periodic, nk=1,
+                          nstates=2, natoms=0)
+    if any(periodic):
+        spec.kpts = np.array([[0.7, -1.1, 0.4]])
+    apply_parity(torch_cuda, oracle_mod, spec, v, psi)
+
+
+def test_apply_h_c1(torch_cuda, oracle_mod):
+    w = W.c1()
+    apply_parity(torch_cuda, oracle_mod, w.spec, w.vion, w.psi0)
+
+
+def test_apply_h_c2_full(torch_cuda, oracle_mod):
+    w = W.c2(nsteps=1)
+    apply_parity(torch_cuda, oracle_mod, w.spec, w.vion, w.psi0)
+
+
+def test_apply_h_c3_full_with_laser(torch_cuda, oracle_mod):
+    w = W.c3(nsteps=1)
+    # at the envelope maximum, so the gauge term is large
+    apply_parity(torch_cuda, oracle_mod, w.spec, w.vion, w.psi0,
+                 A_t=0.5 * w.spec.laser[2])
+
+
+def test_apply_h_mixed_c2(torch_cuda, oracle_mod):
+    w = W.c2(nsteps=1)
+    err = apply_parity(torch_cuda, oracle_mod, w.spec, w.vion, w.psi0,
+                       prec=1, tol=1e-5)
+    assert err > 1e-10   # the FP32 path really is FP32
+
+
+# ---------------------------------------------------------------------------
+# density, LDA potential, dipole, kick, norms, Gram, energy
+# ---------------------------------------------------------------------------
+def test_observables_match_oracle(torch_cuda, oracle_mod):
+    torch = torch_cuda
+    spec, v, psi = W.tiny(n=(21, 18, 17), nk=1, nstates=4, natoms=2, lmax=2,
+                          rc=1.3, sigma=0.4)
+    o = oracle_mod.Oracle(spec)
+    g = grid(spec)
+    dpsi = dev(torch, psi)
+    rho = g.density(dpsi).cpu().numpy()
+    want = o.density(psi)
+    assert np.abs(rho - want).max() < 1e-13 * np.abs(want).max()
+    d = g.dipole(dev(torch, want))
+    assert np.abs(d - o.dipole(want)).max() < 1e-12 * np.abs(d).max()
+    g.update_vlocal(dev(torch, v), dev(torch, want))
+    # the potential is observable through H.psi
+    hp = g.apply_h(dev(torch, psi[0])).cpu().numpy().reshape(psi[0].shape)
+    assert rel_err(hp, o.apply_h(o.vlocal(v, want), psi[0])) < 1e-12
+    nr = g.norms(dpsi).cpu().numpy()
+    assert np.abs(nr - o.norms(psi)).max() < 1e-12 * nr.max()
+    G = g.gram(dpsi).cpu().numpy()
+    Go = o.gram(psi)
+    assert np.abs(G - Go).max() < 1e-12 * np.abs(Go).max()
+    e = g.energy(dpsi, dev(torch, v))
+    eo = o.energy(psi, v)
+    assert abs(e - eo) < 1e-11 * abs(eo)
+    g.kick(dpsi, 0.37)
+    assert np.abs(dpsi.cpu().numpy() - o.kick(psi, 0.37)).max() < 1e-14 * \
+        np.abs(psi).max()
+
+
+def test_gram_larger_than_one_tile(torch_cuda, oracle_mod):
+    torch = torch_cuda
+    w = W.c3(nsteps=1, nstates=40, n=16, h=0.45)
+    o = oracle_mod.Oracle(w.spec)
+    G = grid(w.spec).gram(dev(torch, w.psi0)).cpu().numpy()
+    assert np.abs(G - o.gram(w.psi0)).max() < 1e-12
+    assert np.abs(G - np.eye(40)[None]).max() < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# ETRS propagation
+# ---------------------------------------------------------------------------
+def propagate_parity(torch, oracle_mod, spec, v, psi, nsteps, dt, t0=0.0,
+                     prec=0, kick=0.0, tol=1e-10, dip_tol=None):
+    o = oracle_mod.Oracle(spec)
+    if kick:
+        psi = o.kick(psi, kick)
+    want, wd, wn = o.propagate_etrs(psi, v, nsteps, dt, t0)
+    g = grid(spec, prec)
+    dpsi = dev(torch, psi)
+    periodic = any(spec.periodic)
+    d, n = g.propagate_etrs(dpsi, dev(torch, v), nsteps, dt, t0,
+                            dipole=not periodic, norms=True)
+    got = dpsi.cpu().numpy()
+    e_psi = rel_err(got.reshape(-1, o.N), want.reshape(-1, o.N))
+    e_norm = np.abs(n.cpu().numpy() - wn).max()
+    res = dict(psi=e_psi, norm=e_norm)
+    if not periodic:
+        dd = d.cpu().numpy()
+        res["dip"] = np.abs(dd - wd).max()
+        res["dip_scale"] = np.abs(wd).max()
+    if prec == 0:
+        assert e_psi < tol, res
+        assert e_norm < tol, res
+        if not periodic:
+            assert res["dip"] < tol * max(res["dip_scale"], 1e-3), res
+    else:
+        if not periodic:
+            assert res["dip"] < dip_tol, res
+    return res
+
+
+def test_propagate_c1_full_length(torch_cuda, oracle_mod):
+    w = W.c1()
+    propagate_parity(torch_cuda, oracle_mod, w.spec, w.vion, w.psi0,
+                     w.nsteps, w.dt)
+
+
+def test_propagate_tiny_every_term(torch_cuda, oracle_mod):
+    spec, v, psi = W.tiny(n=(17, 15, 14), nk=1, nstates=3, natoms=2, lmax=2,
+                          rc=1.2, sigma=0.4, xc=1,
+                          laser=(0.3, 0.8, 3.0, 0.2, 0.1, 0.9))
+    h3 = np.prod(spec.h)
+    psi = psi / np.sqrt(np.sum(np.abs(psi) ** 2, axis=2, keepdims=True) * h3)
+    propagate_parity(torch_cuda, oracle_mod, spec, 0.3 * v, psi, 6, 0.01,
+                     t0=0.2, kick=0.05)
+
+
+def test_propagate_periodic_kpoints(torch_cuda, oracle_mod):
+    spec, v, psi = W.tiny(n=(16, 14, 15), h=(0.35, 0.35, 0.35),
+                          periodic=(1, 1, 1), nk=2, nstates=2, natoms=2,
+                          lmax=1, rc=1.1, sigma=0.4, xc=1,
+                          laser=(0.3, 0.8, 3.0, 0.0, 0.0, 1.0))
+    h3 = np.prod(spec.h)
+    psi = psi / np.sqrt(np.sum(np.abs(psi) ** 2, axis=2, keepdims=True) * h3)
+    propagate_parity(torch_cuda, oracle_mod, spec, 0.3 * v, psi, 4, 0.01)
+
+
+def test_propagate_c2_full_size_few_steps(torch_cuda, oracle_mod):
+    w = W.c2(nsteps=4)
+    propagate_parity(torch_cuda, oracle_mod, w.spec, w.vion, w.psi0,
+                     w.nsteps, w.dt, kick=w.kick)
+
+
+def test_propagate_mixed_c2_dipole(torch_cuda, oracle_mod):
+    w = W.c2(nsteps=8)
+    res = propagate_parity(torch_cuda, oracle_mod, w.spec, w.vion, w.psi0,
+                           w.nsteps, w.dt, kick=w.kick, prec=1,
+                           dip_tol=1e-6)
+    assert res["psi"] < 1e-4, res
+
+
+def test_propagate_zero_steps_reports_initial_observables(torch_cuda,
+                                                          oracle_mod):
+    w = W.c1()
+    propagate_parity(torch_cuda, oracle_mod, w.spec, w.vion, w.psi0, 0, w.dt)
+
+
+# ---------------------------------------------------------------------------
+# error paths (host-side checks; every kernel exits normally)
+# ---------------------------------------------------------------------------
+def test_error_paths(torch_cuda):
+    torch = torch_cuda
+    from paper_1912_07921_amd import ks
+    spec, v, psi = W.tiny(nstates=2, natoms=1)
+    g = grid(spec)
+    dpsi = dev(torch, psi[0])
+    with pytest.raises(ks.KSError) as e:
+        g.apply_h(dpsi)            # no potential yet
+    assert e.value.code == -5
+    g.update_vlocal(dev(torch, v))
+    with pytest.raises(ks.KSError) as e:
+        g.apply_h(dpsi, k=3)
+    assert e.value.code == -1
+    with pytest.raises(ks.KSError) as e:
+        ks.ks_apply_h(g.h, dpsi, dpsi, 0, 0, 2, 0.0)
+    assert e.value.code == -1
+    bad = W.tiny(periodic=(1, 1, 1), rc=5.0)[0]
+    with pytest.raises(ks.KSError) as e:
+        grid(bad)
+    assert e.value.code == -4
+    with pytest.raises(ValueError):
+        g.dipole(dev(torch, np.zeros(spec.npoints + 1)))
+    per, pv, _ = W.tiny(periodic=(1, 1, 1), natoms=0)
+    gp = grid(per)
+    with pytest.raises(ks.KSError) as e:
+        gp.dipole(dev(torch, np.zeros(per.npoints)))
+    assert e.value.code == -4
