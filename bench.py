@@ -1,0 +1,180 @@
+#!/usr/bin/env python
+"""Benchmark of the real-time TDDFT hot path on one MI355X.
+
+One step = one ETRS step of every state of the workload (8 H.psi passes with
+the projector gathers, the Taylor combines, the predictor density and LDA
+update, the final density, potential, dipole and norms), inputs resident in
+HBM.  Throughput is H.psi grid-point-states per second:
+8 * N * (nk * nstates) * steps / time.
+
+Prints one JSON line with the FP64 rate, the roofline of the dominant kernel
+(the H.psi stencil, timed live with HIP events on its stream), the CPU
+oracle timed on the host on a bounded sample, and the FP32-mixed form on the
+same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per grid point and state for one ETRS step (8 H.psi
+# passes: 3 x (read t_{j-1}, write t_j) + (read t3, psi, t1, t2; write the
+# sum), twice): FP64 16-byte terms / mixed 8-byte terms with 16-byte psi
+STEP_BYTES = {0: 352.0, 1: 224.0}
+METRIC = ("H·ψ grid-point·states/s + HBM GB/s frac; serving p50/p99 step, "
+          "FP32-mix vs FP64")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from paper_1912_07921_amd import workloads as W
+    return {"c1": W.c1, "c2": W.c2, "c3": W.c3, "c5": W.c5}[name]()
+
+
+def run_gpu(w, precision, steps, warmup, torch):
+    """(seconds for `steps` steps, dipole trace, profile, grid)."""
+    from paper_1912_07921_amd import ks
+    g = ks.Grid(w.spec, precision=precision)
+    psi = torch.from_numpy(w.psi0.copy()).cuda()
+    vion = torch.from_numpy(w.vion).cuda()
+    if w.kick:
+        g.kick(psi, w.kick)
+    periodic = any(w.spec.periodic)
+    if warmup:
+        g.propagate_etrs(psi, vion, warmup, w.dt, dipole=not periodic,
+                         norms=True)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    g.profile_begin(64 * steps + 64)
+    e0.record(st)
+    d, n = g.propagate_etrs(psi, vion, steps, w.dt, t0=warmup * w.dt,
+                            dipole=not periodic, norms=True)
+    e1.record(st)
+    prof = g.profile_end()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    dip = d.cpu().numpy() if d is not None else None
+    return sec, dip, n.cpu().numpy(), prof, g
+
+
+def cpu_baseline(w, sample_steps):
+    from oracle import oracle
+    o = oracle.Oracle(w.spec)
+    psi = o.kick(w.psi0, w.kick) if w.kick else w.psi0
+    t = time.perf_counter()
+    o.propagate_etrs(psi, w.vion, sample_steps, w.dt)
+    sec = time.perf_counter() - t
+    N, S = w.spec.npoints, w.spec.nk * w.spec.nstates
+    return dict(value=8.0 * N * S * sample_steps / sec,
+                unit="grid-point·states/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"{sample_steps} ETRS steps of the same workload "
+                       f"({w.name}, all {S} states), {sec:.2f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3",
+                                                         "c5"])
+    ap.add_argument("--cpu-steps", type=int, default=3,
+                    help="oracle ETRS steps timed for the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the "
+              "path would shard over states with one density all-reduce per "
+              "half step, which this build does not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log(f"workload {args.workload}: generating inputs")
+    w = make_workload(args.workload)
+    N, S = w.spec.npoints, w.spec.nk * w.spec.nstates
+    units = 8.0 * N * S
+
+    log(f"FP64: {args.warmup} warmup + {args.steps} timed steps")
+    sec, dip64, nrm64, prof, _ = run_gpu(w, 0, args.steps, args.warmup, torch)
+    value = units * args.steps / sec
+    hp_ms, hp_n = prof["hpsi"]
+    avg_ms = hp_ms / max(hp_n, 1)
+    bytes_per_launch = STEP_BYTES[0] / 8.0 * N * S
+    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1),
+                    peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None)
+    kernel_times = {k: dict(total_ms=round(v[0], 3), launches=v[1],
+                            avg_us=round(1e3 * v[0] / max(v[1], 1), 2))
+                    for k, v in prof.items()}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-point·states/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "grid": list(w.spec.n), "h": w.spec.h[0],
+            "periodic": any(w.spec.periodic),
+            "kpoints": w.spec.nk, "states": S, "atoms": w.spec.natoms,
+            "projectors_per_atom": int((max(w.spec.lmax) + 1) ** 2)
+            if w.spec.natoms else 0,
+            "xc": "LDA exchange" if w.spec.xc else "none",
+            "dt": w.dt, "kick": w.kick,
+        },
+        "roofline": roofline,
+        "kernels": kernel_times,
+    }
+
+    if not args.no_mixed:
+        log(f"mixed: {args.warmup} warmup + {args.steps} timed steps")
+        msec, dipm, nrmm, mprof, _ = run_gpu(w, 1, args.steps, args.warmup,
+                                             torch)
+        mh_ms, mh_n = mprof["hpsi"]
+        mavg = mh_ms / max(mh_n, 1)
+        mach = STEP_BYTES[1] / 8.0 * N * S / (mavg / 1e3) / 1e9
+        mixed = dict(value=units * args.steps / msec,
+                     ms_per_step=1e3 * msec / args.steps,
+                     speedup_vs_fp64=sec / msec,
+                     roofline_achieved_GBs=round(mach, 1),
+                     roofline_frac=round(mach / HBM_PEAK_GBS, 4),
+                     norm_drift_max=float(abs(nrmm - nrm64).max()))
+        if dip64 is not None:
+            mixed["dipole_err_vs_fp64"] = float(abs(dipm - dip64).max())
+        out["mixed"] = mixed
+
+    if not args.no_cpu:
+        log(f"CPU oracle: {args.cpu_steps} steps")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        out["cpu_baseline"]["cpu_model"] = platform.processor() or \
+            platform.machine()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

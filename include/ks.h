@@ -75,7 +75,7 @@ typedef enum {
 } ks_precision;
 
 typedef struct {
-    int n[3];            /* nx, ny, nz >= 1; nx <= 256 */
+    int n[3];            /* nx, ny, nz >= 1; nx <= 192 */
     double h[3];         /* grid spacing per axis (bohr), > 0 */
     int periodic[3];     /* 1: Bloch-periodic axis, 0: zero boundary */
     int fd_half_width;   /* must be 4 (25-point star); else KS_E_UNSUPPORTED */
@@ -168,6 +168,28 @@ int ks_gram(ks_grid *g, const void *d_psi, void *d_gram);
  * Synchronises the stream.  Needs a workspace. */
 int ks_energy(ks_grid *g, const void *d_psi, const double *d_vion, double t,
               double *out_host);
+
+/* Launch shape of the H.psi kernel: a workgroup owns tile_rows full x-rows
+ * of one state and marches through zchunk z-planes.  0 keeps the library's
+ * choice for that parameter.  KS_E_ARG / KS_E_UNSUPPORTED if the shape does
+ * not fit (nx * tile_rows <= 512, LDS); KS_E_OOM (and the workspace is
+ * dropped) if the current workspace is too small for it.  Results do not
+ * depend on the shape. */
+int ks_set_launch(ks_grid *g, int tile_rows, int zchunk);
+
+/* out[0] = tile_rows, out[1] = zchunk, out[2] = workgroups per H.psi launch
+ * over all states, out[3] = threads per workgroup. */
+int ks_get_launch(const ks_grid *g, int out[4]);
+
+/* Kernel timing with HIP events on the grid's stream.  After
+ * ks_profile_begin(g, capacity), every later launch of the H.psi kernel
+ * (class 0), of the projector gather (class 1) and of the density /
+ * reduction kernels (class 2) is bracketed by a pair of events, up to
+ * `capacity` pairs.  ks_profile_end() waits for the stream, stops recording
+ * and returns per class the summed kernel time (ms) and the number of
+ * launches timed, in out_ms[3] and out_count[3] (host arrays). */
+int ks_profile_begin(ks_grid *g, int capacity);
+int ks_profile_end(ks_grid *g, double out_ms[3], long out_count[3]);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *ks_last_error(void);

@@ -45,7 +45,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct ks_grid {
     Geo geo;
     int nk = 1, ns = 1, stot = 1;
-    std::vector<double> kpts, kw, occ, wocc, kL;
+    std::vector<double> kpts, kw, occ, wocc;
+    std::vector<double2> kph;   // [nk][3] exp(i k_a L_a)
     int xc = 0;
     double laser[6] = {0, 0, 0, 0, 0, 0};
     bool mixed = false;
@@ -55,7 +56,7 @@ struct ks_grid {
     // owned device memory
     std::vector<void *> owned;
     double *d_v = nullptr;       // current local potential
-    double *d_kL = nullptr;
+    double2 *d_kph = nullptr;
     double *d_wocc = nullptr;
     bool vloc_set = false;
 
@@ -72,12 +73,19 @@ struct ks_grid {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     struct {
-        size_t t1, t2, t3, half, npart, normpart, D, rho, vpred, dpart,
-            gpart, dotpart, xpart, total;
+        size_t t1, t2, t3, half, npart, normpart, D, Dpart, rho, vpred,
+            dpart, gpart, dotpart, xpart, total;
     } lay{};
     int ntiles_max = 64;
+    int nchunk = 1;
     int gram_ksplit = 16;
     int norm_chunks = 64;
+
+    // kernel timing
+    std::vector<hipEvent_t> ev;   // 2 per record
+    std::vector<int> ev_class;
+    int ev_used = 0;
+    bool profiling = false;
 };
 
 namespace {
@@ -142,7 +150,9 @@ int build_projectors(ks_grid *g, const ks_grid_desc *d)
     std::vector<int> nproj(na), npts(na);
     std::vector<long> ioff(na), poff(na);
     std::vector<int> sidx, sshift;
-    std::vector<double> ptab, Ej((size_t)na * kMaxProj, 0.0);
+    std::vector<double> ptab, EjN((size_t)na * kMaxProj, 0.0);
+    std::vector<double4> apos(na);
+    std::vector<double2> arad(na);
     const double h3 = G.h[0] * G.h[1] * G.h[2];
     for (int a = 0; a < na; ++a) {
         const int lmax = d->lmax[a];
@@ -158,10 +168,8 @@ int build_projectors(ks_grid *g, const ks_grid_desc *d)
                 return fail(KS_E_UNSUPPORTED,
                             "atom %d: rc must be below half the cell", a);
         nproj[a] = (lmax + 1) * (lmax + 1);
-        for (int j = 0; j < nproj[a]; ++j) {
-            int l = j == 0 ? 0 : (j < 4 ? 1 : 2);
-            Ej[(size_t)a * kMaxProj + j] = h3 * d->E[3 * a + l];
-        }
+        apos[a] = make_double4(X[0], X[1], X[2], rc * rc);
+        arad[a] = make_double2(1.0 / (2.0 * sg * sg), 1.0 / (rc * rc));
         // index ranges (unwrapped) of the bounding box of the sphere
         int lo[3], hi[3];
         for (int ax = 0; ax < 3; ++ax) {
@@ -223,40 +231,25 @@ int build_projectors(ks_grid *g, const ks_grid_desc *d)
             double f = s > 0.0 ? 1.0 / std::sqrt(s) : 0.0;
             for (int i = 0; i < np; ++i)
                 pa[(size_t)j * np + i] *= f;
+            const int l = j == 0 ? 0 : (j < 4 ? 1 : 2);
+            EjN[(size_t)a * kMaxProj + j] = f * h3 * d->E[3 * a + l];
         }
         sidx.insert(sidx.end(), gidx.begin(), gidx.end());
         sshift.insert(sshift.end(), code.begin(), code.end());
     }
     g->total_pts = (long)sidx.size();
+    g->nchunk = gather_chunks(*std::max_element(npts.begin(), npts.end()));
     g->h_npts = npts;
     g->h_nproj = nproj;
-    // scatter CSR over grid points
-    const long N = G.N;
-    std::vector<int> soff(N + 1, 0);
-    for (int a = 0; a < na; ++a)
-        for (int i = 0; i < npts[a]; ++i)
-            soff[sidx[ioff[a] + i] + 1]++;
-    for (long i = 0; i < N; ++i)
-        soff[i + 1] += soff[i];
-    std::vector<int2> sent(std::max(1, soff[N]));
-    std::vector<int> fillp(soff.begin(), soff.end() - 1);
-    for (int a = 0; a < na; ++a)
-        for (int i = 0; i < npts[a]; ++i) {
-            int gg = sidx[ioff[a] + i];
-            sent[fillp[gg]++] = make_int2(a, i);
-        }
-    std::vector<unsigned char> rowhit((size_t)G.nz * G.ny, 0);
-    for (long i = 0; i < N; ++i)
-        if (soff[i + 1] > soff[i])
-            rowhit[i / G.nx] = 1;
+    if (na > 4096)
+        return fail(KS_E_UNSUPPORTED, "more than 4096 atoms");
     std::vector<float> ptabf(ptab.begin(), ptab.end());
-
-    int *d_nproj, *d_npts, *d_sidx, *d_sshift, *d_soff;
+    int *d_nproj, *d_npts, *d_sidx, *d_sshift;
     long *d_ioff, *d_poff;
-    double *d_ptab, *d_Ej;
+    double *d_ptab, *d_EjN;
     float *d_ptabf;
-    int2 *d_sent;
-    unsigned char *d_rowhit;
+    double4 *d_apos;
+    double2 *d_arad;
     int rc;
     if ((rc = dev_upload(g, &d_nproj, nproj)) ||
         (rc = dev_upload(g, &d_npts, npts)) ||
@@ -266,10 +259,9 @@ int build_projectors(ks_grid *g, const ks_grid_desc *d)
         (rc = dev_upload(g, &d_sshift, sshift)) ||
         (rc = dev_upload(g, &d_ptab, ptab)) ||
         (rc = dev_upload(g, &d_ptabf, ptabf)) ||
-        (rc = dev_upload(g, &d_Ej, Ej)) ||
-        (rc = dev_upload(g, &d_soff, soff)) ||
-        (rc = dev_upload(g, &d_sent, sent)) ||
-        (rc = dev_upload(g, &d_rowhit, rowhit)))
+        (rc = dev_upload(g, &d_EjN, EjN)) ||
+        (rc = dev_upload(g, &d_apos, apos)) ||
+        (rc = dev_upload(g, &d_arad, arad)))
         return rc;
     g->pj.nproj = d_nproj;
     g->pj.npts = d_npts;
@@ -279,27 +271,49 @@ int build_projectors(ks_grid *g, const ks_grid_desc *d)
     g->pj.sshift = d_sshift;
     g->pj.ptab = d_ptab;
     g->pj.ptabf = d_ptabf;
-    g->pj.Ej = d_Ej;
-    g->pj.soff = d_soff;
-    g->pj.sent = d_sent;
-    g->pj.rowhit = d_rowhit;
+    g->pj.EjN = d_EjN;
+    g->pj.apos = d_apos;
+    g->pj.arad = d_arad;
     return KS_OK;
 }
 
-void choose_tiles(ks_grid *g)
+// LDS bytes of one H.psi workgroup for tile height TY.
+size_t lds_for(const ks_grid *g, int TY)
+{
+    return hpsi_lds_bytes(g->geo.nx, TY, g->natoms, g->mixed);
+}
+
+// Launch shape: rows per tile TY (a workgroup has about 512 threads) and
+// planes per z-chunk (the full z extent unless that leaves fewer than ~4
+// workgroups per CU).  Either may be forced (> 0) by the caller.
+int set_tiles(ks_grid *g, int TY, int zchunk)
 {
     const Geo &G = g->geo;
-    // nx <= 256, so TY >= 2 and a workgroup has at most 512 threads
-    int TY = std::max(1, std::min(G.ny, 512 / G.nx));
+    if (TY <= 0) {
+        TY = std::max(1, std::min(G.ny, 512 / G.nx));
+        while (TY > 1 && lds_for(g, TY) > kLdsBudget)
+            --TY;
+    }
+    if (TY > G.ny || G.nx * TY > 512)
+        return fail(KS_E_ARG, "tile height %d invalid for nx=%d ny=%d", TY,
+                    G.nx, G.ny);
+    if (lds_for(g, TY) > kLdsBudget)
+        return fail(KS_E_UNSUPPORTED, "tile needs %zu bytes of LDS",
+                    lds_for(g, TY));
     g->TY = TY;
     g->ntile_y = (G.ny + TY - 1) / TY;
-    // enough workgroups to fill 256 CUs several times over
-    long per_state = g->ntile_y;
-    int nzc = (int)std::max<long>(1, 2048 / std::max<long>(1, per_state *
-                                                                 g->stot));
-    nzc = std::min(nzc, std::max(1, G.nz / 8));
-    g->zchunk = (G.nz + nzc - 1) / nzc;
+    if (zchunk <= 0) {
+        const long per_state = g->ntile_y;
+        int nzc = (int)std::max<long>(1, 1024 / std::max<long>(1, per_state *
+                                                                   g->stot));
+        nzc = std::min(nzc, std::max(1, G.nz / 16));
+        zchunk = (G.nz + nzc - 1) / nzc;
+    }
+    g->zchunk = std::min(zchunk, G.nz);
     g->nzc = (G.nz + g->zchunk - 1) / g->zchunk;
+    if ((long)g->ntile_y * g->nzc * g->stot >= (1L << 31))
+        return fail(KS_E_UNSUPPORTED, "too many workgroups");
+    return KS_OK;
 }
 
 void layout(ks_grid *g)
@@ -321,6 +335,8 @@ void layout(ks_grid *g)
     g->lay.npart = take(S * N * 8);
     g->lay.normpart = take(S * g->ntiles_max * 8);
     g->lay.D = take(S * std::max(1, g->natoms) * kMaxProj * 16);
+    g->lay.Dpart = take(S * std::max(1, g->natoms) * g->nchunk * kMaxProj *
+                        16);
     g->lay.rho = take(N * 8);
     g->lay.vpred = take(N * 8);
     g->lay.dpart = take(ndb * 3 * 8);
@@ -334,6 +350,25 @@ template <class T> T *wsp(ks_grid *g, size_t off)
 {
     return reinterpret_cast<T *>(g->ws + off);
 }
+
+// Event pair around one launch of class c (0 H.psi, 1 gather, 2 reductions).
+struct Timed {
+    ks_grid *g;
+    int slot = -1;
+    Timed(ks_grid *gg, int c) : g(gg)
+    {
+        if (g->profiling && g->ev_used < (int)g->ev_class.size()) {
+            slot = g->ev_used++;
+            g->ev_class[slot] = c;
+            hipEventRecord(g->ev[2 * slot], g->stream);
+        }
+    }
+    ~Timed()
+    {
+        if (slot >= 0)
+            hipEventRecord(g->ev[2 * slot + 1], g->stream);
+    }
+};
 
 void laser_A(const ks_grid *g, double t, double A[3])
 {
@@ -352,7 +387,7 @@ HArgs base_hargs(ks_grid *g)
 {
     HArgs a;
     a.geo = g->geo;
-    a.kL = g->d_kL;
+    a.kph = g->d_kph;
     a.nstates = g->ns;
     a.wocc = g->d_wocc;
     a.pj = g->pj;
@@ -367,9 +402,12 @@ GArgs base_gargs(ks_grid *g)
 {
     GArgs a;
     a.geo = g->geo;
-    a.kL = g->d_kL;
+    a.kph = g->d_kph;
     a.nstates = g->ns;
     a.pj = g->pj;
+    a.nchunk = g->nchunk;
+    if (g->ws)
+        a.Dpart = g->ws + g->lay.Dpart;
     return a;
 }
 
@@ -405,13 +443,19 @@ int taylor_exponential(ks_grid *g, const double2 *in, double2 *out,
     for (int j = 1; j <= 4; ++j) {
         const bool f64 = (j == 1) || !mx;
         ga.in = cur;
-        KS_HIP(launch_gather(mx, f64, ga, S, g->stream));
+        if (g->natoms > 0) {
+            Timed tm(g, 1);
+            KS_HIP(launch_gather(mx, f64, ga, S, g->stream));
+        }
         a.in = cur;
         a.cre = 0.0;
         a.cim = -tau / j;
         if (j < 4) {
             a.out = tb[j - 1];
-            KS_HIP(launch_hpsi(kTerm, mx, f64, a, S, g->stream));
+            {
+                Timed tm(g, 0);
+                KS_HIP(launch_hpsi(kTerm, mx, f64, a, S, g->stream));
+            }
             cur = tb[j - 1];
         } else {
             a.out = out;
@@ -420,6 +464,7 @@ int taylor_exponential(ks_grid *g, const double2 *in, double2 *out,
             a.t2 = tb[1];
             a.npart = npart;
             a.normpart = normpart;
+            Timed tm(g, 0);
             KS_HIP(launch_hpsi(final_mode, mx, false, a, S, g->stream));
         }
     }
@@ -448,8 +493,8 @@ int ks_grid_create(const ks_grid_desc *d, ks_grid **out)
         if (!(d->h[a] > 0.0))
             return fail(KS_E_ARG, "h[%d] must be > 0", a);
     }
-    if (d->n[0] > 256)
-        return fail(KS_E_UNSUPPORTED, "nx = %d > 256", d->n[0]);
+    if (d->n[0] > 192)
+        return fail(KS_E_UNSUPPORTED, "nx = %d > 192", d->n[0]);
     if (d->fd_half_width != 4)
         return fail(KS_E_UNSUPPORTED, "fd_half_width %d (only 4)",
                     d->fd_half_width);
@@ -498,20 +543,25 @@ int ks_grid_create(const ks_grid_desc *d, ks_grid **out)
     for (int k = 0; k < d->nk; ++k)
         for (int s = 0; s < d->nstates; ++s)
             g->wocc[k * d->nstates + s] = g->kw[k] * g->occ[s];
-    g->kL.resize(3 * d->nk);
+    g->kph.resize(3 * d->nk);
     for (int k = 0; k < d->nk; ++k)
-        for (int a = 0; a < 3; ++a)
-            g->kL[3 * k + a] = g->kpts[3 * k + a] * d->n[a] * d->h[a];
+        for (int a = 0; a < 3; ++a) {
+            const double ang = g->kpts[3 * k + a] * d->n[a] * d->h[a];
+            g->kph[3 * k + a] = make_double2(std::cos(ang), std::sin(ang));
+        }
     hipGetDevice(&g->device);
     int rc;
-    if ((rc = dev_upload(g, &g->d_kL, g->kL)) ||
+    if ((rc = dev_upload(g, &g->d_kph, g->kph)) ||
         (rc = dev_upload(g, &g->d_wocc, g->wocc)) ||
         (rc = dev_alloc(g, &g->d_v, (size_t)N)) ||
         (rc = build_projectors(g, d))) {
         ks_grid_destroy(g);
         return rc;
     }
-    choose_tiles(g);
+    if ((rc = set_tiles(g, 0, 0))) {
+        ks_grid_destroy(g);
+        return rc;
+    }
     layout(g);
     *out = g;
     return KS_OK;
@@ -522,6 +572,8 @@ int ks_grid_destroy(ks_grid *g)
     if (!g)
         return KS_OK;
     hipStreamSynchronize(g->stream);
+    for (hipEvent_t e : g->ev)
+        hipEventDestroy(e);
     for (void *p : g->owned)
         hipFree(p);
     delete g;
@@ -593,7 +645,10 @@ int ks_apply_h(ks_grid *g, const void *d_psi, void *d_hpsi, int k, int s0,
     ga.in = d_psi;
     ga.D = D;
     ga.sg0 = k * g->ns + s0;
-    KS_HIP(launch_gather(g->mixed, true, ga, ns, g->stream));
+    if (g->natoms > 0) {
+        Timed tm(g, 1);
+        KS_HIP(launch_gather(g->mixed, true, ga, ns, g->stream));
+    }
     HArgs a = base_hargs(g);
     a.in = d_psi;
     a.out = d_hpsi;
@@ -604,7 +659,10 @@ int ks_apply_h(ks_grid *g, const void *d_psi, void *d_hpsi, int k, int s0,
     a.a2half = 0.5 * (A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
     a.D = D;
     a.sg0 = k * g->ns + s0;
-    KS_HIP(launch_hpsi(kApply, g->mixed, true, a, ns, g->stream));
+    {
+        Timed tm(g, 0);
+        KS_HIP(launch_hpsi(kApply, g->mixed, true, a, ns, g->stream));
+    }
     return KS_OK;
 }
 
@@ -770,6 +828,74 @@ int ks_energy(ks_grid *g, const void *d_psi, const double *d_vion, double t,
     return KS_OK;
 }
 
+int ks_set_launch(ks_grid *g, int tile_rows, int zchunk)
+{
+    if (!g)
+        return fail(KS_E_ARG, "grid is NULL");
+    const int oldTY = g->TY, oldz = g->zchunk;
+    int rc = set_tiles(g, tile_rows, zchunk);
+    if (rc) {
+        set_tiles(g, oldTY, oldz);
+        return rc;
+    }
+    const size_t need = g->lay.total;
+    layout(g);
+    if (g->ws && g->lay.total > g->ws_bytes) {
+        g->ws = nullptr;   // the caller must lend a larger workspace
+        return fail(KS_E_OOM, "workspace too small for this launch shape");
+    }
+    (void)need;
+    return KS_OK;
+}
+
+int ks_get_launch(const ks_grid *g, int out[4])
+{
+    if (!g || !out)
+        return fail(KS_E_ARG, "NULL argument");
+    out[0] = g->TY;
+    out[1] = g->zchunk;
+    out[2] = g->ntile_y * g->nzc * g->stot;
+    out[3] = hpsi_threads(g->geo.nx, g->TY);
+    return KS_OK;
+}
+
+int ks_profile_begin(ks_grid *g, int capacity)
+{
+    if (!g || capacity < 1)
+        return fail(KS_E_ARG, "grid is NULL or capacity < 1");
+    while ((int)g->ev_class.size() < capacity) {
+        hipEvent_t a, b;
+        KS_HIP(hipEventCreate(&a));
+        KS_HIP(hipEventCreate(&b));
+        g->ev.push_back(a);
+        g->ev.push_back(b);
+        g->ev_class.push_back(0);
+    }
+    g->ev_used = 0;
+    g->profiling = true;
+    return KS_OK;
+}
+
+int ks_profile_end(ks_grid *g, double out_ms[3], long out_count[3])
+{
+    if (!g || !out_ms || !out_count)
+        return fail(KS_E_ARG, "NULL argument");
+    g->profiling = false;
+    KS_HIP(hipStreamSynchronize(g->stream));
+    for (int c = 0; c < 3; ++c) {
+        out_ms[c] = 0.0;
+        out_count[c] = 0;
+    }
+    for (int i = 0; i < g->ev_used; ++i) {
+        float ms = 0.0f;
+        KS_HIP(hipEventElapsedTime(&ms, g->ev[2 * i], g->ev[2 * i + 1]));
+        out_ms[g->ev_class[i]] += ms;
+        out_count[g->ev_class[i]] += 1;
+    }
+    g->ev_used = 0;
+    return KS_OK;
+}
+
 int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
                       int nsteps, double dt, double t0, double *d_dipole,
                       double *d_norms)
@@ -843,6 +969,7 @@ int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
             a.vion = d_vion;
             a.vout = vpred;
             a.xc = 1;
+            Timed tm(g, 2);
             KS_HIP(launch_density(a, g->stream));
             vnext = vpred;
         }
@@ -862,16 +989,19 @@ int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
             a.vout = g->d_v;
             a.xc = g->xc;
             a.dpart = d_dipole ? dpart : nullptr;
+            Timed tm(g, 2);
             KS_HIP(launch_density(a, g->stream));
             if (d_dipole)
                 KS_HIP(launch_dipole_finalize(dpart, ndb, h3,
                                               d_dipole + 3 * (step + 1),
                                               g->stream));
         }
-        if (d_norms)
+        if (d_norms) {
+            Timed tm(g, 2);
             KS_HIP(launch_norm_finalize(normpart, S, ntiles, h3,
                                         d_norms + (size_t)(step + 1) * S,
                                         g->stream));
+        }
     }
     return KS_OK;
 }

@@ -30,9 +30,11 @@ struct Geo {
 };
 
 // Projector tables on the device.  Sphere points of atom a occupy
-// [ioff[a], ioff[a] + npts[a]) of sidx/sshift; its table is
-// ptab[poff[a] + j * npts[a] + pt].  The scatter CSR lists, for every grid
-// point g, the (atom, sphere point) pairs covering it in soff[g]..soff[g+1].
+// [ioff[a], ioff[a] + npts[a]) of sidx/sshift (sshift: the lattice shift
+// T that brings the point into the sphere, three signed bytes); the
+// normalised table is ptab[poff[a] + j * npts[a] + pt].  The scatter
+// evaluates projectors from apos (x, y, z, rc^2) and arad
+// (1 / (2 sigma^2), 1 / rc^2); EjN[a][j] = N_j h^3 E_{a,l(j)}.
 struct ProjDev {
     int natoms = 0;
     const int *nproj = nullptr;
@@ -40,13 +42,12 @@ struct ProjDev {
     const long *ioff = nullptr;
     const long *poff = nullptr;
     const int *sidx = nullptr;
-    const int *sshift = nullptr;   // packed lattice shift, 0 = none
+    const int *sshift = nullptr;
     const double *ptab = nullptr;
     const float *ptabf = nullptr;
-    const double *Ej = nullptr;    // [natoms][9] = h^3 E_{a,l(j)}
-    const int *soff = nullptr;
-    const int2 *sent = nullptr;
-    const unsigned char *rowhit = nullptr;  // [nz*ny]: row has sphere points
+    const double *EjN = nullptr;
+    const double4 *apos = nullptr;
+    const double2 *arad = nullptr;
 };
 
 struct HArgs {
@@ -60,7 +61,7 @@ struct HArgs {
     double a2half = 0.0;           // |A|^2 / 2
     double A[3] = {0.0, 0.0, 0.0};
     double cre = 1.0, cim = 0.0;   // complex scale of H.in
-    const double *kL = nullptr;    // [nk][3] k_a L_a
+    const double2 *kph = nullptr;  // [nk][3] exp(i k_a L_a)
     int nstates = 1;               // states per k-point
     int sg0 = 0;                   // global state index of launch state 0
     const double *wocc = nullptr;  // [nk*nstates] w_k f_s
@@ -71,13 +72,19 @@ struct HArgs {
     int TY = 1, zchunk = 1, ntile_y = 1, nzc = 1;
 };
 
+// LDS available to one workgroup of the H.psi kernel.
+constexpr size_t kLdsBudget = 65536;
+
 struct GArgs {
     Geo geo;
     const void *in = nullptr;
     void *D = nullptr;
-    const double *kL = nullptr;
+    const double2 *kph = nullptr;
     int nstates = 1;
     int sg0 = 0;
+    int ns = 0;                    // states in this launch
+    void *Dpart = nullptr;         // [ns][natoms][nchunk][9] chunk sums
+    int nchunk = 1;                // chunks of the largest sphere
     ProjDev pj;
 };
 
@@ -94,11 +101,16 @@ struct DArgs {
     double *dpart = nullptr;       // optional [nblocks][3] dipole partials
 };
 
+// Launch shape of the H.psi kernel.
+int hpsi_threads(int nx, int TY);
+size_t hpsi_lds_bytes(int nx, int TY, int natoms, bool mixed);
+
 // Launchers (ks_kernels.hip).  All asynchronous on `st`.
 hipError_t launch_hpsi(int mode, bool mixed, bool in_is_f64, const HArgs &a,
                        int ns, hipStream_t st);
 hipError_t launch_gather(bool mixed, bool in_is_f64, const GArgs &a, int ns,
                          hipStream_t st);
+int gather_chunks(int max_npts);
 int density_blocks(long N);
 hipError_t launch_density(const DArgs &a, hipStream_t st);
 hipError_t launch_dipole_finalize(const double *dpart, int nblocks,

@@ -22,6 +22,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace ks {
 
 // Half-width-4 central weights: Laplacian (c0..c4) and gradient (d1..d4).
@@ -100,68 +102,6 @@ __device__ __forceinline__ int floordiv(int a, int n)
     return a >= 0 ? a / n : -((-a + n - 1) / n);
 }
 
-template <class R> __device__ __forceinline__ typename Cplx<R>::T
-phase(double ang)
-{
-    double s, c;
-    sincos(ang, &s, &c);
-    return cmk<typename Cplx<R>::T>(c, s);
-}
-
-// Lattice shift packed as three signed bytes (x, y, z).
-__device__ __forceinline__ double shift_angle(int code, const double *kL)
-{
-    int tx = (int)(signed char)(code & 0xff);
-    int ty = (int)(signed char)((code >> 8) & 0xff);
-    int tz = (int)(signed char)((code >> 16) & 0xff);
-    return tx * kL[0] + ty * kL[1] + tz * kL[2];
-}
-
-// value at (x, y, z) with y in range, z possibly outside (boundary rule)
-template <class R, class InT>
-__device__ __forceinline__ typename Cplx<R>::T
-load_z(const InT *st, const Geo &G, const double *kL, int x, int y, int z)
-{
-    using V = typename Cplx<R>::T;
-    if ((unsigned)z < (unsigned)G.nz)
-        return ldc<R>(st, ((long)z * G.ny + y) * G.nx + x);
-    if (!G.per[2])
-        return czero<V>();
-    int w = floordiv(z, G.nz);
-    int zz = z - w * G.nz;
-    V v = ldc<R>(st, ((long)zz * G.ny + y) * G.nx + x);
-    return cmul(v, phase<R>(w * kL[2]));
-}
-
-// value at (x, y, z) with z in range, y possibly outside
-template <class R, class InT>
-__device__ __forceinline__ typename Cplx<R>::T
-load_y(const InT *st, const Geo &G, const double *kL, int x, int y, int z)
-{
-    using V = typename Cplx<R>::T;
-    if ((unsigned)y < (unsigned)G.ny)
-        return ldc<R>(st, ((long)z * G.ny + y) * G.nx + x);
-    if (!G.per[1])
-        return czero<V>();
-    int w = floordiv(y, G.ny);
-    int yy = y - w * G.ny;
-    V v = ldc<R>(st, ((long)z * G.ny + yy) * G.nx + x);
-    return cmul(v, phase<R>(w * kL[1]));
-}
-
-// neighbour along x within an LDS row (index possibly outside [0, nx))
-template <class V, class R>
-__device__ __forceinline__ V row_x(const V *row, int xi, int nx, int per,
-                                   double kLx)
-{
-    if ((unsigned)xi < (unsigned)nx)
-        return row[xi];
-    if (!per)
-        return czero<V>();
-    int w = floordiv(xi, nx);
-    return cmul(row[xi - w * nx], phase<R>(w * kLx));
-}
-
 template <class T> __device__ __forceinline__ T wave_sum(T v)
 {
 #pragma unroll
@@ -193,150 +133,375 @@ __device__ __forceinline__ void block_sum(T (&v)[NV], T *sbuf)
         }
 }
 
+
+// ---------------------------------------------------------------------------
+// Bloch phases.  kph[k][a] = exp(i k_a L_a) is tabulated on the host; a wrap
+// by w cells along axis a multiplies by kph[k][a]^w (|w| is 1 except on
+// axes shorter than the stencil).
+// ---------------------------------------------------------------------------
+template <class V>
+__device__ __forceinline__ V phase_pow(const double2 *kph, int axis, int w)
+{
+    V ph = cmk<V>(kph[axis].x, kph[axis].y);
+    if (w < 0) {
+        ph.y = -ph.y;
+        w = -w;
+    }
+    V r = ph;
+    for (int i = 1; i < w; ++i)
+        r = cmul(r, ph);
+    return r;
+}
+
+template <class V>
+__device__ __forceinline__ V shift_phase(const double2 *kph, int code)
+{
+    // lattice shift packed as three signed bytes (x, y, z)
+    V r = cmk<V>(1.0, 0.0);
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int t = (int)(signed char)((code >> (8 * ax)) & 0xff);
+        if (t)
+            r = cmul(r, phase_pow<V>(kph, ax, t));
+    }
+    return r;
+}
+
+__device__ __forceinline__ double axis_coord(int n, double h, int per, int i)
+{
+    return per ? i * h : (i - 0.5 * (n - 1)) * h;
+}
+
+// ---------------------------------------------------------------------------
+// Workgroups are handed to the 8 XCDs round robin in launch order; remap the
+// launch index so that each XCD receives a contiguous range of work items
+// (neighbouring y-tiles of the same state, which share halo rows in that
+// XCD's L2).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_remap(int L, int nblk)
+{
+    constexpr int X = 8;
+    const int per = nblk / X, rem = nblk % X;
+    const int x = L % X, i = L / X;
+    return x * per + min(x, rem) + i;
+}
+
 // ---------------------------------------------------------------------------
 // H.psi with a fused epilogue.  R: arithmetic precision; InT: storage type of
 // the input states; TT: storage type of t-terms (t1, t2, term outputs).
+//
+// LDS holds the current xy plane of the tile padded by 4 rows above and below
+// and 4 columns left and right, filled at load time with the neighbours'
+// values, zeros (zero boundary) or Bloch-wrapped values; the stencil then
+// reads its x and y neighbours without branches.  The z neighbours come from
+// a per-thread register queue.  Per z-plane: one barrier; two plane buffers
+// alternate, and the loads of plane z+1 (halo) and z+5 (own column) are in
+// flight while plane z is computed.
+//
+// The KB scatter evaluates the projectors at the point from the atom
+// geometry (p_j = N_j P_j(r) exp(-r^2 / 2 sigma^2) (1 - r^2/rc^2)^2, the
+// normalisation N_j folded into the coefficients D by the gather), for the
+// atoms whose sphere meets the workgroup's y-slab (listed once per
+// workgroup, in atom order) and the current plane.
 // ---------------------------------------------------------------------------
+constexpr int kHaloMax = 6;   // halo elements per thread
+
 template <class R, class InT, class TT, int MODE>
 __global__ __launch_bounds__(512) void k_hpsi(HArgs a)
 {
     using V = typename Cplx<R>::T;
-    extern __shared__ unsigned char smem_raw[];
-    V *sp = reinterpret_cast<V *>(smem_raw);
+    extern __shared__ double2 smem_d2[];
+    unsigned char *smem_raw = reinterpret_cast<unsigned char *>(smem_d2);
+    __shared__ int s_ncand;
 
-    const Geo G = a.geo;
-    const int nx = G.nx, ny = G.ny, nz = G.nz;
-    const long N = G.N;
-    const int tile = blockIdx.x;
-    const int tile_y = tile % a.ntile_y;
+    const int nx = a.geo.nx, ny = a.geo.ny, nz = a.geo.nz;
+    const int P = nx * ny;
+    const long N = a.geo.N;
+    const int ntiles = a.ntile_y * a.nzc;
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    const int sl = w / ntiles;
+    const int tile = w - sl * ntiles;
     const int zc = tile / a.ntile_y;
-    const int sl = blockIdx.y;
+    const int tile_y = tile - zc * a.ntile_y;
     const int sg = a.sg0 + sl;
     const int kk = sg / a.nstates;
-    const double *kL = a.kL + 3 * kk;
+    const double2 *kph = a.kph + 3 * kk;
+    const int perx = a.geo.per[0], pery = a.geo.per[1], perz = a.geo.per[2];
 
     const int TY = a.TY;
     const int y0 = tile_y * TY;
     const int rows = min(TY, ny - y0);
     const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
     const int x = tid % nx;
     const int yl = tid / nx;
     const bool act = yl < rows;
     const int y = y0 + (act ? yl : 0);
     const int z0 = zc * a.zchunk;
     const int z1 = min(nz, z0 + a.zchunk);
+    const int RS = nx + 2 * kHalf;                  // LDS row stride
+    const int own = (yl + kHalf) * RS + x + kHalf;  // LDS slot of the point
+    const int po = y * nx + x;                      // offset within a plane
+
+    const int natoms = a.pj.natoms;
+    const int plane = (TY + 2 * kHalf) * RS;
+    V *buf0 = reinterpret_cast<V *>(smem_raw);
+    V *buf1 = buf0 + plane;
+    int *scand = reinterpret_cast<int *>(buf1 + plane);
 
     const InT *in = reinterpret_cast<const InT *>(a.in) + (size_t)sl * N;
-    const R ih2x = (R)(1.0 / (G.h[0] * G.h[0]));
-    const R ih2y = (R)(1.0 / (G.h[1] * G.h[1]));
-    const R ih2z = (R)(1.0 / (G.h[2] * G.h[2]));
-    const R ihx = (R)(1.0 / G.h[0]), ihy = (R)(1.0 / G.h[1]),
-            ihz = (R)(1.0 / G.h[2]);
+
+    // ---- projector coefficients (read through the scalar cache: every
+    // lane of a wave uses the same atom) and candidate atoms of this y-slab
+    const V *Dg = reinterpret_cast<const V *>(a.D) +
+                  (size_t)sl * natoms * kMaxProj;
+    if (tid == 0) {
+        int c = 0;
+        if (natoms > 0) {
+            const double Ly = ny * a.geo.h[1];
+            const double ylo = axis_coord(ny, a.geo.h[1], pery, y0);
+            const double yhi = axis_coord(ny, a.geo.h[1], pery,
+                                          y0 + rows - 1);
+            for (int at = 0; at < natoms; ++at) {
+                const double4 ap = a.pj.apos[at];
+                const double rc = sqrt(ap.w);
+                double best = 1e300;
+                for (int im = -1; im <= 1; ++im) {
+                    if (im && !pery)
+                        continue;
+                    const double Y = ap.y + im * Ly;
+                    const double d = Y < ylo ? ylo - Y : (Y > yhi ? Y - yhi
+                                                                  : 0.0);
+                    best = fmin(best, d);
+                }
+                if (best < rc)
+                    scand[c++] = at;
+            }
+        }
+        s_ncand = c;
+    }
+
+    // ---- Bloch phases of x/y wraps by -4..4 cells: sPh[(wy+4)*9 + wx+4],
+    // and of z wraps: sPz[wz+4] ----
+    V *sPh = reinterpret_cast<V *>(reinterpret_cast<unsigned char *>(scand) +
+                                   ((natoms * sizeof(int) + 15) & ~15));
+    V *sPz = sPh + 81;
+    for (int t = tid; t < 81 + 9; t += nthr) {
+        V ph;
+        if (t < 81) {
+            const int wx = t % 9 - 4, wy = t / 9 - 4;
+            ph = cmk<V>(1.0, 0.0);
+            if (wx)
+                ph = cmul(ph, phase_pow<V>(kph, 0, wx));
+            if (wy)
+                ph = cmul(ph, phase_pow<V>(kph, 1, wy));
+        } else {
+            const int wz = t - 81 - 4;
+            ph = wz ? phase_pow<V>(kph, 2, wz) : cmk<V>(1.0, 0.0);
+        }
+        sPh[t] = ph;   // sPz follows sPh
+    }
+
+    // ---- halo elements of this thread: plane offset (-1: zero, -2: none)
+    // and packed (LDS slot, phase id; id 40 is no wrap) ----
+    const int nyh = 2 * kHalf * nx;                 // y-halo rows
+    const int nxh = 2 * kHalf * (rows + 2 * kHalf); // x-halo columns
+    int hoff[kHaloMax], hpk[kHaloMax];
+#pragma unroll
+    for (int i = 0; i < kHaloMax; ++i) {
+        const int e = tid + i * nthr;
+        hoff[i] = -2;
+        hpk[i] = 0;
+        int ys, xs, slot;
+        if (e < nyh) {
+            const int hr = e / nx, hx = e - hr * nx;
+            const int r = hr < kHalf ? hr : rows + hr;   // LDS row
+            ys = y0 - kHalf + r;
+            xs = hx;
+            slot = r * RS + hx + kHalf;
+        } else if (e < nyh + nxh) {
+            const int e2 = e - nyh;
+            const int r = e2 / (2 * kHalf), cc = e2 - r * (2 * kHalf);
+            ys = y0 - kHalf + r;
+            xs = cc < kHalf ? cc - kHalf : nx + cc - kHalf;
+            slot = r * RS + (cc < kHalf ? cc : nx + cc);
+        } else {
+            continue;
+        }
+        int wy = 0, wx = 0;
+        bool zero = false;
+        if (ys < 0 || ys >= ny) {
+            if (pery) {
+                wy = floordiv(ys, ny);
+                ys -= wy * ny;
+            } else {
+                zero = true;
+            }
+        }
+        if (xs < 0 || xs >= nx) {
+            if (perx) {
+                wx = floordiv(xs, nx);
+                xs -= wx * nx;
+            } else {
+                zero = true;
+            }
+        }
+        hoff[i] = zero ? -1 : ys * nx + xs;
+        hpk[i] = slot | (((wy + 4) * 9 + wx + 4) << 20);
+    }
+
+    // halo element i of plane zq (in range)
+    auto halo_val = [&](int i, int zq) -> V {
+        V v = czero<V>();
+        if (hoff[i] >= 0) {
+            v = ldc<R>(in, (long)zq * P + hoff[i]);
+            const int pid = hpk[i] >> 20;
+            if (pid != 40)
+                v = cmul(v, sPh[pid]);
+        }
+        return v;
+    };
+    // own column value of plane zq (any integer)
+    auto col_val = [&](int zq) -> V {
+        if (zq >= 0 && zq < nz)
+            return ldc<R>(in, (long)zq * P + po);
+        if (!perz)
+            return czero<V>();
+        const int wz = floordiv(zq, nz);
+        return cmul(ldc<R>(in, (long)(zq - wz * nz) * P + po),
+                    sPz[wz + 4]);
+    };
+    __syncthreads();   // phase tables, candidate list and D are in LDS
+
+    // ---- prologue: z-column for planes z0-4 .. z0+4, plane z0 -> buf0 ----
+    V q[2 * kHalf + 1];
+#pragma unroll
+    for (int m = 0; m <= 2 * kHalf; ++m)
+        q[m] = act ? col_val(z0 - kHalf + m) : czero<V>();
+    if (act)
+        buf0[own] = q[kHalf];
+#pragma unroll
+    for (int i = 0; i < kHaloMax; ++i)
+        if (hoff[i] >= -1)
+            buf0[hpk[i] & 0xfffff] = halo_val(i, z0);
+
     R LC[5], GD[5];
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
         LC[m] = (R)kLap[m];
         GD[m] = (R)kGrad[m];
     }
+    const R ih2x = (R)(1.0 / (a.geo.h[0] * a.geo.h[0]));
+    const R ih2y = (R)(1.0 / (a.geo.h[1] * a.geo.h[1]));
+    const R ih2z = (R)(1.0 / (a.geo.h[2] * a.geo.h[2]));
+    const R c0sum = LC[0] * (ih2x + ih2y + ih2z);
     const bool has_A = (a.A[0] != 0.0) || (a.A[1] != 0.0) || (a.A[2] != 0.0);
-    const R Ax = (R)a.A[0], Ay = (R)a.A[1], Az = (R)a.A[2];
+    const R Ax = (R)(a.A[0] / a.geo.h[0]), Ay = (R)(a.A[1] / a.geo.h[1]),
+            Az = (R)(a.A[2] / a.geo.h[2]);
     const V cs = cmk<V>(a.cre, a.cim);
-    const V *Dst = reinterpret_cast<const V *>(a.D) +
-                   (size_t)sl * a.pj.natoms * kMaxProj;
+    const double hx = a.geo.h[0], hy = a.geo.h[1], hz = a.geo.h[2];
+    const double Lx = nx * hx, Ly = ny * hy, Lz = nz * hz;
+    const double xcrd = axis_coord(nx, hx, perx, x);
+    const double ycrd = axis_coord(ny, hy, pery, y);
     const double w_occ = (MODE == kFinal || MODE == kFinalPred)
                              ? a.wocc[sg] : 0.0;
-
-    V q[2 * kHalf + 1];
-#pragma unroll
-    for (int m = 0; m < 2 * kHalf; ++m)
-        q[m] = act ? load_z<R>(in, G, kL, x, y, z0 - kHalf + m)
-                   : czero<V>();
-
     double nrm = 0.0;
-    const int nthr = blockDim.x;
-    const int row = yl + kHalf;
-
+    V *cur = buf0, *nxt = buf1;
     for (int z = z0; z < z1; ++z) {
-        q[2 * kHalf] = act ? load_z<R>(in, G, kL, x, y, z + kHalf)
-                           : czero<V>();
-        if (act)
-            sp[row * nx + x] = q[kHalf];
-        for (int e = tid; e < 2 * kHalf * nx; e += nthr) {
-            int hr = e / nx, hx = e - hr * nx;
-            int yy = hr < kHalf ? y0 - kHalf + hr : y0 + rows + (hr - kHalf);
-            int lr = hr < kHalf ? hr : rows + hr;
-            sp[lr * nx + hx] = load_y<R>(in, G, kL, hx, yy, z);
-        }
+        const bool more = z + 1 < z1;
+        // loads for the next plane, in flight during this plane's compute
+        V hv[kHaloMax];
+#pragma unroll
+        for (int i = 0; i < kHaloMax; ++i)
+            hv[i] = more ? halo_val(i, z + 1) : czero<V>();
+        const V nq = (more && act) ? col_val(z + kHalf + 1) : czero<V>();
         __syncthreads();
         if (act) {
             const V c = q[kHalf];
-            const V *rp = sp + row * nx;
-            V sx = czero<V>(), gx = czero<V>();
-            if (x >= kHalf && x < nx - kHalf) {
-#pragma unroll
-                for (int m = 1; m <= kHalf; ++m) {
-                    V p = rp[x + m], n = rp[x - m];
-                    sx = cadd(sx, cscale(cadd(p, n), LC[m]));
-                    gx = cadd(gx, cscale(csub(p, n), GD[m]));
-                }
-            } else {
-#pragma unroll
-                for (int m = 1; m <= kHalf; ++m) {
-                    V p = row_x<V, R>(rp, x + m, nx, G.per[0], kL[0]);
-                    V n = row_x<V, R>(rp, x - m, nx, G.per[0], kL[0]);
-                    sx = cadd(sx, cscale(cadd(p, n), LC[m]));
-                    gx = cadd(gx, cscale(csub(p, n), GD[m]));
-                }
-            }
-            V sy = czero<V>(), gy = czero<V>();
+            const V *rp = cur + own;
+            V sx = czero<V>(), sy = czero<V>(), sz = czero<V>();
+            V gx = czero<V>(), gy = czero<V>(), gz = czero<V>();
 #pragma unroll
             for (int m = 1; m <= kHalf; ++m) {
-                V p = sp[(row + m) * nx + x], n = sp[(row - m) * nx + x];
-                sy = cadd(sy, cscale(cadd(p, n), LC[m]));
-                gy = cadd(gy, cscale(csub(p, n), GD[m]));
+                const V xp = rp[m], xn = rp[-m];
+                const V yp = rp[m * RS], yn = rp[-m * RS];
+                const V zp = q[kHalf + m], zn = q[kHalf - m];
+                sx = cadd(sx, cscale(cadd(xp, xn), LC[m]));
+                sy = cadd(sy, cscale(cadd(yp, yn), LC[m]));
+                sz = cadd(sz, cscale(cadd(zp, zn), LC[m]));
+                if (has_A) {
+                    gx = cadd(gx, cscale(csub(xp, xn), GD[m]));
+                    gy = cadd(gy, cscale(csub(yp, yn), GD[m]));
+                    gz = cadd(gz, cscale(csub(zp, zn), GD[m]));
+                }
             }
-            V sz = czero<V>(), gz = czero<V>();
-#pragma unroll
-            for (int m = 1; m <= kHalf; ++m) {
-                V p = q[kHalf + m], n = q[kHalf - m];
-                sz = cadd(sz, cscale(cadd(p, n), LC[m]));
-                gz = cadd(gz, cscale(csub(p, n), GD[m]));
-            }
-            const long g = ((long)z * ny + y) * nx + x;
-            // -1/2 Lap + (v + |A|^2/2)
+            const long g = (long)z * P + po;
             V lap = cadd(cadd(cscale(sx, ih2x), cscale(sy, ih2y)),
                          cscale(sz, ih2z));
-            lap = cadd(lap, cscale(c, LC[0] * (ih2x + ih2y + ih2z)));
+            lap = cadd(lap, cscale(c, c0sum));
             const R vv = (R)(a.v[g] + a.a2half);
             V hp = cadd(cscale(lap, (R)-0.5), cscale(c, vv));
             if (has_A) {
                 // -i A.grad
-                V gr = cadd(cadd(cscale(gx, Ax * ihx), cscale(gy, Ay * ihy)),
-                            cscale(gz, Az * ihz));
+                const V gr = cadd(cadd(cscale(gx, Ax), cscale(gy, Ay)),
+                                  cscale(gz, Az));
                 hp.x += gr.y;
                 hp.y -= gr.x;
             }
-            if (a.pj.natoms > 0 && a.pj.rowhit[z * ny + y]) {
-                const int e0 = a.pj.soff[g], e1 = a.pj.soff[g + 1];
-                for (int e = e0; e < e1; ++e) {
-                    const int2 en = a.pj.sent[e];
-                    const int at = en.x, pt = en.y;
-                    const int np = a.pj.nproj[at];
-                    const int npt = a.pj.npts[at];
-                    const long pb = a.pj.poff[at] + pt;
-                    V acc = czero<V>();
-                    const V *Da = Dst + at * kMaxProj;
-                    for (int j = 0; j < np; ++j) {
-                        R pv;
-                        if constexpr (sizeof(R) == 8)
-                            pv = a.pj.ptab[pb + (long)j * npt];
-                        else
-                            pv = a.pj.ptabf[pb + (long)j * npt];
-                        acc = cadd(acc, cscale(Da[j], pv));
+            const int ncand = __builtin_amdgcn_readfirstlane(s_ncand);
+            if (ncand > 0) {
+                const double zcrd = axis_coord(nz, hz, perz, z);
+                for (int ci = 0; ci < ncand; ++ci) {
+                    const int at = __builtin_amdgcn_readfirstlane(scand[ci]);
+                    const double4 ap = a.pj.apos[at];
+                    double dz = zcrd - ap.z;
+                    int mz = 0;
+                    if (perz) {
+                        mz = (int)rint(dz / Lz);
+                        dz -= mz * Lz;
                     }
-                    const int code = a.pj.sshift[a.pj.ioff[at] + pt];
-                    if (code)
-                        acc = cmulc(acc, phase<R>(shift_angle(code, kL)));
+                    if (!(dz * dz < ap.w))
+                        continue;
+                    double dx = xcrd - ap.x, dy = ycrd - ap.y;
+                    int mx = 0, my = 0;
+                    if (perx) {
+                        mx = (int)rint(dx / Lx);
+                        dx -= mx * Lx;
+                    }
+                    if (pery) {
+                        my = (int)rint(dy / Ly);
+                        dy -= my * Ly;
+                    }
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (!(r2 < ap.w))
+                        continue;
+                    const double2 ar = a.pj.arad[at];   // 1/(2 s^2), 1/rc^2
+                    const double wv = 1.0 - r2 * ar.y;
+                    const R rad = (R)(exp(-r2 * ar.x) * wv * wv);
+                    const int np = a.pj.nproj[at];
+                    const V *Da = Dg + at * kMaxProj;
+                    const R X = (R)dx, Y = (R)dy, Z = (R)dz;
+                    V acc = Da[0];
+                    if (np > 1) {
+                        acc = cadd(acc, cscale(Da[1], X));
+                        acc = cadd(acc, cscale(Da[2], Y));
+                        acc = cadd(acc, cscale(Da[3], Z));
+                    }
+                    if (np > 4) {
+                        acc = cadd(acc, cscale(Da[4], X * Y));
+                        acc = cadd(acc, cscale(Da[5], Y * Z));
+                        acc = cadd(acc, cscale(Da[6], Z * X));
+                        acc = cadd(acc, cscale(Da[7], X * X - Y * Y));
+                        acc = cadd(acc, cscale(Da[8], (R)3 * Z * Z -
+                                                          (X * X + Y * Y +
+                                                           Z * Z)));
+                    }
+                    acc = cscale(acc, rad);
+                    if (mx | my | mz) {
+                        acc = cmul(acc, sPh[(my + 4) * 9 + mx + 4]);
+                        if (mz)
+                            acc = cmul(acc, sPz[mz + 4]);
+                    }
                     hp = cadd(hp, acc);
                 }
             }
@@ -346,7 +511,7 @@ __global__ __launch_bounds__(512) void k_hpsi(HArgs a)
                 o.y = hp.y;
                 reinterpret_cast<double2 *>(a.out)[(size_t)sl * N + g] = o;
             } else if constexpr (MODE == kTerm) {
-                V t = cmul(cs, hp);
+                const V t = cmul(cs, hp);
                 TT o;
                 o.x = t.x;
                 o.y = t.y;
@@ -354,22 +519,22 @@ __global__ __launch_bounds__(512) void k_hpsi(HArgs a)
             } else {
                 const V t4 = cmul(cs, hp);
                 const size_t i = (size_t)sl * N + g;
-                const double2 b = a.base[i];
+                const double2 bb = a.base[i];
                 const TT u1 = reinterpret_cast<const TT *>(a.t1)[i];
                 const TT u2 = reinterpret_cast<const TT *>(a.t2)[i];
-                double re = b.x + (double)u1.x + (double)u2.x + (double)c.x +
-                            (double)t4.x;
-                double im = b.y + (double)u1.y + (double)u2.y + (double)c.y +
-                            (double)t4.y;
+                const double re = bb.x + (double)u1.x + (double)u2.x +
+                                  (double)c.x + (double)t4.x;
+                const double im = bb.y + (double)u1.y + (double)u2.y +
+                                  (double)c.y + (double)t4.y;
                 double2 o;
                 o.x = re;
                 o.y = im;
                 reinterpret_cast<double2 *>(a.out)[i] = o;
                 if constexpr (MODE == kFinalPred) {
-                    double pr = b.x + 2.0 * u1.x + 4.0 * u2.x + 8.0 * c.x +
-                                16.0 * (double)t4.x;
-                    double pi = b.y + 2.0 * u1.y + 4.0 * u2.y + 8.0 * c.y +
-                                16.0 * (double)t4.y;
+                    const double pr = bb.x + 2.0 * u1.x + 4.0 * u2.x +
+                                      8.0 * c.x + 16.0 * (double)t4.x;
+                    const double pi = bb.y + 2.0 * u1.y + 4.0 * u2.y +
+                                      8.0 * c.y + 16.0 * (double)t4.y;
                     if (a.npart)
                         a.npart[i] = w_occ * (pr * pr + pi * pi);
                 } else {
@@ -380,49 +545,75 @@ __global__ __launch_bounds__(512) void k_hpsi(HArgs a)
                 }
             }
         }
-        __syncthreads();
+        // plane z+1 into the other buffer (free: its last readers passed
+        // this iteration's barrier)
+        if (more) {
+            if (act)
+                nxt[own] = q[kHalf + 1];
+#pragma unroll
+            for (int i = 0; i < kHaloMax; ++i)
+                if (hoff[i] >= -1)
+                    nxt[hpk[i] & 0xfffff] = hv[i];
+        }
 #pragma unroll
         for (int m = 0; m < 2 * kHalf; ++m)
             q[m] = q[m + 1];
+        q[2 * kHalf] = nq;
+        V *t = cur;
+        cur = nxt;
+        nxt = t;
     }
     if constexpr (MODE == kFinal) {
         if (!a.normpart)
             return;
+        __syncthreads();
         double vals[1] = {nrm};
         block_sum<double, 1>(vals, reinterpret_cast<double *>(smem_raw));
         if (tid == 0)
-            a.normpart[(size_t)sl * (a.ntile_y * a.nzc) + tile] = vals[0];
+            a.normpart[(size_t)sl * ntiles + tile] = vals[0];
     }
 }
 
 // ---------------------------------------------------------------------------
-// KB projector gather: D[s][a][j] = h^3 E_{a,l(j)} sum_pt p~_j(pt) in_s(pt)
-// One workgroup per (atom, state); fixed-order reduction (deterministic).
+// KB projector gather: D[s][a][j] = N_j h^3 E_{a,l(j)} sum_pt p~_j(pt) in_s(pt)
+// (N_j: the projector normalisation, folded in for the scatter).
+// Stage 1: a workgroup takes one atom, one chunk of kGatherChunk sphere points
+// and kGatherStates states, one wavefront per state (the states share the
+// table reads), and writes a partial sum per chunk.  Stage 2 adds the chunks
+// in order.  Both stages reduce in a fixed order (deterministic).
 // ---------------------------------------------------------------------------
+constexpr int kGatherStates = 4;
+constexpr int kGatherChunk = 1024;
+
 template <class R, class InT>
-__global__ __launch_bounds__(256) void k_gather(GArgs a)
+__global__ __launch_bounds__(64 * kGatherStates) void k_gather(GArgs a)
 {
     using V = typename Cplx<R>::T;
-    __shared__ R sbuf[(256 / 64) * 2 * kMaxProj];
     const int at = blockIdx.x;
-    const int sl = blockIdx.y;
+    const int ch = blockIdx.z;
+    const int lane = threadIdx.x & 63;
+    const int sl = blockIdx.y * kGatherStates + (threadIdx.x >> 6);
+    if (sl >= a.ns)
+        return;
     const int sg = a.sg0 + sl;
     const int kk = sg / a.nstates;
-    const double *kL = a.kL + 3 * kk;
+    const double2 *kph = a.kph + 3 * kk;
     const InT *in = reinterpret_cast<const InT *>(a.in) + (size_t)sl * a.geo.N;
     const int np = a.pj.nproj[at];
     const int npt = a.pj.npts[at];
     const long io = a.pj.ioff[at];
     const long po = a.pj.poff[at];
+    const int p0 = ch * kGatherChunk;
+    const int p1 = min(npt, p0 + kGatherChunk);
     R acc[2 * kMaxProj];
 #pragma unroll
     for (int j = 0; j < 2 * kMaxProj; ++j)
         acc[j] = 0;
-    for (int pt = threadIdx.x; pt < npt; pt += blockDim.x) {
+    for (int pt = p0 + lane; pt < p1; pt += 64) {
         V val = ldc<R>(in, a.pj.sidx[io + pt]);
         const int code = a.pj.sshift[io + pt];
         if (code)
-            val = cmul(val, phase<R>(shift_angle(code, kL)));
+            val = cmul(val, shift_phase<V>(kph, code));
 #pragma unroll
         for (int j = 0; j < kMaxProj; ++j) {
             if (j < np) {
@@ -436,15 +627,39 @@ __global__ __launch_bounds__(256) void k_gather(GArgs a)
             }
         }
     }
-    block_sum<R, 2 * kMaxProj>(acc, sbuf);
-    if (threadIdx.x == 0) {
-        V *D = reinterpret_cast<V *>(a.D) +
-               ((size_t)sl * a.pj.natoms + at) * kMaxProj;
-        for (int j = 0; j < kMaxProj; ++j) {
-            R e = (j < np) ? (R)a.pj.Ej[at * kMaxProj + j] : (R)0;
-            D[j] = cmk<V>(e * acc[2 * j], e * acc[2 * j + 1]);
-        }
+#pragma unroll
+    for (int j = 0; j < 2 * kMaxProj; ++j)
+        acc[j] = wave_sum(acc[j]);
+    if (lane == 0) {
+        V *part = reinterpret_cast<V *>(a.Dpart) +
+                  (((size_t)sl * a.pj.natoms + at) * a.nchunk + ch) * kMaxProj;
+        for (int j = 0; j < kMaxProj; ++j)
+            part[j] = cmk<V>(acc[2 * j], acc[2 * j + 1]);
     }
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_gather_finalize(GArgs a)
+{
+    using V = typename Cplx<R>::T;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long total = (long)a.ns * a.pj.natoms * kMaxProj;
+    if (i >= total)
+        return;
+    const int j = (int)(i % kMaxProj);
+    const long sa = i / kMaxProj;           // s * natoms + atom
+    const int at = (int)(sa % a.pj.natoms);
+    const int nch = (a.pj.npts[at] + kGatherChunk - 1) / kGatherChunk;
+    const V *part = reinterpret_cast<const V *>(a.Dpart) +
+                    (size_t)sa * a.nchunk * kMaxProj + j;
+    R re = 0, im = 0;
+    for (int c = 0; c < nch; ++c) {
+        V v = part[(size_t)c * kMaxProj];
+        re += v.x;
+        im += v.y;
+    }
+    const R e = (j < a.pj.nproj[at]) ? (R)a.pj.EjN[at * kMaxProj + j] : (R)0;
+    reinterpret_cast<V *>(a.D)[i] = cmk<V>(e * re, e * im);
 }
 
 // ---------------------------------------------------------------------------
@@ -452,11 +667,6 @@ __global__ __launch_bounds__(256) void k_gather(GArgs a)
 // weighted |psi|^2); optional v = v_ion + v_x(rho); optional dipole partials
 // ---------------------------------------------------------------------------
 constexpr int kDensThreads = 256;
-
-__device__ __forceinline__ double axis_coord(int n, double h, int per, int i)
-{
-    return per ? i * h : (i - 0.5 * (n - 1)) * h;
-}
 
 __global__ __launch_bounds__(kDensThreads) void k_density(DArgs a)
 {
@@ -685,15 +895,32 @@ __global__ __launch_bounds__(256) void k_exchange_partial(Geo G,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+int hpsi_threads(int nx, int TY)
+{
+    // enough threads that the halo (8 rows of nx, 8 columns of TY + 8)
+    // needs at most kHaloMax loads per thread
+    int want = std::max(nx * TY, 2 * nx);
+    const int halo = 2 * kHalf * nx + 2 * kHalf * (TY + 2 * kHalf);
+    want = std::max(want, (halo + kHaloMax - 1) / kHaloMax);
+    return ((want + 63) / 64) * 64;
+}
+
+size_t hpsi_lds_bytes(int nx, int TY, int natoms, bool mixed)
+{
+    const size_t v = mixed ? 8 : 16;
+    size_t bytes = 2 * (size_t)(TY + 2 * kHalf) * (nx + 2 * kHalf) * v +
+                   (((size_t)natoms * sizeof(int) + 15) & ~size_t(15)) +
+                   90 * v;
+    return std::max<size_t>(bytes, 64 * sizeof(double));
+}
+
 template <class R, class InT, class TT, int MODE>
 static hipError_t go_hpsi(const HArgs &a, int ns, hipStream_t st)
 {
-    using V = typename Cplx<R>::T;
-    const int nthr = ((a.geo.nx * a.TY + 63) / 64) * 64;
-    size_t lds = (size_t)(a.TY + 2 * kHalf) * a.geo.nx * sizeof(V);
-    if (lds < 64 * sizeof(double))
-        lds = 64 * sizeof(double);
-    dim3 grid(a.ntile_y * a.nzc, ns);
+    const int nthr = hpsi_threads(a.geo.nx, a.TY);
+    const size_t lds = hpsi_lds_bytes(a.geo.nx, a.TY, a.pj.natoms,
+                                      sizeof(R) == 4);
+    dim3 grid((unsigned)(a.ntile_y * a.nzc * ns));
     hipLaunchKernelGGL((k_hpsi<R, InT, TT, MODE>), grid, dim3(nthr), lds, st,
                        a);
     return hipGetLastError();
@@ -730,21 +957,38 @@ hipError_t launch_hpsi(int mode, bool mixed, bool in_is_f64, const HArgs &a,
     return hipErrorInvalidValue;
 }
 
+int gather_chunks(int max_npts)
+{
+    return std::max(1, (max_npts + kGatherChunk - 1) / kGatherChunk);
+}
+
 hipError_t launch_gather(bool mixed, bool in_is_f64, const GArgs &a, int ns,
                          hipStream_t st)
 {
     if (ns <= 0 || a.pj.natoms <= 0)
         return hipSuccess;
-    dim3 grid(a.pj.natoms, ns);
+    GArgs b = a;
+    b.ns = ns;
+    dim3 grid(a.pj.natoms, (ns + kGatherStates - 1) / kGatherStates,
+              a.nchunk);
+    dim3 blk(64 * kGatherStates);
     if (!mixed)
-        hipLaunchKernelGGL((k_gather<double, double2>), grid, dim3(256), 0, st,
-                           a);
+        hipLaunchKernelGGL((k_gather<double, double2>), grid, blk, 0, st, b);
     else if (in_is_f64)
-        hipLaunchKernelGGL((k_gather<float, double2>), grid, dim3(256), 0, st,
-                           a);
+        hipLaunchKernelGGL((k_gather<float, double2>), grid, blk, 0, st, b);
     else
-        hipLaunchKernelGGL((k_gather<float, float2>), grid, dim3(256), 0, st,
-                           a);
+        hipLaunchKernelGGL((k_gather<float, float2>), grid, blk, 0, st, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const long total = (long)ns * a.pj.natoms * kMaxProj;
+    dim3 g2((unsigned)((total + 255) / 256));
+    if (!mixed)
+        hipLaunchKernelGGL((k_gather_finalize<double>), g2, dim3(256), 0, st,
+                           b);
+    else
+        hipLaunchKernelGGL((k_gather_finalize<float>), g2, dim3(256), 0, st,
+                           b);
     return hipGetLastError();
 }
 

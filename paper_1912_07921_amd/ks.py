@@ -73,6 +73,11 @@ EXPORTS = {
     "ks_gram": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ks_energy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                             C.POINTER(C.c_double)]),
+    "ks_set_launch": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    "ks_get_launch": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
+    "ks_profile_begin": (C.c_int, [C.c_void_p, C.c_int]),
+    "ks_profile_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
+                                 C.POINTER(C.c_long)]),
     "ks_last_error": (C.c_char_p, []),
 }
 
@@ -222,6 +227,30 @@ def ks_energy(h, psi, vion, t):
     return out.value
 
 
+def ks_set_launch(h, tile_rows, zchunk):
+    return _check(lib().ks_set_launch(h, int(tile_rows), int(zchunk)))
+
+
+def ks_get_launch(h):
+    out = (C.c_int * 4)()
+    _check(lib().ks_get_launch(h, out))
+    return dict(tile_rows=out[0], zchunk=out[1], workgroups=out[2],
+                threads=out[3])
+
+
+def ks_profile_begin(h, capacity):
+    return _check(lib().ks_profile_begin(h, int(capacity)))
+
+
+def ks_profile_end(h):
+    """{class: (total_ms, launches)} for classes hpsi, gather, reduce."""
+    ms = (C.c_double * 3)()
+    cnt = (C.c_long * 3)()
+    _check(lib().ks_profile_end(h, ms, cnt))
+    return {name: (ms[i], cnt[i])
+            for i, name in enumerate(("hpsi", "gather", "reduce"))}
+
+
 # ---------------------------------------------------------------------------
 # convenience object
 # ---------------------------------------------------------------------------
@@ -238,7 +267,12 @@ class Grid:
         self.ns = int(spec.nstates)
         self.precision = precision
         self.h, self._keep = ks_grid_create(spec, precision, stream)
+        self._alloc_ws()
+
+    def _alloc_ws(self):
+        torch = self.torch
         nbytes = ks_workspace_bytes(self.h)
+        self.ws = None
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8,
                               device=self.device)
         off = (-self.ws.data_ptr()) % 256
@@ -328,6 +362,24 @@ class Grid:
                                device=self.device)
         ks_gram(self.h, psi, out)
         return out
+
+    def set_launch(self, tile_rows=0, zchunk=0):
+        try:
+            ks_set_launch(self.h, tile_rows, zchunk)
+        except KSError as e:
+            if e.code == -2:       # workspace too small: lend a larger one
+                self._alloc_ws()
+            else:
+                raise
+
+    def get_launch(self):
+        return ks_get_launch(self.h)
+
+    def profile_begin(self, capacity=100000):
+        ks_profile_begin(self.h, capacity)
+
+    def profile_end(self):
+        return ks_profile_end(self.h)
 
     def energy(self, psi, vion, t=0.0):
         self._psi(psi)

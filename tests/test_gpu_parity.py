@@ -269,3 +269,35 @@ def test_error_paths(torch_cuda):
     with pytest.raises(ks.KSError) as e:
         gp.dipole(dev(torch, np.zeros(per.npoints)))
     assert e.value.code == -4
+
+
+def test_apply_h_independent_of_launch_shape(torch_cuda, oracle_mod):
+    """Tile height and z-chunking change only the work split: H.psi is
+    bitwise the same for every shape."""
+    torch = torch_cuda
+    spec, v, psi = W.tiny(n=(40, 27, 33), h=(0.25, 0.25, 0.25), nstates=3,
+                          natoms=3, lmax=2, rc=1.3, sigma=0.4)
+    g = grid(spec)
+    g.update_vlocal(dev(torch, v))
+    dpsi = dev(torch, psi[0])
+    ref = g.apply_h(dpsi).cpu().numpy()
+    want = oracle_mod.Oracle(spec).apply_h(v, psi[0])
+    assert rel_err(ref, want) < 1e-12
+    for ty, zc in [(1, 0), (2, 5), (3, 33), (7, 1), (12, 16), (12, 0)]:
+        g.set_launch(ty, zc)
+        got = g.apply_h(dpsi).cpu().numpy()
+        assert np.array_equal(got, ref), (ty, zc)
+
+
+def test_propagate_independent_of_launch_shape(torch_cuda, oracle_mod):
+    torch = torch_cuda
+    w = W.c1(nsteps=3)
+    outs = []
+    for ty, zc in [(0, 0), (3, 7), (16, 24)]:
+        g = grid(w.spec)
+        g.set_launch(ty, zc)
+        dpsi = dev(torch, w.psi0)
+        g.propagate_etrs(dpsi, dev(torch, w.vion), 3, w.dt)
+        outs.append(dpsi.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
