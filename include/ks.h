@@ -183,13 +183,14 @@ int ks_get_launch(const ks_grid *g, int out[4]);
 
 /* Kernel timing with HIP events on the grid's stream.  After
  * ks_profile_begin(g, capacity), every later launch of the H.psi kernel
- * (class 0), of the projector gather (class 1) and of the density /
- * reduction kernels (class 2) is bracketed by a pair of events, up to
- * `capacity` pairs.  ks_profile_end() waits for the stream, stops recording
- * and returns per class the summed kernel time (ms) and the number of
- * launches timed, in out_ms[3] and out_count[3] (host arrays). */
+ * (class 0), of the projector gather (class 1), of the density / reduction
+ * kernels (class 2) and of the projector apply (class 3) is bracketed by a
+ * pair of events, up to `capacity` pairs.  ks_profile_end() waits for the
+ * stream, stops recording and returns per class the summed kernel time (ms)
+ * and the number of launches timed, in out_ms[4] and out_count[4] (host
+ * arrays). */
 int ks_profile_begin(ks_grid *g, int capacity);
-int ks_profile_end(ks_grid *g, double out_ms[3], long out_count[3]);
+int ks_profile_end(ks_grid *g, double out_ms[4], long out_count[4]);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *ks_last_error(void);

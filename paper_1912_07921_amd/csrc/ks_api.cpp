@@ -64,6 +64,7 @@ struct ks_grid {
     ProjDev pj;
     int natoms = 0;
     long total_pts = 0;
+    long nhull = 0;
     std::vector<int> h_npts, h_nproj;
 
     // launch shape
@@ -73,7 +74,7 @@ struct ks_grid {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     struct {
-        size_t t1, t2, t3, half, npart, normpart, D, Dpart, rho, vpred,
+        size_t t1, t2, t3, half, npart, normpart, D, W, Dpart, rho, vpred,
             dpart, gpart, dotpart, xpart, total;
     } lay{};
     int ntiles_max = 64;
@@ -136,8 +137,9 @@ double solid_harm(int j, double x, double y, double z)
     }
 }
 
-// Build sphere point lists, normalised projector tables, the grid-point
-// scatter CSR, and upload them.
+// Build the sphere point lists of every atom (grid index, packed
+// coordinates, lattice shift), the projector normalisations, the hull rows
+// and the per-chunk atom lists of the hull, and upload them.
 int build_projectors(ks_grid *g, const ks_grid_desc *d)
 {
     const Geo &G = g->geo;
@@ -146,11 +148,13 @@ int build_projectors(ks_grid *g, const ks_grid_desc *d)
     g->pj.natoms = na;
     if (na == 0)
         return KS_OK;
+    if (na > 65535)
+        return fail(KS_E_UNSUPPORTED, "more than 65535 atoms");
     const int n3[3] = {G.nx, G.ny, G.nz};
     std::vector<int> nproj(na), npts(na);
-    std::vector<long> ioff(na), poff(na);
-    std::vector<int> sidx, sshift;
-    std::vector<double> ptab, EjN((size_t)na * kMaxProj, 0.0);
+    std::vector<long> ioff(na);
+    std::vector<int> sidx, sxyz, sshift;
+    std::vector<double> EjN2((size_t)na * kMaxProj, 0.0);
     std::vector<double4> apos(na);
     std::vector<double2> arad(na);
     const double h3 = G.h[0] * G.h[1] * G.h[2];
@@ -182,8 +186,7 @@ int build_projectors(ks_grid *g, const ks_grid_desc *d)
             }
         }
         ioff[a] = (long)sidx.size();
-        std::vector<double> disp;  // 3 per point
-        std::vector<int> gidx, code;
+        double norm2[kMaxProj] = {0};
         for (int iz = lo[2]; iz <= hi[2]; ++iz)
             for (int iy = lo[1]; iy <= hi[1]; ++iy)
                 for (int ix = lo[0]; ix <= hi[0]; ++ix) {
@@ -202,85 +205,124 @@ int build_projectors(ks_grid *g, const ks_grid_desc *d)
                     }
                     if (!(r2 < rc * rc))
                         continue;
-                    gidx.push_back((wr[2] * G.ny + wr[1]) * G.nx + wr[0]);
-                    int c = (w[0] & 0xff) | ((w[1] & 0xff) << 8) |
-                            ((w[2] & 0xff) << 16);
-                    code.push_back(c);
-                    disp.push_back(r[0]);
-                    disp.push_back(r[1]);
-                    disp.push_back(r[2]);
+                    sidx.push_back((wr[2] * G.ny + wr[1]) * G.nx + wr[0]);
+                    sxyz.push_back(wr[0] | (wr[1] << 10) | (wr[2] << 20));
+                    sshift.push_back((w[0] & 0xff) | ((w[1] & 0xff) << 8) |
+                                     ((w[2] & 0xff) << 16));
+                    const double win = 1.0 - r2 / (rc * rc);
+                    const double rad = std::exp(-r2 / (2.0 * sg * sg)) *
+                                       win * win;
+                    for (int j = 0; j < nproj[a]; ++j) {
+                        const double pv = solid_harm(j, r[0], r[1], r[2]) *
+                                          rad;
+                        norm2[j] += pv * pv;
+                    }
                 }
-        const int np = (int)gidx.size();
-        npts[a] = np;
-        poff[a] = (long)ptab.size();
-        ptab.resize(ptab.size() + (size_t)nproj[a] * np);
-        double *pa = ptab.data() + poff[a];
-        for (int i = 0; i < np; ++i) {
-            const double *r = &disp[3 * i];
-            double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-            double win = 1.0 - rr / (rc * rc);
-            double rad = std::exp(-rr / (2.0 * sg * sg)) * win * win;
-            for (int j = 0; j < nproj[a]; ++j)
-                pa[(size_t)j * np + i] = solid_harm(j, r[0], r[1], r[2]) * rad;
-        }
+        npts[a] = (int)(sidx.size() - ioff[a]);
         for (int j = 0; j < nproj[a]; ++j) {
-            double s = 0.0;
-            for (int i = 0; i < np; ++i)
-                s += pa[(size_t)j * np + i] * pa[(size_t)j * np + i];
-            s *= h3;
-            double f = s > 0.0 ? 1.0 / std::sqrt(s) : 0.0;
-            for (int i = 0; i < np; ++i)
-                pa[(size_t)j * np + i] *= f;
+            const double s2 = norm2[j] * h3;
+            const double nj2 = s2 > 0.0 ? 1.0 / s2 : 0.0;   // N_j^2
             const int l = j == 0 ? 0 : (j < 4 ? 1 : 2);
-            EjN[(size_t)a * kMaxProj + j] = f * h3 * d->E[3 * a + l];
+            EjN2[(size_t)a * kMaxProj + j] = nj2 * h3 * d->E[3 * a + l];
         }
-        sidx.insert(sidx.end(), gidx.begin(), gidx.end());
-        sshift.insert(sshift.end(), code.begin(), code.end());
     }
     g->total_pts = (long)sidx.size();
     g->nchunk = gather_chunks(*std::max_element(npts.begin(), npts.end()));
     g->h_npts = npts;
     g->h_nproj = nproj;
-    if (na > 4096)
-        return fail(KS_E_UNSUPPORTED, "more than 4096 atoms");
-    std::vector<float> ptabf(ptab.begin(), ptab.end());
-    int *d_nproj, *d_npts, *d_sidx, *d_sshift;
-    long *d_ioff, *d_poff;
-    double *d_ptab, *d_EjN;
-    float *d_ptabf;
+
+    // hull rows: x range covered by spheres in each (z, y) row
+    const long nrows = (long)G.nz * G.ny;
+    std::vector<int> xlo(nrows, G.nx), xhi(nrows, -1);
+    for (size_t i = 0; i < sidx.size(); ++i) {
+        const long row = sidx[i] / G.nx;
+        const int x = sidx[i] % G.nx;
+        xlo[row] = std::min(xlo[row], x);
+        xhi[row] = std::max(xhi[row], x);
+    }
+    std::vector<int4> rowinfo(nrows);
+    std::vector<int> hxyz;
+    long nhull = 0;
+    for (long row = 0; row < nrows; ++row) {
+        rowinfo[row] = make_int4(xlo[row], xhi[row], (int)nhull, 0);
+        if (xhi[row] >= xlo[row]) {
+            const int y = (int)(row % G.ny), z = (int)(row / G.ny);
+            for (int x = xlo[row]; x <= xhi[row]; ++x)
+                hxyz.push_back(x | (y << 10) | (z << 20));
+            nhull += xhi[row] - xlo[row] + 1;
+        }
+    }
+    if (nhull >= (1L << 31))
+        return fail(KS_E_UNSUPPORTED, "projector hull too large");
+    const int nhch = (int)((nhull + kHullChunk - 1) / kHullChunk);
+    std::vector<std::vector<int>> chunk_atoms(nhch);
+    for (int a = 0; a < na; ++a) {
+        int last = -1;
+        for (int i = 0; i < npts[a]; ++i) {
+            const int gg = sidx[ioff[a] + i];
+            const long row = gg / G.nx;
+            const int x = gg % G.nx;
+            const long hh = rowinfo[row].z + (x - rowinfo[row].x);
+            const int c = (int)(hh / kHullChunk);
+            if (c != last &&
+                (chunk_atoms[c].empty() || chunk_atoms[c].back() != a))
+                chunk_atoms[c].push_back(a);
+            last = c;
+        }
+    }
+    std::vector<int> hc_off(nhch + 1, 0), hc_atoms;
+    for (int c = 0; c < nhch; ++c) {
+        hc_off[c + 1] = hc_off[c] + (int)chunk_atoms[c].size();
+        hc_atoms.insert(hc_atoms.end(), chunk_atoms[c].begin(),
+                        chunk_atoms[c].end());
+    }
+    g->nhull = nhull;
+
+    int *d_nproj, *d_npts, *d_sidx, *d_sxyz, *d_sshift, *d_hxyz, *d_hc_off,
+        *d_hc_atoms;
+    long *d_ioff;
+    double *d_EjN2;
     double4 *d_apos;
     double2 *d_arad;
+    int4 *d_rowinfo;
     int rc;
     if ((rc = dev_upload(g, &d_nproj, nproj)) ||
         (rc = dev_upload(g, &d_npts, npts)) ||
         (rc = dev_upload(g, &d_ioff, ioff)) ||
-        (rc = dev_upload(g, &d_poff, poff)) ||
         (rc = dev_upload(g, &d_sidx, sidx)) ||
+        (rc = dev_upload(g, &d_sxyz, sxyz)) ||
         (rc = dev_upload(g, &d_sshift, sshift)) ||
-        (rc = dev_upload(g, &d_ptab, ptab)) ||
-        (rc = dev_upload(g, &d_ptabf, ptabf)) ||
-        (rc = dev_upload(g, &d_EjN, EjN)) ||
+        (rc = dev_upload(g, &d_EjN2, EjN2)) ||
         (rc = dev_upload(g, &d_apos, apos)) ||
-        (rc = dev_upload(g, &d_arad, arad)))
+        (rc = dev_upload(g, &d_arad, arad)) ||
+        (rc = dev_upload(g, &d_rowinfo, rowinfo)) ||
+        (rc = dev_upload(g, &d_hxyz, hxyz)) ||
+        (rc = dev_upload(g, &d_hc_off, hc_off)) ||
+        (rc = dev_upload(g, &d_hc_atoms, hc_atoms)))
         return rc;
     g->pj.nproj = d_nproj;
     g->pj.npts = d_npts;
     g->pj.ioff = d_ioff;
-    g->pj.poff = d_poff;
     g->pj.sidx = d_sidx;
+    g->pj.sxyz = d_sxyz;
     g->pj.sshift = d_sshift;
-    g->pj.ptab = d_ptab;
-    g->pj.ptabf = d_ptabf;
-    g->pj.EjN = d_EjN;
+    g->pj.EjN2 = d_EjN2;
     g->pj.apos = d_apos;
     g->pj.arad = d_arad;
+    g->pj.rowinfo = d_rowinfo;
+    g->pj.nhull = (int)nhull;
+    g->pj.hxyz = d_hxyz;
+    g->pj.nhchunk = nhch;
+    g->pj.hc_off = d_hc_off;
+    g->pj.hc_atoms = d_hc_atoms;
     return KS_OK;
 }
 
-// LDS bytes of one H.psi workgroup for tile height TY.
-size_t lds_for(const ks_grid *g, int TY)
+// LDS bytes of one H.psi workgroup.
+size_t lds_for(const ks_grid *g, int TY, int zchunk)
 {
-    return hpsi_lds_bytes(g->geo.nx, TY, g->natoms, g->mixed);
+    return hpsi_lds_bytes(g->geo.nx, TY, g->natoms > 0 ? zchunk : 0,
+                          g->mixed);
 }
 
 // Launch shape: rows per tile TY (a workgroup has about 512 threads) and
@@ -290,29 +332,45 @@ int set_tiles(ks_grid *g, int TY, int zchunk)
 {
     const Geo &G = g->geo;
     if (TY <= 0) {
+        // about 512 threads per workgroup: the 8 halo rows are then at most
+        // twice the tile's own rows
         TY = std::max(1, std::min(G.ny, 512 / G.nx));
-        while (TY > 1 && lds_for(g, TY) > kLdsBudget)
+        while (TY > 1 && lds_for(g, TY, G.nz) > kLdsBudget)
             --TY;
     }
     if (TY > G.ny || G.nx * TY > 512)
         return fail(KS_E_ARG, "tile height %d invalid for nx=%d ny=%d", TY,
                     G.nx, G.ny);
-    if (lds_for(g, TY) > kLdsBudget)
-        return fail(KS_E_UNSUPPORTED, "tile needs %zu bytes of LDS",
-                    lds_for(g, TY));
-    g->TY = TY;
-    g->ntile_y = (G.ny + TY - 1) / TY;
+    const int ntile_y = (G.ny + TY - 1) / TY;
     if (zchunk <= 0) {
-        const long per_state = g->ntile_y;
+        const long per_state = ntile_y;
         int nzc = (int)std::max<long>(1, 1024 / std::max<long>(1, per_state *
                                                                    g->stot));
         nzc = std::min(nzc, std::max(1, G.nz / 16));
         zchunk = (G.nz + nzc - 1) / nzc;
+        while (zchunk > 1 && lds_for(g, TY, zchunk) > kLdsBudget)
+            zchunk = (zchunk + 1) / 2;
     }
-    g->zchunk = std::min(zchunk, G.nz);
-    g->nzc = (G.nz + g->zchunk - 1) / g->zchunk;
-    if ((long)g->ntile_y * g->nzc * g->stot >= (1L << 31))
+    zchunk = std::min(zchunk, G.nz);
+    if (lds_for(g, TY, zchunk) > kLdsBudget)
+        return fail(KS_E_UNSUPPORTED, "tile needs %zu bytes of LDS",
+                    lds_for(g, TY, zchunk));
+    {
+        // the kernel holds at most 16 halo loads per thread and plane
+        const int nthr = hpsi_threads(G.nx, TY);
+        const int dyn = 2 * kHalf * G.nx +
+                        (G.per[0] ? 2 * kHalf * (TY + 2 * kHalf) : 0);
+        if ((dyn + nthr - 1) / nthr > 16)
+            return fail(KS_E_UNSUPPORTED, "tile height %d too small for "
+                        "nx=%d", TY, G.nx);
+    }
+    const int nzc = (G.nz + zchunk - 1) / zchunk;
+    if ((long)ntile_y * nzc * g->stot >= (1L << 31))
         return fail(KS_E_UNSUPPORTED, "too many workgroups");
+    g->TY = TY;
+    g->ntile_y = ntile_y;
+    g->zchunk = zchunk;
+    g->nzc = nzc;
     return KS_OK;
 }
 
@@ -335,6 +393,7 @@ void layout(ks_grid *g)
     g->lay.npart = take(S * N * 8);
     g->lay.normpart = take(S * g->ntiles_max * 8);
     g->lay.D = take(S * std::max(1, g->natoms) * kMaxProj * 16);
+    g->lay.W = take(S * std::max<size_t>(1, g->nhull) * 16);
     g->lay.Dpart = take(S * std::max(1, g->natoms) * g->nchunk * kMaxProj *
                         16);
     g->lay.rho = take(N * 8);
@@ -351,7 +410,8 @@ template <class T> T *wsp(ks_grid *g, size_t off)
     return reinterpret_cast<T *>(g->ws + off);
 }
 
-// Event pair around one launch of class c (0 H.psi, 1 gather, 2 reductions).
+// Event pair around one launch of class c (0 H.psi, 1 projector gather,
+// 2 reductions, 3 projector apply).
 struct Timed {
     ks_grid *g;
     int slot = -1;
@@ -390,7 +450,12 @@ HArgs base_hargs(ks_grid *g)
     a.kph = g->d_kph;
     a.nstates = g->ns;
     a.wocc = g->d_wocc;
-    a.pj = g->pj;
+    if (g->natoms > 0 && g->nhull > 0) {
+        a.rowinfo = g->pj.rowinfo;
+        a.nhull = (int)g->nhull;
+        if (g->ws)
+            a.W = g->ws + g->lay.W;
+    }
     a.TY = g->TY;
     a.zchunk = g->zchunk;
     a.ntile_y = g->ntile_y;
@@ -406,8 +471,10 @@ GArgs base_gargs(ks_grid *g)
     a.nstates = g->ns;
     a.pj = g->pj;
     a.nchunk = g->nchunk;
-    if (g->ws)
+    if (g->ws) {
         a.Dpart = g->ws + g->lay.Dpart;
+        a.W = g->ws + g->lay.W;
+    }
     return a;
 }
 
@@ -436,7 +503,6 @@ int taylor_exponential(ks_grid *g, const double2 *in, double2 *out,
     a.A[1] = A[1];
     a.A[2] = A[2];
     a.a2half = 0.5 * (A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
-    a.D = D;
     GArgs ga = base_gargs(g);
     ga.D = D;
     const void *cur = in;
@@ -444,8 +510,12 @@ int taylor_exponential(ks_grid *g, const double2 *in, double2 *out,
         const bool f64 = (j == 1) || !mx;
         ga.in = cur;
         if (g->natoms > 0) {
-            Timed tm(g, 1);
-            KS_HIP(launch_gather(mx, f64, ga, S, g->stream));
+            {
+                Timed tm(g, 1);
+                KS_HIP(launch_gather(mx, f64, ga, S, g->stream));
+            }
+            Timed tm(g, 3);
+            KS_HIP(launch_kbapply(mx, ga, S, g->stream));
         }
         a.in = cur;
         a.cre = 0.0;
@@ -648,6 +718,7 @@ int ks_apply_h(ks_grid *g, const void *d_psi, void *d_hpsi, int k, int s0,
     if (g->natoms > 0) {
         Timed tm(g, 1);
         KS_HIP(launch_gather(g->mixed, true, ga, ns, g->stream));
+        KS_HIP(launch_kbapply(g->mixed, ga, ns, g->stream));
     }
     HArgs a = base_hargs(g);
     a.in = d_psi;
@@ -657,7 +728,7 @@ int ks_apply_h(ks_grid *g, const void *d_psi, void *d_hpsi, int k, int s0,
     a.A[1] = A[1];
     a.A[2] = A[2];
     a.a2half = 0.5 * (A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
-    a.D = D;
+
     a.sg0 = k * g->ns + s0;
     {
         Timed tm(g, 0);
@@ -770,6 +841,7 @@ int ks_energy(ks_grid *g, const void *d_psi, const double *d_vion, double t,
         ga.D = D;
         ga.sg0 = k * g->ns;
         KS_HIP(launch_gather(false, true, ga, g->ns, g->stream));
+        KS_HIP(launch_kbapply(false, ga, g->ns, g->stream));
         HArgs a = base_hargs(g);
         a.in = ga.in;
         a.out = hp + (size_t)k * g->ns * N;
@@ -778,7 +850,7 @@ int ks_energy(ks_grid *g, const void *d_psi, const double *d_vion, double t,
         a.A[1] = A[1];
         a.A[2] = A[2];
         a.a2half = 0.5 * (A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
-        a.D = D;
+
         a.sg0 = k * g->ns;
         KS_HIP(launch_hpsi(kApply, false, true, a, g->ns, g->stream));
     }
@@ -876,13 +948,13 @@ int ks_profile_begin(ks_grid *g, int capacity)
     return KS_OK;
 }
 
-int ks_profile_end(ks_grid *g, double out_ms[3], long out_count[3])
+int ks_profile_end(ks_grid *g, double out_ms[4], long out_count[4])
 {
     if (!g || !out_ms || !out_count)
         return fail(KS_E_ARG, "NULL argument");
     g->profiling = false;
     KS_HIP(hipStreamSynchronize(g->stream));
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 4; ++c) {
         out_ms[c] = 0.0;
         out_count[c] = 0;
     }

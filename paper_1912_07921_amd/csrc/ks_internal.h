@@ -29,26 +29,38 @@ struct Geo {
     double h[3];
 };
 
-// Projector tables on the device.  Sphere points of atom a occupy
-// [ioff[a], ioff[a] + npts[a]) of sidx/sshift (sshift: the lattice shift
-// T that brings the point into the sphere, three signed bytes); the
-// normalised table is ptab[poff[a] + j * npts[a] + pt].  The scatter
-// evaluates projectors from apos (x, y, z, rc^2) and arad
-// (1 / (2 sigma^2), 1 / rc^2); EjN[a][j] = N_j h^3 E_{a,l(j)}.
+// Projector data on the device.
+//  - Sphere points of atom a occupy [ioff[a], ioff[a] + npts[a]) of sidx
+//    (grid index), sxyz (x | y << 10 | z << 20) and sshift (lattice shift T
+//    that brings the point into the sphere, three signed bytes).
+//  - apos[a] = (x, y, z, rc^2), arad[a] = (1 / (2 sigma^2), 1 / rc^2); the
+//    projector values are evaluated from these (p_j = N_j P_j(r) rad(r)).
+//  - EjN2[a][j] = N_j^2 h^3 E_{a,l(j)} (N_j: grid normalisation of p_j).
+//  - Hull: for grid row (z, y), rowinfo = (x_lo, x_hi, base, 0) spans the x
+//    range that spheres cover (x_lo > x_hi: none); hull point
+//    h = base + x - x_lo.  hxyz[h] packs its coordinates.  Hull chunks of 64
+//    points list the atoms whose sphere meets them in
+//    hc_atoms[hc_off[c] .. hc_off[c+1]).
 struct ProjDev {
     int natoms = 0;
     const int *nproj = nullptr;
     const int *npts = nullptr;
     const long *ioff = nullptr;
-    const long *poff = nullptr;
     const int *sidx = nullptr;
+    const int *sxyz = nullptr;
     const int *sshift = nullptr;
-    const double *ptab = nullptr;
-    const float *ptabf = nullptr;
-    const double *EjN = nullptr;
+    const double *EjN2 = nullptr;
     const double4 *apos = nullptr;
     const double2 *arad = nullptr;
+    const int4 *rowinfo = nullptr;
+    int nhull = 0;
+    const int *hxyz = nullptr;
+    int nhchunk = 0;
+    const int *hc_off = nullptr;
+    const int *hc_atoms = nullptr;
 };
+
+constexpr int kHullChunk = 64;
 
 struct HArgs {
     Geo geo;
@@ -67,8 +79,9 @@ struct HArgs {
     const double *wocc = nullptr;  // [nk*nstates] w_k f_s
     double *npart = nullptr;       // [ns][N] density partials
     double *normpart = nullptr;    // [ns][ntiles]
-    ProjDev pj;
-    const void *D = nullptr;       // [ns][natoms][9] projector coefficients
+    const int4 *rowinfo = nullptr; // hull rows (null: no projectors)
+    const void *W = nullptr;       // [ns][nhull] V_NL in on the hull
+    int nhull = 0;
     int TY = 1, zchunk = 1, ntile_y = 1, nzc = 1;
 };
 
@@ -78,13 +91,14 @@ constexpr size_t kLdsBudget = 65536;
 struct GArgs {
     Geo geo;
     const void *in = nullptr;
-    void *D = nullptr;
+    void *D = nullptr;             // [ns][natoms][9] coefficients
+    void *W = nullptr;             // [ns][nhull] (apply stage)
     const double2 *kph = nullptr;
     int nstates = 1;
     int sg0 = 0;
     int ns = 0;                    // states in this launch
     void *Dpart = nullptr;         // [ns][natoms][nchunk][9] chunk sums
-    int nchunk = 1;                // chunks of the largest sphere
+    int nchunk = 1;                // gather chunks of the largest sphere
     ProjDev pj;
 };
 
@@ -103,13 +117,17 @@ struct DArgs {
 
 // Launch shape of the H.psi kernel.
 int hpsi_threads(int nx, int TY);
-size_t hpsi_lds_bytes(int nx, int TY, int natoms, bool mixed);
+int hpsi_halo_per_thread(const Geo &g, int TY, int nthr);
+size_t hpsi_lds_bytes(int nx, int TY, int zchunk, bool mixed);
 
 // Launchers (ks_kernels.hip).  All asynchronous on `st`.
 hipError_t launch_hpsi(int mode, bool mixed, bool in_is_f64, const HArgs &a,
                        int ns, hipStream_t st);
+// KB projectors: D = coefficients of `in` (gather), then W = V_NL in on
+// the hull (apply).  Both no-ops without atoms.
 hipError_t launch_gather(bool mixed, bool in_is_f64, const GArgs &a, int ns,
                          hipStream_t st);
+hipError_t launch_kbapply(bool mixed, const GArgs &a, int ns, hipStream_t st);
 int gather_chunks(int max_npts);
 int density_blocks(long N);
 hipError_t launch_density(const DArgs &a, hipStream_t st);

@@ -188,31 +188,27 @@ __device__ __forceinline__ int xcd_remap(int L, int nblk)
 
 // ---------------------------------------------------------------------------
 // H.psi with a fused epilogue.  R: arithmetic precision; InT: storage type of
-// the input states; TT: storage type of t-terms (t1, t2, term outputs).
+// the input states; TT: storage type of t-terms (t1, t2, term outputs);
+// GRAD: the velocity-gauge term -i A.grad is present; HM: halo loads per
+// thread and plane.
 //
 // LDS holds the current xy plane of the tile padded by 4 rows above and below
-// and 4 columns left and right, filled at load time with the neighbours'
-// values, zeros (zero boundary) or Bloch-wrapped values; the stencil then
-// reads its x and y neighbours without branches.  The z neighbours come from
-// a per-thread register queue.  Per z-plane: one barrier; two plane buffers
-// alternate, and the loads of plane z+1 (halo) and z+5 (own column) are in
-// flight while plane z is computed.
-//
-// The KB scatter evaluates the projectors at the point from the atom
-// geometry (p_j = N_j P_j(r) exp(-r^2 / 2 sigma^2) (1 - r^2/rc^2)^2, the
-// normalisation N_j folded into the coefficients D by the gather), for the
-// atoms whose sphere meets the workgroup's y-slab (listed once per
-// workgroup, in atom order) and the current plane.
+// and 4 columns left and right: the neighbours' values, zeros (zero
+// boundary; written once) or Bloch-wrapped values.  The stencil reads its x
+// and y neighbours there without branches; the z neighbours come from a
+// per-thread register queue.  Per z-plane: one barrier, two plane buffers
+// alternating.  Every stream is fetched two planes ahead of its use: the
+// halo of plane z+2, the own column of plane z+6, the potential and the KB
+// term of plane z+2 are in flight while plane z is computed.  The KB term
+// V_NL in is precomputed on the hull rows (k_kbapply) and added with one
+// coalesced read.
 // ---------------------------------------------------------------------------
-constexpr int kHaloMax = 6;   // halo elements per thread
-
-template <class R, class InT, class TT, int MODE>
+template <class R, class InT, class TT, int MODE, bool GRAD, int HM>
 __global__ __launch_bounds__(512) void k_hpsi(HArgs a)
 {
     using V = typename Cplx<R>::T;
     extern __shared__ double2 smem_d2[];
     unsigned char *smem_raw = reinterpret_cast<unsigned char *>(smem_d2);
-    __shared__ int s_ncand;
 
     const int nx = a.geo.nx, ny = a.geo.ny, nz = a.geo.nz;
     const int P = nx * ny;
@@ -243,49 +239,19 @@ __global__ __launch_bounds__(512) void k_hpsi(HArgs a)
     const int own = (yl + kHalf) * RS + x + kHalf;  // LDS slot of the point
     const int po = y * nx + x;                      // offset within a plane
 
-    const int natoms = a.pj.natoms;
     const int plane = (TY + 2 * kHalf) * RS;
     V *buf0 = reinterpret_cast<V *>(smem_raw);
     V *buf1 = buf0 + plane;
-    int *scand = reinterpret_cast<int *>(buf1 + plane);
+    V *sPh = buf1 + plane;        // x/y wrap phases, 81 entries
+    V *sPz = sPh + 81;            // z wrap phases, 9 entries
+    int4 *sRow = reinterpret_cast<int4 *>(sPz + 9);   // hull rows of tile
 
     const InT *in = reinterpret_cast<const InT *>(a.in) + (size_t)sl * N;
-
-    // ---- projector coefficients (read through the scalar cache: every
-    // lane of a wave uses the same atom) and candidate atoms of this y-slab
-    const V *Dg = reinterpret_cast<const V *>(a.D) +
-                  (size_t)sl * natoms * kMaxProj;
-    if (tid == 0) {
-        int c = 0;
-        if (natoms > 0) {
-            const double Ly = ny * a.geo.h[1];
-            const double ylo = axis_coord(ny, a.geo.h[1], pery, y0);
-            const double yhi = axis_coord(ny, a.geo.h[1], pery,
-                                          y0 + rows - 1);
-            for (int at = 0; at < natoms; ++at) {
-                const double4 ap = a.pj.apos[at];
-                const double rc = sqrt(ap.w);
-                double best = 1e300;
-                for (int im = -1; im <= 1; ++im) {
-                    if (im && !pery)
-                        continue;
-                    const double Y = ap.y + im * Ly;
-                    const double d = Y < ylo ? ylo - Y : (Y > yhi ? Y - yhi
-                                                                  : 0.0);
-                    best = fmin(best, d);
-                }
-                if (best < rc)
-                    scand[c++] = at;
-            }
-        }
-        s_ncand = c;
-    }
+    const bool proj = a.rowinfo != nullptr;
+    const V *Wst = reinterpret_cast<const V *>(a.W) + (size_t)sl * a.nhull;
 
     // ---- Bloch phases of x/y wraps by -4..4 cells: sPh[(wy+4)*9 + wx+4],
-    // and of z wraps: sPz[wz+4] ----
-    V *sPh = reinterpret_cast<V *>(reinterpret_cast<unsigned char *>(scand) +
-                                   ((natoms * sizeof(int) + 15) & ~15));
-    V *sPz = sPh + 81;
+    // of z wraps: sPz[wz+4]; hull rows of this tile: sRow[(z-z0)*TY + yl] ----
     for (int t = tid; t < 81 + 9; t += nthr) {
         V ph;
         if (t < 81) {
@@ -299,66 +265,80 @@ __global__ __launch_bounds__(512) void k_hpsi(HArgs a)
             const int wz = t - 81 - 4;
             ph = wz ? phase_pow<V>(kph, 2, wz) : cmk<V>(1.0, 0.0);
         }
-        sPh[t] = ph;   // sPz follows sPh
+        sPh[t] = ph;
     }
+    if (proj)
+        for (int t = tid; t < (z1 - z0) * TY; t += nthr) {
+            const int zz = z0 + t / TY, r = t % TY;
+            sRow[t] = r < rows ? a.rowinfo[zz * ny + y0 + r]
+                               : make_int4(1, 0, 0, 0);
+        }
 
-    // ---- halo elements of this thread: plane offset (-1: zero, -2: none)
-    // and packed (LDS slot, phase id; id 40 is no wrap) ----
-    const int nyh = 2 * kHalf * nx;                 // y-halo rows
-    const int nxh = 2 * kHalf * (rows + 2 * kHalf); // x-halo columns
-    int hoff[kHaloMax], hpk[kHaloMax];
+    // ---- halo of the padded plane: 8 rows of nx and 8 columns of rows+8.
+    // Both buffers start zeroed, which holds every entry outside a
+    // zero-boundary axis for all planes.  The other ("dynamic") entries are
+    // loaded per plane: the in-grid (or wrapped) halo rows, and on a
+    // periodic x axis the wrapped columns of every row with content.
+    // Dynamic entry d goes to this thread when d = tid + i * nthr, i < HM.
+    // hoff: offset within a plane (-1: none); hpk: LDS slot | phase id << 20
+    // (id 40: no wrap) ----
+    for (int t = tid; t < 2 * plane; t += nthr)
+        buf0[t] = czero<V>();
+    const int u0 = pery ? 0 : max(0, kHalf - y0);   // first dynamic top row
+    const int nup = kHalf - u0;
+    const int nlow = pery ? kHalf : max(0, min(kHalf, ny - (y0 + rows)));
+    const int ndy = (nup + nlow) * nx;
+    const int r_lo = u0, r_hi = rows + kHalf + nlow;
+    const int ndyn = ndy + (perx ? (r_hi - r_lo) * 2 * kHalf : 0);
+    int hoff[HM], hpk[HM];
 #pragma unroll
-    for (int i = 0; i < kHaloMax; ++i) {
-        const int e = tid + i * nthr;
-        hoff[i] = -2;
+    for (int i = 0; i < HM; ++i) {
+        const int d = tid + i * nthr;
+        hoff[i] = -1;
         hpk[i] = 0;
-        int ys, xs, slot;
-        if (e < nyh) {
-            const int hr = e / nx, hx = e - hr * nx;
-            const int r = hr < kHalf ? hr : rows + hr;   // LDS row
-            ys = y0 - kHalf + r;
+        if (d >= ndyn)
+            continue;
+        int r, xs, slot;
+        if (d < ndy) {
+            int hx;
+            if (d < nup * nx) {
+                r = u0 + d / nx;
+                hx = d - (d / nx) * nx;
+            } else {
+                const int d1 = d - nup * nx;
+                r = rows + kHalf + d1 / nx;
+                hx = d1 - (d1 / nx) * nx;
+            }
             xs = hx;
             slot = r * RS + hx + kHalf;
-        } else if (e < nyh + nxh) {
-            const int e2 = e - nyh;
-            const int r = e2 / (2 * kHalf), cc = e2 - r * (2 * kHalf);
-            ys = y0 - kHalf + r;
+        } else {
+            const int d2 = d - ndy;
+            const int cc = d2 % (2 * kHalf);
+            r = r_lo + d2 / (2 * kHalf);
             xs = cc < kHalf ? cc - kHalf : nx + cc - kHalf;
             slot = r * RS + (cc < kHalf ? cc : nx + cc);
-        } else {
-            continue;
         }
+        int ys = y0 - kHalf + r;
         int wy = 0, wx = 0;
-        bool zero = false;
         if (ys < 0 || ys >= ny) {
-            if (pery) {
-                wy = floordiv(ys, ny);
-                ys -= wy * ny;
-            } else {
-                zero = true;
-            }
+            wy = floordiv(ys, ny);
+            ys -= wy * ny;
         }
         if (xs < 0 || xs >= nx) {
-            if (perx) {
-                wx = floordiv(xs, nx);
-                xs -= wx * nx;
-            } else {
-                zero = true;
-            }
+            wx = floordiv(xs, nx);
+            xs -= wx * nx;
         }
-        hoff[i] = zero ? -1 : ys * nx + xs;
+        hoff[i] = ys * nx + xs;
         hpk[i] = slot | (((wy + 4) * 9 + wx + 4) << 20);
     }
+    __syncthreads();   // zeroed buffers, phase tables and hull rows ready
 
-    // halo element i of plane zq (in range)
+    // halo entry i of plane zq (in range)
     auto halo_val = [&](int i, int zq) -> V {
-        V v = czero<V>();
-        if (hoff[i] >= 0) {
-            v = ldc<R>(in, (long)zq * P + hoff[i]);
-            const int pid = hpk[i] >> 20;
-            if (pid != 40)
-                v = cmul(v, sPh[pid]);
-        }
+        V v = ldc<R>(in, (long)zq * P + hoff[i]);
+        const int pid = hpk[i] >> 20;
+        if (pid != 40)
+            v = cmul(v, sPh[pid]);
         return v;
     };
     // own column value of plane zq (any integer)
@@ -371,9 +351,21 @@ __global__ __launch_bounds__(512) void k_hpsi(HArgs a)
         return cmul(ldc<R>(in, (long)(zq - wz * nz) * P + po),
                     sPz[wz + 4]);
     };
-    __syncthreads();   // phase tables, candidate list and D are in LDS
+    // projector term at this point of plane zq (z0 <= zq < z1)
+    auto kb_val = [&](int zq) -> V {
+        V v = czero<V>();
+        if (proj && act) {
+            const int4 ri = sRow[(zq - z0) * TY + yl];
+            if (x >= ri.x && x <= ri.y)
+                v = Wst[ri.z + x - ri.x];
+        }
+        return v;
+    };
+    auto v_val = [&](int zq) -> double {
+        return act ? a.v[(long)zq * P + po] : 0.0;
+    };
 
-    // ---- prologue: z-column for planes z0-4 .. z0+4, plane z0 -> buf0 ----
+    // ---- prologue ----
     V q[2 * kHalf + 1];
 #pragma unroll
     for (int m = 0; m <= 2 * kHalf; ++m)
@@ -381,9 +373,20 @@ __global__ __launch_bounds__(512) void k_hpsi(HArgs a)
     if (act)
         buf0[own] = q[kHalf];
 #pragma unroll
-    for (int i = 0; i < kHaloMax; ++i)
-        if (hoff[i] >= -1)
+    for (int i = 0; i < HM; ++i)
+        if (hoff[i] >= 0)
             buf0[hpk[i] & 0xfffff] = halo_val(i, z0);
+    // streams one and two planes ahead
+    V hvA[HM];
+#pragma unroll
+    for (int i = 0; i < HM; ++i)
+        hvA[i] = (z0 + 1 < z1 && hoff[i] >= 0) ? halo_val(i, z0 + 1)
+                                               : czero<V>();
+    V nqA = (z0 + 1 < z1 && act) ? col_val(z0 + kHalf + 1) : czero<V>();
+    V kb = kb_val(z0);
+    V kbA = z0 + 1 < z1 ? kb_val(z0 + 1) : czero<V>();
+    double vc = v_val(z0);
+    double vA = z0 + 1 < z1 ? v_val(z0 + 1) : 0.0;
 
     R LC[5], GD[5];
 #pragma unroll
@@ -395,26 +398,25 @@ __global__ __launch_bounds__(512) void k_hpsi(HArgs a)
     const R ih2y = (R)(1.0 / (a.geo.h[1] * a.geo.h[1]));
     const R ih2z = (R)(1.0 / (a.geo.h[2] * a.geo.h[2]));
     const R c0sum = LC[0] * (ih2x + ih2y + ih2z);
-    const bool has_A = (a.A[0] != 0.0) || (a.A[1] != 0.0) || (a.A[2] != 0.0);
     const R Ax = (R)(a.A[0] / a.geo.h[0]), Ay = (R)(a.A[1] / a.geo.h[1]),
             Az = (R)(a.A[2] / a.geo.h[2]);
     const V cs = cmk<V>(a.cre, a.cim);
-    const double hx = a.geo.h[0], hy = a.geo.h[1], hz = a.geo.h[2];
-    const double Lx = nx * hx, Ly = ny * hy, Lz = nz * hz;
-    const double xcrd = axis_coord(nx, hx, perx, x);
-    const double ycrd = axis_coord(ny, hy, pery, y);
     const double w_occ = (MODE == kFinal || MODE == kFinalPred)
                              ? a.wocc[sg] : 0.0;
     double nrm = 0.0;
     V *cur = buf0, *nxt = buf1;
     for (int z = z0; z < z1; ++z) {
-        const bool more = z + 1 < z1;
-        // loads for the next plane, in flight during this plane's compute
-        V hv[kHaloMax];
+        const bool more2 = z + 2 < z1;
+        // two planes ahead: in flight during this plane and the next one
+        V hvB[HM];
 #pragma unroll
-        for (int i = 0; i < kHaloMax; ++i)
-            hv[i] = more ? halo_val(i, z + 1) : czero<V>();
-        const V nq = (more && act) ? col_val(z + kHalf + 1) : czero<V>();
+        for (int i = 0; i < HM; ++i)
+            hvB[i] = (more2 && hoff[i] >= 0) ? halo_val(i, z + 2)
+                                             : czero<V>();
+        const V nqB = (z + 1 < z1 && act) ? col_val(z + kHalf + 2)
+                                          : czero<V>();
+        const V kbB = more2 ? kb_val(z + 2) : czero<V>();
+        const double vB = more2 ? v_val(z + 2) : 0.0;
         __syncthreads();
         if (act) {
             const V c = q[kHalf];
@@ -429,7 +431,7 @@ __global__ __launch_bounds__(512) void k_hpsi(HArgs a)
                 sx = cadd(sx, cscale(cadd(xp, xn), LC[m]));
                 sy = cadd(sy, cscale(cadd(yp, yn), LC[m]));
                 sz = cadd(sz, cscale(cadd(zp, zn), LC[m]));
-                if (has_A) {
+                if constexpr (GRAD) {
                     gx = cadd(gx, cscale(csub(xp, xn), GD[m]));
                     gy = cadd(gy, cscale(csub(yp, yn), GD[m]));
                     gz = cadd(gz, cscale(csub(zp, zn), GD[m]));
@@ -439,72 +441,16 @@ __global__ __launch_bounds__(512) void k_hpsi(HArgs a)
             V lap = cadd(cadd(cscale(sx, ih2x), cscale(sy, ih2y)),
                          cscale(sz, ih2z));
             lap = cadd(lap, cscale(c, c0sum));
-            const R vv = (R)(a.v[g] + a.a2half);
+            const R vv = (R)(vc + a.a2half);
             V hp = cadd(cscale(lap, (R)-0.5), cscale(c, vv));
-            if (has_A) {
+            if constexpr (GRAD) {
                 // -i A.grad
                 const V gr = cadd(cadd(cscale(gx, Ax), cscale(gy, Ay)),
                                   cscale(gz, Az));
                 hp.x += gr.y;
                 hp.y -= gr.x;
             }
-            const int ncand = __builtin_amdgcn_readfirstlane(s_ncand);
-            if (ncand > 0) {
-                const double zcrd = axis_coord(nz, hz, perz, z);
-                for (int ci = 0; ci < ncand; ++ci) {
-                    const int at = __builtin_amdgcn_readfirstlane(scand[ci]);
-                    const double4 ap = a.pj.apos[at];
-                    double dz = zcrd - ap.z;
-                    int mz = 0;
-                    if (perz) {
-                        mz = (int)rint(dz / Lz);
-                        dz -= mz * Lz;
-                    }
-                    if (!(dz * dz < ap.w))
-                        continue;
-                    double dx = xcrd - ap.x, dy = ycrd - ap.y;
-                    int mx = 0, my = 0;
-                    if (perx) {
-                        mx = (int)rint(dx / Lx);
-                        dx -= mx * Lx;
-                    }
-                    if (pery) {
-                        my = (int)rint(dy / Ly);
-                        dy -= my * Ly;
-                    }
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    if (!(r2 < ap.w))
-                        continue;
-                    const double2 ar = a.pj.arad[at];   // 1/(2 s^2), 1/rc^2
-                    const double wv = 1.0 - r2 * ar.y;
-                    const R rad = (R)(exp(-r2 * ar.x) * wv * wv);
-                    const int np = a.pj.nproj[at];
-                    const V *Da = Dg + at * kMaxProj;
-                    const R X = (R)dx, Y = (R)dy, Z = (R)dz;
-                    V acc = Da[0];
-                    if (np > 1) {
-                        acc = cadd(acc, cscale(Da[1], X));
-                        acc = cadd(acc, cscale(Da[2], Y));
-                        acc = cadd(acc, cscale(Da[3], Z));
-                    }
-                    if (np > 4) {
-                        acc = cadd(acc, cscale(Da[4], X * Y));
-                        acc = cadd(acc, cscale(Da[5], Y * Z));
-                        acc = cadd(acc, cscale(Da[6], Z * X));
-                        acc = cadd(acc, cscale(Da[7], X * X - Y * Y));
-                        acc = cadd(acc, cscale(Da[8], (R)3 * Z * Z -
-                                                          (X * X + Y * Y +
-                                                           Z * Z)));
-                    }
-                    acc = cscale(acc, rad);
-                    if (mx | my | mz) {
-                        acc = cmul(acc, sPh[(my + 4) * 9 + mx + 4]);
-                        if (mz)
-                            acc = cmul(acc, sPz[mz + 4]);
-                    }
-                    hp = cadd(hp, acc);
-                }
-            }
+            hp = cadd(hp, kb);
             if constexpr (MODE == kApply) {
                 double2 o;
                 o.x = hp.x;
@@ -547,18 +493,26 @@ __global__ __launch_bounds__(512) void k_hpsi(HArgs a)
         }
         // plane z+1 into the other buffer (free: its last readers passed
         // this iteration's barrier)
-        if (more) {
+        if (z + 1 < z1) {
             if (act)
                 nxt[own] = q[kHalf + 1];
 #pragma unroll
-            for (int i = 0; i < kHaloMax; ++i)
-                if (hoff[i] >= -1)
-                    nxt[hpk[i] & 0xfffff] = hv[i];
+            for (int i = 0; i < HM; ++i)
+                if (hoff[i] >= 0)
+                    nxt[hpk[i] & 0xfffff] = hvA[i];
         }
 #pragma unroll
         for (int m = 0; m < 2 * kHalf; ++m)
             q[m] = q[m + 1];
-        q[2 * kHalf] = nq;
+        q[2 * kHalf] = nqA;
+        nqA = nqB;
+#pragma unroll
+        for (int i = 0; i < HM; ++i)
+            hvA[i] = hvB[i];
+        kb = kbA;
+        kbA = kbB;
+        vc = vA;
+        vA = vB;
         V *t = cur;
         cur = nxt;
         nxt = t;
@@ -575,69 +529,117 @@ __global__ __launch_bounds__(512) void k_hpsi(HArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// KB projector gather: D[s][a][j] = N_j h^3 E_{a,l(j)} sum_pt p~_j(pt) in_s(pt)
-// (N_j: the projector normalisation, folded in for the scatter).
-// Stage 1: a workgroup takes one atom, one chunk of kGatherChunk sphere points
-// and kGatherStates states, one wavefront per state (the states share the
-// table reads), and writes a partial sum per chunk.  Stage 2 adds the chunks
-// in order.  Both stages reduce in a fixed order (deterministic).
+// KB projectors.  p_j(r) = N_j P_j(r) rad(r) with the real solid harmonics
+// P = (1; x, y, z; xy, yz, zx, x^2 - y^2, 3z^2 - r^2) and
+// rad = exp(-r^2 / (2 sigma^2)) (1 - r^2 / rc^2)^2, evaluated here without
+// N_j (which the coefficients carry).
 // ---------------------------------------------------------------------------
-constexpr int kGatherStates = 4;
-constexpr int kGatherChunk = 1024;
+template <class R>
+__device__ __forceinline__ void proj_shape(double dx, double dy, double dz,
+                                           double r2, double2 ar, int np,
+                                           R p[kMaxProj])
+{
+    const double wv = 1.0 - r2 * ar.y;
+    const R rad = (R)(exp(-r2 * ar.x) * wv * wv);
+    const R X = (R)dx, Y = (R)dy, Z = (R)dz;
+    p[0] = rad;
+    p[1] = rad * X;
+    p[2] = rad * Y;
+    p[3] = rad * Z;
+    p[4] = rad * X * Y;
+    p[5] = rad * Y * Z;
+    p[6] = rad * Z * X;
+    p[7] = rad * (X * X - Y * Y);
+    p[8] = rad * ((R)3 * Z * Z - (X * X + Y * Y + Z * Z));
+    for (int j = np; j < kMaxProj; ++j)
+        p[j] = 0;
+}
+
+// Stage 1 of the gather: S_j = sum_pt P_j(r) rad(r) exp(i k.T) in(pt) over
+// chunks of kGatherChunk sphere points.  A workgroup takes one atom, one
+// chunk and 16 states: wavefront w handles 4 states, each lane a point, so
+// the projector shape is evaluated once per point and wavefront.
+constexpr int kGatherChunk = 256;
+constexpr int kGatherSPW = 4;             // states per wavefront
+constexpr int kGatherStates = 4 * kGatherSPW;
 
 template <class R, class InT>
-__global__ __launch_bounds__(64 * kGatherStates) void k_gather(GArgs a)
+__global__ __launch_bounds__(256) void k_gather(GArgs a)
 {
     using V = typename Cplx<R>::T;
     const int at = blockIdx.x;
     const int ch = blockIdx.z;
     const int lane = threadIdx.x & 63;
-    const int sl = blockIdx.y * kGatherStates + (threadIdx.x >> 6);
-    if (sl >= a.ns)
-        return;
-    const int sg = a.sg0 + sl;
-    const int kk = sg / a.nstates;
-    const double2 *kph = a.kph + 3 * kk;
-    const InT *in = reinterpret_cast<const InT *>(a.in) + (size_t)sl * a.geo.N;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int s0 = blockIdx.y * kGatherStates + wave * kGatherSPW;
     const int np = a.pj.nproj[at];
     const int npt = a.pj.npts[at];
     const long io = a.pj.ioff[at];
-    const long po = a.pj.poff[at];
+    const double4 ap = a.pj.apos[at];
+    const double2 ar = a.pj.arad[at];
+    const int nx = a.geo.nx, ny = a.geo.ny, nz = a.geo.nz;
+    const double Lx = nx * a.geo.h[0], Ly = ny * a.geo.h[1],
+                 Lz = nz * a.geo.h[2];
     const int p0 = ch * kGatherChunk;
     const int p1 = min(npt, p0 + kGatherChunk);
-    R acc[2 * kMaxProj];
+    R acc[kGatherSPW][2 * kMaxProj];
 #pragma unroll
-    for (int j = 0; j < 2 * kMaxProj; ++j)
-        acc[j] = 0;
+    for (int q = 0; q < kGatherSPW; ++q)
+#pragma unroll
+        for (int j = 0; j < 2 * kMaxProj; ++j)
+            acc[q][j] = 0;
     for (int pt = p0 + lane; pt < p1; pt += 64) {
-        V val = ldc<R>(in, a.pj.sidx[io + pt]);
+        const int g = a.pj.sidx[io + pt];
+        const int pk = a.pj.sxyz[io + pt];
         const int code = a.pj.sshift[io + pt];
-        if (code)
-            val = cmul(val, shift_phase<V>(kph, code));
+        const int ix = pk & 0x3ff, iy = (pk >> 10) & 0x3ff, iz = pk >> 20;
+        const int tx = (int)(signed char)(code & 0xff);
+        const int ty = (int)(signed char)((code >> 8) & 0xff);
+        const int tz = (int)(signed char)((code >> 16) & 0xff);
+        const double dx = axis_coord(nx, a.geo.h[0], a.geo.per[0], ix) +
+                          tx * Lx - ap.x;
+        const double dy = axis_coord(ny, a.geo.h[1], a.geo.per[1], iy) +
+                          ty * Ly - ap.y;
+        const double dz = axis_coord(nz, a.geo.h[2], a.geo.per[2], iz) +
+                          tz * Lz - ap.z;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        R p[kMaxProj];
+        proj_shape<R>(dx, dy, dz, r2, ar, np, p);
 #pragma unroll
-        for (int j = 0; j < kMaxProj; ++j) {
-            if (j < np) {
-                R pv;
-                if constexpr (sizeof(R) == 8)
-                    pv = a.pj.ptab[po + (long)j * npt + pt];
-                else
-                    pv = a.pj.ptabf[po + (long)j * npt + pt];
-                acc[2 * j] += pv * val.x;
-                acc[2 * j + 1] += pv * val.y;
+        for (int q = 0; q < kGatherSPW; ++q) {
+            const int sl = s0 + q;
+            if (sl >= a.ns)
+                break;
+            V val = ldc<R>(reinterpret_cast<const InT *>(a.in) +
+                               (size_t)sl * a.geo.N, g);
+            if (code) {
+                const int kk = (a.sg0 + sl) / a.nstates;
+                val = cmul(val, shift_phase<V>(a.kph + 3 * kk, code));
+            }
+#pragma unroll
+            for (int j = 0; j < kMaxProj; ++j) {
+                acc[q][2 * j] += p[j] * val.x;
+                acc[q][2 * j + 1] += p[j] * val.y;
             }
         }
     }
 #pragma unroll
-    for (int j = 0; j < 2 * kMaxProj; ++j)
-        acc[j] = wave_sum(acc[j]);
-    if (lane == 0) {
-        V *part = reinterpret_cast<V *>(a.Dpart) +
-                  (((size_t)sl * a.pj.natoms + at) * a.nchunk + ch) * kMaxProj;
-        for (int j = 0; j < kMaxProj; ++j)
-            part[j] = cmk<V>(acc[2 * j], acc[2 * j + 1]);
+    for (int q = 0; q < kGatherSPW; ++q) {
+        const int sl = s0 + q;
+#pragma unroll
+        for (int j = 0; j < 2 * kMaxProj; ++j)
+            acc[q][j] = wave_sum(acc[q][j]);
+        if (lane == 0 && sl < a.ns) {
+            V *part = reinterpret_cast<V *>(a.Dpart) +
+                      (((size_t)sl * a.pj.natoms + at) * a.nchunk + ch) *
+                          kMaxProj;
+            for (int j = 0; j < kMaxProj; ++j)
+                part[j] = cmk<V>(acc[q][2 * j], acc[q][2 * j + 1]);
+        }
     }
 }
 
+// Stage 2: D[s][a][j] = N_j^2 h^3 E_{a,l(j)} sum over chunks (in order).
 template <class R>
 __global__ __launch_bounds__(256) void k_gather_finalize(GArgs a)
 {
@@ -658,8 +660,90 @@ __global__ __launch_bounds__(256) void k_gather_finalize(GArgs a)
         re += v.x;
         im += v.y;
     }
-    const R e = (j < a.pj.nproj[at]) ? (R)a.pj.EjN[at * kMaxProj + j] : (R)0;
+    const R e = (j < a.pj.nproj[at]) ? (R)a.pj.EjN2[at * kMaxProj + j]
+                                     : (R)0;
     reinterpret_cast<V *>(a.D)[i] = cmk<V>(e * re, e * im);
+}
+
+// V_NL in on the hull: W[s][h] = sum over atoms a whose sphere holds hull
+// point h of sum_j P_j(r) rad(r) D[s][a][j] exp(-i k.T).  A workgroup takes
+// a chunk of 64 hull points and 16 states (4 per wavefront); atoms in index
+// order (deterministic).
+constexpr int kApplySPW = 4;
+constexpr int kApplyStates = 4 * kApplySPW;
+
+template <class R>
+__global__ __launch_bounds__(256) void k_kbapply(GArgs a)
+{
+    using V = typename Cplx<R>::T;
+    const int chunk = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int s0 = blockIdx.y * kApplyStates + wave * kApplySPW;
+    const int h = chunk * kHullChunk + lane;
+    const bool valid = h < a.pj.nhull;
+    const int nx = a.geo.nx, ny = a.geo.ny, nz = a.geo.nz;
+    const int perx = a.geo.per[0], pery = a.geo.per[1], perz = a.geo.per[2];
+    const double Lx = nx * a.geo.h[0], Ly = ny * a.geo.h[1],
+                 Lz = nz * a.geo.h[2];
+    const int pk = valid ? a.pj.hxyz[h] : 0;
+    const double xc = axis_coord(nx, a.geo.h[0], perx, pk & 0x3ff);
+    const double yc = axis_coord(ny, a.geo.h[1], pery, (pk >> 10) & 0x3ff);
+    const double zc = axis_coord(nz, a.geo.h[2], perz, pk >> 20);
+    V acc[kApplySPW];
+#pragma unroll
+    for (int q = 0; q < kApplySPW; ++q)
+        acc[q] = czero<V>();
+    const int c0 = a.pj.hc_off[chunk], c1 = a.pj.hc_off[chunk + 1];
+    for (int ci = c0; ci < c1; ++ci) {
+        const int at = a.pj.hc_atoms[ci];
+        const double4 ap = a.pj.apos[at];
+        double dx = xc - ap.x, dy = yc - ap.y, dz = zc - ap.z;
+        int mx = 0, my = 0, mz = 0;
+        if (perx) {
+            mx = (int)rint(dx / Lx);
+            dx -= mx * Lx;
+        }
+        if (pery) {
+            my = (int)rint(dy / Ly);
+            dy -= my * Ly;
+        }
+        if (perz) {
+            mz = (int)rint(dz / Lz);
+            dz -= mz * Lz;
+        }
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (!valid || !(r2 < ap.w))
+            continue;
+        const int np = a.pj.nproj[at];
+        R p[kMaxProj];
+        proj_shape<R>(dx, dy, dz, r2, a.pj.arad[at], np, p);
+        const int code = (mx & 0xff) | ((my & 0xff) << 8) | ((mz & 0xff) << 16);
+#pragma unroll
+        for (int q = 0; q < kApplySPW; ++q) {
+            const int sl = s0 + q;
+            if (sl >= a.ns)
+                break;
+            const V *D = reinterpret_cast<const V *>(a.D) +
+                         ((size_t)sl * a.pj.natoms + at) * kMaxProj;
+            V t = czero<V>();
+            for (int j = 0; j < np; ++j)
+                t = cadd(t, cscale(D[j], p[j]));
+            if (code) {
+                const int kk = (a.sg0 + sl) / a.nstates;
+                t = cmul(t, shift_phase<V>(a.kph + 3 * kk, code));
+            }
+            acc[q] = cadd(acc[q], t);
+        }
+    }
+    if (valid)
+#pragma unroll
+        for (int q = 0; q < kApplySPW; ++q) {
+            const int sl = s0 + q;
+            if (sl < a.ns)
+                reinterpret_cast<V *>(a.W)[(size_t)sl * a.pj.nhull + h] =
+                    acc[q];
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -897,33 +981,61 @@ __global__ __launch_bounds__(256) void k_exchange_partial(Geo G,
 // ---------------------------------------------------------------------------
 int hpsi_threads(int nx, int TY)
 {
-    // enough threads that the halo (8 rows of nx, 8 columns of TY + 8)
-    // needs at most kHaloMax loads per thread
-    int want = std::max(nx * TY, 2 * nx);
-    const int halo = 2 * kHalf * nx + 2 * kHalf * (TY + 2 * kHalf);
-    want = std::max(want, (halo + kHaloMax - 1) / kHaloMax);
+    const int want = std::max(nx * TY, 64);
     return ((want + 63) / 64) * 64;
 }
 
-size_t hpsi_lds_bytes(int nx, int TY, int natoms, bool mixed)
+int hpsi_halo_per_thread(const Geo &g, int TY, int nthr)
+{
+    // dynamic halo entries (in-grid rows, and wrapped columns on a
+    // periodic x axis) of a full tile
+    const int dyn = 2 * kHalf * g.nx + (g.per[0] ? 2 * kHalf * (TY + 2 * kHalf)
+                                                  : 0);
+    const int hm = (dyn + nthr - 1) / nthr;
+    return hm <= 2 ? 2 : (hm <= 4 ? 4 : (hm <= 8 ? 8 : 16));
+}
+
+size_t hpsi_lds_bytes(int nx, int TY, int zchunk, bool mixed)
 {
     const size_t v = mixed ? 8 : 16;
-    size_t bytes = 2 * (size_t)(TY + 2 * kHalf) * (nx + 2 * kHalf) * v +
-                   (((size_t)natoms * sizeof(int) + 15) & ~size_t(15)) +
-                   90 * v;
-    return std::max<size_t>(bytes, 64 * sizeof(double));
+    return 2 * (size_t)(TY + 2 * kHalf) * (nx + 2 * kHalf) * v + 90 * v +
+           (size_t)zchunk * TY * sizeof(int4);
+}
+
+template <class R, class InT, class TT, int MODE, bool GRAD>
+static hipError_t go_hpsi2(const HArgs &a, int ns, hipStream_t st)
+{
+    const int nthr = hpsi_threads(a.geo.nx, a.TY);
+    const size_t lds = hpsi_lds_bytes(a.geo.nx, a.TY, a.zchunk,
+                                      sizeof(R) == 4);
+    dim3 grid((unsigned)(a.ntile_y * a.nzc * ns));
+    switch (hpsi_halo_per_thread(a.geo, a.TY, nthr)) {
+    case 2:
+        hipLaunchKernelGGL((k_hpsi<R, InT, TT, MODE, GRAD, 2>), grid,
+                           dim3(nthr), lds, st, a);
+        break;
+    case 4:
+        hipLaunchKernelGGL((k_hpsi<R, InT, TT, MODE, GRAD, 4>), grid,
+                           dim3(nthr), lds, st, a);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_hpsi<R, InT, TT, MODE, GRAD, 8>), grid,
+                           dim3(nthr), lds, st, a);
+        break;
+    default:
+        hipLaunchKernelGGL((k_hpsi<R, InT, TT, MODE, GRAD, 16>), grid,
+                           dim3(nthr), lds, st, a);
+        break;
+    }
+    return hipGetLastError();
 }
 
 template <class R, class InT, class TT, int MODE>
 static hipError_t go_hpsi(const HArgs &a, int ns, hipStream_t st)
 {
-    const int nthr = hpsi_threads(a.geo.nx, a.TY);
-    const size_t lds = hpsi_lds_bytes(a.geo.nx, a.TY, a.pj.natoms,
-                                      sizeof(R) == 4);
-    dim3 grid((unsigned)(a.ntile_y * a.nzc * ns));
-    hipLaunchKernelGGL((k_hpsi<R, InT, TT, MODE>), grid, dim3(nthr), lds, st,
-                       a);
-    return hipGetLastError();
+    const bool grad = (a.A[0] != 0.0) || (a.A[1] != 0.0) || (a.A[2] != 0.0);
+    return grad ? go_hpsi2<R, InT, TT, MODE, true>(a, ns, st)
+                : go_hpsi2<R, InT, TT, MODE, false>(a, ns, st);
 }
 
 hipError_t launch_hpsi(int mode, bool mixed, bool in_is_f64, const HArgs &a,
@@ -971,7 +1083,7 @@ hipError_t launch_gather(bool mixed, bool in_is_f64, const GArgs &a, int ns,
     b.ns = ns;
     dim3 grid(a.pj.natoms, (ns + kGatherStates - 1) / kGatherStates,
               a.nchunk);
-    dim3 blk(64 * kGatherStates);
+    dim3 blk(256);
     if (!mixed)
         hipLaunchKernelGGL((k_gather<double, double2>), grid, blk, 0, st, b);
     else if (in_is_f64)
@@ -989,6 +1101,20 @@ hipError_t launch_gather(bool mixed, bool in_is_f64, const GArgs &a, int ns,
     else
         hipLaunchKernelGGL((k_gather_finalize<float>), g2, dim3(256), 0, st,
                            b);
+    return hipGetLastError();
+}
+
+hipError_t launch_kbapply(bool mixed, const GArgs &a, int ns, hipStream_t st)
+{
+    if (ns <= 0 || a.pj.natoms <= 0 || a.pj.nhull <= 0)
+        return hipSuccess;
+    GArgs b = a;
+    b.ns = ns;
+    dim3 grid(a.pj.nhchunk, (ns + kApplyStates - 1) / kApplyStates);
+    if (!mixed)
+        hipLaunchKernelGGL((k_kbapply<double>), grid, dim3(256), 0, st, b);
+    else
+        hipLaunchKernelGGL((k_kbapply<float>), grid, dim3(256), 0, st, b);
     return hipGetLastError();
 }
 

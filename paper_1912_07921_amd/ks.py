@@ -243,12 +243,13 @@ def ks_profile_begin(h, capacity):
 
 
 def ks_profile_end(h):
-    """{class: (total_ms, launches)} for classes hpsi, gather, reduce."""
-    ms = (C.c_double * 3)()
-    cnt = (C.c_long * 3)()
+    """{class: (total_ms, launches)} for classes hpsi, gather, reduce,
+    kbapply."""
+    ms = (C.c_double * 4)()
+    cnt = (C.c_long * 4)()
     _check(lib().ks_profile_end(h, ms, cnt))
-    return {name: (ms[i], cnt[i])
-            for i, name in enumerate(("hpsi", "gather", "reduce"))}
+    return {name: (ms[i], cnt[i]) for i, name in
+            enumerate(("hpsi", "gather", "reduce", "kbapply"))}
 
 
 # ---------------------------------------------------------------------------
