@@ -15,9 +15,11 @@ same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
+import re
 import sys
 import time
 
@@ -31,6 +33,46 @@ HBM_PEAK_GBS = 8000.0
 STEP_BYTES = {0: 352.0, 1: 224.0}
 METRIC = ("H·ψ grid-point·states/s + HBM GB/s frac; serving p50/p99 step, "
           "FP32-mix vs FP64")
+
+
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SRC = os.path.join(ROOT, "paper_1912_07921_amd", "csrc",
+                          "ks_kernels.hip")
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic(workload):
+    """HBM bytes per H.psi launch recorded from rocprofv3 FETCH_SIZE and
+    WRITE_SIZE runs (scaled by the copy-kernel calibration), if the kernel
+    source has not changed since; else None."""
+    path = os.path.join(PROFILES, f"hpsi_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)\s+"
+                  r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    if not m or m.group(2) != kernel_source_hash():
+        return None
+    return float(m.group(1))
+
+
+def calibrate_copy(torch, gib=2):
+    """A plain device copy of known size, for scaling the rocprofv3 HBM
+    counters: `gib` GiB read and `gib` GiB written by one copy kernel."""
+    n = gib * (1 << 30) // 8
+    src = torch.empty(n, dtype=torch.float64, device="cuda")
+    src.fill_(1.0)
+    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    flush.fill_(2.0)          # 1 GiB: evicts src from the 256 MB MALL
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copied {gib} GiB ({n * 8} bytes)")
 
 
 def log(msg):
@@ -96,6 +138,8 @@ def main():
                     help="oracle ETRS steps timed for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 2 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the "
@@ -105,6 +149,9 @@ def main():
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
     log(f"workload {args.workload}: generating inputs")
     w = make_workload(args.workload)
     N, S = w.spec.npoints, w.spec.nk * w.spec.nstates
@@ -117,9 +164,14 @@ def main():
     avg_ms = hp_ms / max(hp_n, 1)
     bytes_per_launch = STEP_BYTES[0] / 8.0 * N * S
     achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    traffic = recorded_traffic(args.workload)
     roofline = dict(bound="hbm", achieved=round(achieved, 1),
                     peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None)
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=traffic,
+                    algorithmic_bytes_per_launch=bytes_per_launch,
+                    kernel="k_hpsi (H.psi stencil pass)",
+                    kernel_avg_us=round(1e3 * avg_ms, 2))
     kernel_times = {k: dict(total_ms=round(v[0], 3), launches=v[1],
                             avg_us=round(1e3 * v[0] / max(v[1], 1), 2))
                     for k, v in prof.items()}

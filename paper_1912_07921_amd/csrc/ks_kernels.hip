@@ -557,10 +557,20 @@ __device__ __forceinline__ void proj_shape(double dx, double dy, double dz,
 
 // Stage 1 of the gather: S_j = sum_pt P_j(r) rad(r) exp(i k.T) in(pt) over
 // chunks of kGatherChunk sphere points.  A workgroup takes one atom, one
-// chunk and 16 states: wavefront w handles 4 states, each lane a point, so
-// the projector shape is evaluated once per point and wavefront.
-constexpr int kGatherChunk = 256;
-constexpr int kGatherSPW = 4;             // states per wavefront
+// chunk and 4 * kGatherSPW states: wavefront w handles kGatherSPW states,
+// each lane a point, so the projector shape is evaluated once per point and
+// wavefront.
+#ifndef KS_GATHER_CHUNK
+#define KS_GATHER_CHUNK 512
+#endif
+#ifndef KS_GATHER_SPW
+#define KS_GATHER_SPW 2
+#endif
+#ifndef KS_APPLY_SPW
+#define KS_APPLY_SPW 4
+#endif
+constexpr int kGatherChunk = KS_GATHER_CHUNK;
+constexpr int kGatherSPW = KS_GATHER_SPW;   // states per wavefront
 constexpr int kGatherStates = 4 * kGatherSPW;
 
 template <class R, class InT>
@@ -667,9 +677,9 @@ __global__ __launch_bounds__(256) void k_gather_finalize(GArgs a)
 
 // V_NL in on the hull: W[s][h] = sum over atoms a whose sphere holds hull
 // point h of sum_j P_j(r) rad(r) D[s][a][j] exp(-i k.T).  A workgroup takes
-// a chunk of 64 hull points and 16 states (4 per wavefront); atoms in index
-// order (deterministic).
-constexpr int kApplySPW = 4;
+// a chunk of 64 hull points and 4 * kApplySPW states (kApplySPW per
+// wavefront); atoms in index order (deterministic).
+constexpr int kApplySPW = KS_APPLY_SPW;
 constexpr int kApplyStates = 4 * kApplySPW;
 
 template <class R>
