@@ -420,13 +420,13 @@ struct Timed {
         if (g->profiling && g->ev_used < (int)g->ev_class.size()) {
             slot = g->ev_used++;
             g->ev_class[slot] = c;
-            hipEventRecord(g->ev[2 * slot], g->stream);
+            (void)hipEventRecord(g->ev[2 * slot], g->stream);
         }
     }
     ~Timed()
     {
         if (slot >= 0)
-            hipEventRecord(g->ev[2 * slot + 1], g->stream);
+            (void)hipEventRecord(g->ev[2 * slot + 1], g->stream);
     }
 };
 
@@ -619,7 +619,7 @@ int ks_grid_create(const ks_grid_desc *d, ks_grid **out)
             const double ang = g->kpts[3 * k + a] * d->n[a] * d->h[a];
             g->kph[3 * k + a] = make_double2(std::cos(ang), std::sin(ang));
         }
-    hipGetDevice(&g->device);
+    (void)hipGetDevice(&g->device);
     int rc;
     if ((rc = dev_upload(g, &g->d_kph, g->kph)) ||
         (rc = dev_upload(g, &g->d_wocc, g->wocc)) ||
@@ -641,11 +641,11 @@ int ks_grid_destroy(ks_grid *g)
 {
     if (!g)
         return KS_OK;
-    hipStreamSynchronize(g->stream);
+    (void)hipStreamSynchronize(g->stream);
     for (hipEvent_t e : g->ev)
-        hipEventDestroy(e);
+        (void)hipEventDestroy(e);
     for (void *p : g->owned)
-        hipFree(p);
+        (void)hipFree(p);
     delete g;
     return KS_OK;
 }

@@ -97,6 +97,64 @@ ldc(const T *p, long i)
     return r;
 }
 
+// Streaming stores and loads of data touched once per pass (the H.psi
+// outputs, the Taylor terms read by the final pass): non-temporal, so they
+// do not evict the plane and halo lines that neighbouring workgroups reuse
+// from L2.
+#ifndef KS_NT_STORE
+#define KS_NT_STORE 1
+#endif
+#ifndef KS_NT_LOAD
+#define KS_NT_LOAD 1
+#endif
+typedef double nd2_t __attribute__((ext_vector_type(2)));
+typedef float nf2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void st_stream(double2 *p, double x, double y)
+{
+#if KS_NT_STORE
+    nd2_t v = {x, y};
+    __builtin_nontemporal_store(v, reinterpret_cast<nd2_t *>(p));
+#else
+    *p = make_double2(x, y);
+#endif
+}
+__device__ __forceinline__ void st_stream(float2 *p, float x, float y)
+{
+#if KS_NT_STORE
+    nf2_t v = {x, y};
+    __builtin_nontemporal_store(v, reinterpret_cast<nf2_t *>(p));
+#else
+    *p = make_float2(x, y);
+#endif
+}
+__device__ __forceinline__ void st_stream(double *p, double x)
+{
+#if KS_NT_STORE
+    __builtin_nontemporal_store(x, p);
+#else
+    *p = x;
+#endif
+}
+__device__ __forceinline__ double2 ld_stream(const double2 *p)
+{
+#if KS_NT_LOAD
+    const nd2_t v = __builtin_nontemporal_load(reinterpret_cast<const nd2_t *>(p));
+    return make_double2(v.x, v.y);
+#else
+    return *p;
+#endif
+}
+__device__ __forceinline__ float2 ld_stream(const float2 *p)
+{
+#if KS_NT_LOAD
+    const nf2_t v = __builtin_nontemporal_load(reinterpret_cast<const nf2_t *>(p));
+    return make_float2(v.x, v.y);
+#else
+    return *p;
+#endif
+}
+
 __device__ __forceinline__ int floordiv(int a, int n)
 {
     return a >= 0 ? a / n : -((-a + n - 1) / n);
@@ -178,8 +236,13 @@ __device__ __forceinline__ double axis_coord(int n, double h, int per, int i)
 // (neighbouring y-tiles of the same state, which share halo rows in that
 // XCD's L2).
 // ---------------------------------------------------------------------------
+#ifndef KS_XCD_REMAP
+#define KS_XCD_REMAP 1
+#endif
 __device__ __forceinline__ int xcd_remap(int L, int nblk)
 {
+    if (!KS_XCD_REMAP)
+        return L;
     constexpr int X = 8;
     const int per = nblk / X, rem = nblk % X;
     const int x = L % X, i = L / X;
@@ -452,41 +515,34 @@ __global__ __launch_bounds__(512) void k_hpsi(HArgs a)
             }
             hp = cadd(hp, kb);
             if constexpr (MODE == kApply) {
-                double2 o;
-                o.x = hp.x;
-                o.y = hp.y;
-                reinterpret_cast<double2 *>(a.out)[(size_t)sl * N + g] = o;
+                st_stream(reinterpret_cast<double2 *>(a.out) +
+                              (size_t)sl * N + g, (double)hp.x, (double)hp.y);
             } else if constexpr (MODE == kTerm) {
                 const V t = cmul(cs, hp);
-                TT o;
-                o.x = t.x;
-                o.y = t.y;
-                reinterpret_cast<TT *>(a.out)[(size_t)sl * N + g] = o;
+                st_stream(reinterpret_cast<TT *>(a.out) + (size_t)sl * N + g,
+                          t.x, t.y);
             } else {
                 const V t4 = cmul(cs, hp);
                 const size_t i = (size_t)sl * N + g;
-                const double2 bb = a.base[i];
-                const TT u1 = reinterpret_cast<const TT *>(a.t1)[i];
-                const TT u2 = reinterpret_cast<const TT *>(a.t2)[i];
+                const double2 bb = ld_stream(a.base + i);
+                const TT u1 = ld_stream(reinterpret_cast<const TT *>(a.t1) + i);
+                const TT u2 = ld_stream(reinterpret_cast<const TT *>(a.t2) + i);
                 const double re = bb.x + (double)u1.x + (double)u2.x +
                                   (double)c.x + (double)t4.x;
                 const double im = bb.y + (double)u1.y + (double)u2.y +
                                   (double)c.y + (double)t4.y;
-                double2 o;
-                o.x = re;
-                o.y = im;
-                reinterpret_cast<double2 *>(a.out)[i] = o;
+                st_stream(reinterpret_cast<double2 *>(a.out) + i, re, im);
                 if constexpr (MODE == kFinalPred) {
                     const double pr = bb.x + 2.0 * u1.x + 4.0 * u2.x +
                                       8.0 * c.x + 16.0 * (double)t4.x;
                     const double pi = bb.y + 2.0 * u1.y + 4.0 * u2.y +
                                       8.0 * c.y + 16.0 * (double)t4.y;
                     if (a.npart)
-                        a.npart[i] = w_occ * (pr * pr + pi * pi);
+                        st_stream(a.npart + i, w_occ * (pr * pr + pi * pi));
                 } else {
                     const double sq = re * re + im * im;
                     if (a.npart)
-                        a.npart[i] = w_occ * sq;
+                        st_stream(a.npart + i, w_occ * sq);
                     nrm += sq;
                 }
             }
