@@ -192,6 +192,45 @@ int ks_get_launch(const ks_grid *g, int out[4]);
 int ks_profile_begin(ks_grid *g, int capacity);
 int ks_profile_end(ks_grid *g, double out_ms[4], long out_count[4]);
 
+/* ---- batched form ----
+ * Several grid objects ("jobs") propagated together: every Taylor pass of
+ * all jobs runs as one persistent H.psi launch over a job table (with one
+ * batched projector gather and apply), the density / potential / dipole /
+ * norm reductions per job, and one ETRS step (the same step as
+ * ks_propagate_etrs) is captured once as a HIP graph and replayed.  Results
+ * equal those of ks_propagate_etrs on each job alone, for the same launch
+ * shapes.  Grids must share the precision, have a workspace, and not be used
+ * on their own while the batch exists (the batch sets their stream). */
+typedef struct ks_batch ks_batch;
+
+typedef struct {
+    ks_grid *grid;
+    void *d_psi;           /* the job's states, propagated in place */
+    const double *d_vion;  /* must stay valid while the batch exists */
+    double dt, t0;
+    double *d_dipole;      /* device (max_steps+1)*3 or NULL */
+    double *d_norms;       /* device (max_steps+1)*nk*nstates or NULL */
+    int max_steps;         /* steps the output buffers have room for */
+} ks_job;
+
+/* Bind the jobs, build the device job table, and compute every job's
+ * v(t0), dipole(t0) and norms(t0) (stream-ordered on `stream`). */
+int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
+                    ks_batch **out);
+
+/* Advance every job by nsteps ETRS steps (KS_E_ARG if a job would pass its
+ * max_steps).  The first call with graphs on captures one step. */
+int ks_batch_step(ks_batch *b, int nsteps);
+
+/* Graph replay (1, the default) or eager launches (0) for later steps. */
+int ks_batch_set_graph(ks_batch *b, int use_graph);
+
+/* Steps job `job` has taken so far. */
+int ks_batch_steps_done(const ks_batch *b, int job, int *out);
+
+/* Wait for the stream and free the batch (not the grids). */
+int ks_batch_destroy(ks_batch *b);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *ks_last_error(void);
 

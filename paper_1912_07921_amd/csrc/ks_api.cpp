@@ -75,7 +75,7 @@ struct ks_grid {
     size_t ws_bytes = 0;
     struct {
         size_t t1, t2, t3, half, npart, normpart, D, W, Dpart, rho, vpred,
-            dpart, gpart, dotpart, xpart, total;
+            dpart, gpart, dotpart, xpart, step, total;
     } lay{};
     int ntiles_max = 64;
     int nchunk = 1;
@@ -402,6 +402,7 @@ void layout(ks_grid *g)
     g->lay.gpart = take((size_t)g->gram_ksplit * g->nk * g->ns * g->ns * 16);
     g->lay.dotpart = take(S * g->norm_chunks * 16);
     g->lay.xpart = take(ndb * 8);
+    g->lay.step = take(sizeof(int));
     g->lay.total = off;
 }
 
@@ -1075,6 +1076,376 @@ int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
                                         g->stream));
         }
     }
+    return KS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched form: several grid objects (jobs) propagated together.  Every
+// Taylor pass of all jobs is one persistent H.psi launch (plus one batched
+// projector gather, finalize and apply launch); the density, potential,
+// dipole and norm reductions are per job; one ETRS step is captured as a HIP
+// graph once and replayed.  Time-dependent inputs (A(t), output slots) come
+// from per-job device step counters, so the replayed graph needs no change.
+// ---------------------------------------------------------------------------
+struct ks_batch {
+    std::vector<ks_grid *> grids;
+    std::vector<ks_job> jobs;
+    std::vector<JobDev> hjobs;
+    hipStream_t stream = nullptr;
+    bool mixed = false, grad = false;
+    int hm = 2;
+    size_t lds = 0;
+    int grid_hpsi = 0, grid_proj = 0;
+    std::vector<void *> owned;
+    JobDev *d_jobs = nullptr;
+    int *d_off[4] = {nullptr, nullptr, nullptr, nullptr};
+    int off_total[4] = {0, 0, 0, 0};
+    int **d_steps = nullptr;
+    std::vector<int> steps_done;
+    bool use_graph = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+template <class T> int batch_alloc(ks_batch *b, T **p, size_t count)
+{
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count * sizeof(T), 16));
+    if (e != hipSuccess)
+        return fail(KS_E_OOM, "hipMalloc: %s", hipGetErrorString(e));
+    b->owned.push_back(q);
+    *p = static_cast<T *>(q);
+    return KS_OK;
+}
+
+BArgs batch_args(const ks_batch *b, int kind, int pass)
+{
+    BArgs a;
+    a.jobs = b->d_jobs;
+    a.njobs = (int)b->hjobs.size();
+    a.off = b->d_off[kind];
+    a.off_total = b->off_total[kind];
+    a.pass = pass;
+    return a;
+}
+
+// Enqueue one ETRS step of every job on the batch stream.
+int batch_enqueue_step(ks_batch *b)
+{
+    const hipStream_t st = b->stream;
+    for (int e = 0; e < 2; ++e) {
+        for (int j = 1; j <= 4; ++j) {
+            const int p = 4 * e + j;
+            KS_HIP(launch_projectors_batch(b->mixed,
+                                           batch_args(b, kItemGather, p),
+                                           batch_args(b, kItemGatherFin, p),
+                                           batch_args(b, kItemApply, p),
+                                           b->grid_proj, st));
+            KS_HIP(launch_pass_batch(b->mixed, batch_args(b, kItemHpsi, p),
+                                     b->grad, b->hm, b->lds, b->grid_hpsi,
+                                     st));
+        }
+        if (e == 0)
+            for (size_t i = 0; i < b->grids.size(); ++i) {
+                ks_grid *g = b->grids[i];
+                if (!g->xc)
+                    continue;
+                DArgs a;
+                a.geo = g->geo;
+                a.nsrc = g->stot;
+                a.npart = b->hjobs[i].npart;
+                a.rho = wsp<double>(g, g->lay.rho);
+                a.vion = b->jobs[i].d_vion;
+                a.vout = wsp<double>(g, g->lay.vpred);
+                a.xc = 1;
+                KS_HIP(launch_density(a, st));
+            }
+    }
+    for (size_t i = 0; i < b->grids.size(); ++i) {
+        ks_grid *g = b->grids[i];
+        const ks_job &jb = b->jobs[i];
+        const double h3 = g->geo.h[0] * g->geo.h[1] * g->geo.h[2];
+        const int *step = wsp<int>(g, g->lay.step);
+        if (b->hjobs[i].npart_end) {
+            DArgs a;
+            a.geo = g->geo;
+            a.nsrc = g->stot;
+            a.npart = b->hjobs[i].npart;
+            a.rho = wsp<double>(g, g->lay.rho);
+            a.vion = jb.d_vion;
+            a.vout = g->d_v;
+            a.xc = g->xc;
+            a.dpart = jb.d_dipole ? wsp<double>(g, g->lay.dpart) : nullptr;
+            KS_HIP(launch_density(a, st));
+            if (jb.d_dipole)
+                KS_HIP(launch_dipole_finalize(a.dpart,
+                                              density_blocks(g->geo.N), h3,
+                                              jb.d_dipole, st, step));
+        }
+        if (jb.d_norms)
+            KS_HIP(launch_norm_finalize(wsp<double>(g, g->lay.normpart),
+                                        g->stot, g->ntile_y * g->nzc, h3,
+                                        jb.d_norms, st, step));
+    }
+    KS_HIP(launch_step_advance(b->d_steps, (int)b->grids.size(), st));
+    return KS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
+                    ks_batch **out)
+{
+    if (!out)
+        return fail(KS_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!jobs || njobs < 1)
+        return fail(KS_E_ARG, "need at least one job");
+    const bool mixed = jobs[0].grid ? jobs[0].grid->mixed : false;
+    for (int i = 0; i < njobs; ++i) {
+        const ks_job &jb = jobs[i];
+        ks_grid *g = jb.grid;
+        if (!g || !jb.d_psi || !jb.d_vion)
+            return fail(KS_E_ARG, "job %d: NULL grid, psi or v_ion", i);
+        if (!g->ws)
+            return fail(KS_E_STATE, "job %d: grid has no workspace", i);
+        if (g->mixed != mixed)
+            return fail(KS_E_ARG, "jobs of one batch share the precision");
+        if (!std::isfinite(jb.dt) || !std::isfinite(jb.t0) ||
+            jb.max_steps < 0)
+            return fail(KS_E_ARG, "job %d: bad dt, t0 or max_steps", i);
+        if (jb.d_dipole && (g->geo.per[0] || g->geo.per[1] || g->geo.per[2]))
+            return fail(KS_E_UNSUPPORTED, "job %d: dipole of a periodic "
+                        "grid", i);
+        for (int k = 0; k < i; ++k)
+            if (jobs[k].grid == g)
+                return fail(KS_E_ARG, "a grid object appears twice");
+    }
+    ks_batch *b = new ks_batch;
+    b->stream = static_cast<hipStream_t>(stream);
+    b->mixed = mixed;
+    b->jobs.assign(jobs, jobs + njobs);
+    b->hm = 2;
+    for (int i = 0; i < njobs; ++i) {
+        ks_grid *g = jobs[i].grid;
+        g->stream = b->stream;
+        b->grids.push_back(g);
+        JobDev J;
+        J.h = base_hargs(g);
+        J.g = base_gargs(g);
+        J.g.D = g->ws + g->lay.D;
+        J.g.ns = g->stot;
+        J.g.sg0 = 0;
+        J.stot = g->stot;
+        J.psi = static_cast<double2 *>(jobs[i].d_psi);
+        J.half = wsp<double2>(g, g->lay.half);
+        J.t[0] = g->ws + g->lay.t1;
+        J.t[1] = g->ws + g->lay.t2;
+        J.t[2] = g->ws + g->lay.t3;
+        J.npart = wsp<double>(g, g->lay.npart);
+        J.npart_end = (g->xc || jobs[i].d_dipole) ? 1 : 0;
+        J.normpart_end = jobs[i].d_norms ? wsp<double>(g, g->lay.normpart)
+                                         : nullptr;
+        J.vion = jobs[i].d_vion;
+        J.vcur = g->d_v;
+        J.vpred = wsp<double>(g, g->lay.vpred);
+        J.xc = g->xc;
+        J.dt = jobs[i].dt;
+        J.step = wsp<int>(g, g->lay.step);
+        b->hjobs.push_back(J);
+        if (g->laser[0] != 0.0)
+            b->grad = true;
+        b->hm = std::max(b->hm, hpsi_halo_per_thread(g->geo, g->TY, 512));
+        b->lds = std::max(b->lds, lds_for(g, g->TY, g->zchunk));
+    }
+    int rc;
+    std::vector<int *> steps(njobs);
+    for (int i = 0; i < njobs; ++i)
+        steps[i] = const_cast<int *>(b->hjobs[i].step);
+    if ((rc = batch_alloc(b, &b->d_jobs, njobs)) ||
+        (rc = batch_alloc(b, &b->d_steps, njobs))) {
+        ks_batch_destroy(b);
+        return rc;
+    }
+    for (int i = 0; i < njobs; ++i) {
+        // A(t) at both ends of every step, with the same arithmetic as the
+        // single-job propagator (t = t0 + s dt and t + dt)
+        const ks_job &jb = jobs[i];
+        std::vector<double4> tab(2 * (size_t)std::max(jb.max_steps, 1));
+        for (int s = 0; s < jb.max_steps; ++s) {
+            const double t = jb.t0 + s * jb.dt;
+            double A[3];
+            for (int e = 0; e < 2; ++e) {
+                laser_A(jb.grid, e ? t + jb.dt : t, A);
+                tab[2 * s + e] = make_double4(
+                    A[0], A[1], A[2],
+                    0.5 * (A[0] * A[0] + A[1] * A[1] + A[2] * A[2]));
+            }
+        }
+        double4 *d = nullptr;
+        if ((rc = batch_alloc(b, &d, tab.size()))) {
+            ks_batch_destroy(b);
+            return rc;
+        }
+        if (hipMemcpy(d, tab.data(), tab.size() * sizeof(double4),
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            ks_batch_destroy(b);
+            return fail(KS_E_HIP, "upload of the A(t) table failed");
+        }
+        b->hjobs[i].Atab = d;
+    }
+    for (int kind = 0; kind < 4; ++kind) {
+        std::vector<int> off(njobs + 1, 0);
+        for (int i = 0; i < njobs; ++i)
+            off[i + 1] = off[i] + batch_items(kind, b->hjobs[i]);
+        b->off_total[kind] = off[njobs];
+        if ((rc = batch_alloc(b, &b->d_off[kind], njobs + 1))) {
+            ks_batch_destroy(b);
+            return rc;
+        }
+        if (hipMemcpy(b->d_off[kind], off.data(), off.size() * sizeof(int),
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            ks_batch_destroy(b);
+            return fail(KS_E_HIP, "upload of item offsets failed");
+        }
+    }
+    if (hipMemcpy(b->d_jobs, b->hjobs.data(), njobs * sizeof(JobDev),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_steps, steps.data(), njobs * sizeof(int *),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+        ks_batch_destroy(b);
+        return fail(KS_E_HIP, "upload of the job table failed");
+    }
+    // persistent grids: a multiple of 8 workgroups (XCD-aware order), at
+    // most what the work needs
+    auto pgrid = [](int items, int cap) {
+        const int g = std::min(std::max(items, 1), cap);
+        return ((g + 7) / 8) * 8;
+    };
+    b->grid_hpsi = pgrid(b->off_total[kItemHpsi], 1024);
+    b->grid_proj = pgrid(std::max({b->off_total[kItemGather],
+                                   b->off_total[kItemGatherFin],
+                                   b->off_total[kItemApply]}), 2048);
+    // initial potential, dipole and norms of every job (eager)
+    for (int i = 0; i < njobs; ++i) {
+        ks_grid *g = b->grids[i];
+        const ks_job &jb = b->jobs[i];
+        const double h3 = g->geo.h[0] * g->geo.h[1] * g->geo.h[2];
+        DArgs a;
+        a.geo = g->geo;
+        a.nsrc = g->stot;
+        a.psi = static_cast<const double2 *>(jb.d_psi);
+        a.wocc = g->d_wocc;
+        a.rho = wsp<double>(g, g->lay.rho);
+        a.vion = jb.d_vion;
+        a.vout = g->d_v;
+        a.xc = g->xc;
+        a.dpart = jb.d_dipole ? wsp<double>(g, g->lay.dpart) : nullptr;
+        hipError_t e = launch_density(a, b->stream);
+        if (e == hipSuccess && jb.d_dipole)
+            e = launch_dipole_finalize(a.dpart, density_blocks(g->geo.N), h3,
+                                       jb.d_dipole, b->stream);
+        if (e == hipSuccess && jb.d_norms) {
+            double *part = wsp<double>(g, g->lay.normpart);
+            e = launch_norm_partial(g->geo,
+                                    static_cast<const double2 *>(jb.d_psi),
+                                    g->stot, g->norm_chunks, part, b->stream);
+            if (e == hipSuccess)
+                e = launch_norm_finalize(part, g->stot, g->norm_chunks, h3,
+                                         jb.d_norms, b->stream);
+        }
+        if (e != hipSuccess) {
+            ks_batch_destroy(b);
+            return fail(KS_E_HIP, "batch initialisation: %s",
+                        hipGetErrorString(e));
+        }
+        g->vloc_set = true;
+    }
+    if (launch_step_set(b->d_steps, njobs, 0, b->stream) != hipSuccess) {
+        ks_batch_destroy(b);
+        return fail(KS_E_HIP, "batch initialisation failed");
+    }
+    b->steps_done.assign(njobs, 0);
+    *out = b;
+    return KS_OK;
+}
+
+int ks_batch_set_graph(ks_batch *b, int use_graph)
+{
+    if (!b)
+        return fail(KS_E_ARG, "batch is NULL");
+    b->use_graph = use_graph != 0;
+    return KS_OK;
+}
+
+int ks_batch_step(ks_batch *b, int nsteps)
+{
+    if (!b || nsteps < 0)
+        return fail(KS_E_ARG, "batch is NULL or nsteps < 0");
+    for (size_t i = 0; i < b->jobs.size(); ++i)
+        if (b->steps_done[i] + nsteps > b->jobs[i].max_steps)
+            return fail(KS_E_ARG, "job %zu would exceed its %d steps", i,
+                        b->jobs[i].max_steps);
+    if (nsteps == 0)
+        return KS_OK;
+    if (b->use_graph) {
+        if (!b->exec) {
+            KS_HIP(hipStreamBeginCapture(b->stream,
+                                         hipStreamCaptureModeThreadLocal));
+            int rc = batch_enqueue_step(b);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(b->stream, &graph);
+            if (rc) {
+                if (graph)
+                    (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (e != hipSuccess)
+                return fail(KS_E_HIP, "graph capture: %s",
+                            hipGetErrorString(e));
+            b->graph = graph;
+            KS_HIP(hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0));
+        }
+        for (int s = 0; s < nsteps; ++s)
+            KS_HIP(hipGraphLaunch(b->exec, b->stream));
+    } else {
+        for (int s = 0; s < nsteps; ++s) {
+            int rc = batch_enqueue_step(b);
+            if (rc)
+                return rc;
+        }
+    }
+    for (auto &d : b->steps_done)
+        d += nsteps;
+    return KS_OK;
+}
+
+int ks_batch_steps_done(const ks_batch *b, int job, int *out)
+{
+    if (!b || !out || job < 0 || job >= (int)b->jobs.size())
+        return fail(KS_E_ARG, "bad batch, job or output");
+    *out = b->steps_done[job];
+    return KS_OK;
+}
+
+int ks_batch_destroy(ks_batch *b)
+{
+    if (!b)
+        return KS_OK;
+    (void)hipStreamSynchronize(b->stream);
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    for (void *p : b->owned)
+        (void)hipFree(p);
+    delete b;
     return KS_OK;
 }
 

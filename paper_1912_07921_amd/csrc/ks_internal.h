@@ -132,11 +132,13 @@ int gather_chunks(int max_npts);
 int density_blocks(long N);
 hipError_t launch_density(const DArgs &a, hipStream_t st);
 hipError_t launch_dipole_finalize(const double *dpart, int nblocks,
-                                  double h3, double *out, hipStream_t st);
+                                  double h3, double *out, hipStream_t st,
+                                  const int *step = nullptr);
 hipError_t launch_norm_partial(const Geo &g, const double2 *psi, int ns,
                                int nchunks, double *normpart, hipStream_t st);
 hipError_t launch_norm_finalize(const double *normpart, int ns, int ntiles,
-                                double h3, double *out, hipStream_t st);
+                                double h3, double *out, hipStream_t st,
+                                const int *step = nullptr);
 hipError_t launch_kick(const Geo &g, double2 *psi, int ns, double kappa,
                        hipStream_t st);
 hipError_t launch_gram(const Geo &g, const double2 *psi, int nk, int ns,
@@ -147,5 +149,49 @@ hipError_t launch_dot_partial(const Geo &g, const double2 *a,
                               double2 *part, hipStream_t st);
 hipError_t launch_exchange_partial(const Geo &g, const double *rho,
                                    double *part, hipStream_t st);
+
+// ---- batched (multi-job) form ----
+// One job of a batch, in device memory: the static parts of its H.psi and
+// projector arguments plus the buffers the Taylor passes rotate through.
+struct JobDev {
+    HArgs h;                       // geometry, launch shape, kph, wocc, hull
+    GArgs g;                       // projector tables, D, Dpart, W, ns
+    int stot = 0;
+    double2 *psi = nullptr;        // caller's states (in/out)
+    double2 *half = nullptr;       // psi_half
+    void *t[3] = {nullptr, nullptr, nullptr};
+    double *npart = nullptr;
+    int npart_end = 0;             // final density needed (xc or dipole)
+    double *normpart_end = nullptr;
+    const double *vion = nullptr;
+    double *vcur = nullptr, *vpred = nullptr;
+    int xc = 0;
+    double dt = 0.0;
+    // [max_steps][2] (A, |A|^2 / 2) at the two ends of each step, tabulated
+    // on the host exactly as the single-job propagator evaluates them
+    const double4 *Atab = nullptr;
+    const int *step = nullptr;     // device step counter of the job
+};
+
+enum ItemKind : int { kItemHpsi = 0, kItemGather = 1, kItemGatherFin = 2,
+                      kItemApply = 3 };
+
+struct BArgs {
+    const JobDev *jobs = nullptr;
+    int njobs = 0;
+    const int *off = nullptr;      // [njobs+1] item offsets (device)
+    int off_total = 0;             // items over all jobs (host copy)
+    int pass = 1;                  // Taylor pass 1..8 of the ETRS step
+};
+
+int batch_items(int kind, const JobDev &J);
+hipError_t launch_pass_batch(bool mixed, const BArgs &b, bool grad, int hm,
+                             size_t lds, int grid, hipStream_t st);
+hipError_t launch_projectors_batch(bool mixed, const BArgs &bg,
+                                   const BArgs &bf, const BArgs &ba,
+                                   int grid, hipStream_t st);
+hipError_t launch_step_advance(int *const *steps, int njobs, hipStream_t st);
+hipError_t launch_step_set(int *const *steps, int njobs, int value,
+                           hipStream_t st);
 
 }  // namespace ks

@@ -266,18 +266,20 @@ __device__ __forceinline__ int xcd_remap(int L, int nblk)
 // V_NL in is precomputed on the hull rows (k_kbapply) and added with one
 // coalesced read.
 // ---------------------------------------------------------------------------
+extern __shared__ double2 smem_d2[];
+
+// One work item of the H.psi pass described by `a`: work item w is
+// (launch state, z-chunk, y-tile).  The whole workgroup takes part.
 template <class R, class InT, class TT, int MODE, bool GRAD, int HM>
-__global__ __launch_bounds__(512) void k_hpsi(HArgs a)
+__device__ __forceinline__ void hpsi_item(const HArgs &a, const int w)
 {
     using V = typename Cplx<R>::T;
-    extern __shared__ double2 smem_d2[];
     unsigned char *smem_raw = reinterpret_cast<unsigned char *>(smem_d2);
 
     const int nx = a.geo.nx, ny = a.geo.ny, nz = a.geo.nz;
     const int P = nx * ny;
     const long N = a.geo.N;
     const int ntiles = a.ntile_y * a.nzc;
-    const int w = xcd_remap(blockIdx.x, gridDim.x);
     const int sl = w / ntiles;
     const int tile = w - sl * ntiles;
     const int zc = tile / a.ntile_y;
@@ -584,6 +586,12 @@ __global__ __launch_bounds__(512) void k_hpsi(HArgs a)
     }
 }
 
+template <class R, class InT, class TT, int MODE, bool GRAD, int HM>
+__global__ __launch_bounds__(512) void k_hpsi(HArgs a)
+{
+    hpsi_item<R, InT, TT, MODE, GRAD, HM>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
 // ---------------------------------------------------------------------------
 // KB projectors.  p_j(r) = N_j P_j(r) rad(r) with the real solid harmonics
 // P = (1; x, y, z; xy, yz, zx, x^2 - y^2, 3z^2 - r^2) and
@@ -630,14 +638,13 @@ constexpr int kGatherSPW = KS_GATHER_SPW;   // states per wavefront
 constexpr int kGatherStates = 4 * kGatherSPW;
 
 template <class R, class InT>
-__global__ __launch_bounds__(256) void k_gather(GArgs a)
+__device__ __forceinline__ void gather_item(const GArgs &a, const int at,
+                                            const int grp, const int ch)
 {
     using V = typename Cplx<R>::T;
-    const int at = blockIdx.x;
-    const int ch = blockIdx.z;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int s0 = blockIdx.y * kGatherStates + wave * kGatherSPW;
+    const int s0 = grp * kGatherStates + wave * kGatherSPW;
     const int np = a.pj.nproj[at];
     const int npt = a.pj.npts[at];
     const long io = a.pj.ioff[at];
@@ -705,12 +712,18 @@ __global__ __launch_bounds__(256) void k_gather(GArgs a)
     }
 }
 
+template <class R, class InT>
+__global__ __launch_bounds__(256) void k_gather(GArgs a)
+{
+    gather_item<R, InT>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // Stage 2: D[s][a][j] = N_j^2 h^3 E_{a,l(j)} sum over chunks (in order).
 template <class R>
-__global__ __launch_bounds__(256) void k_gather_finalize(GArgs a)
+__device__ __forceinline__ void gather_finalize_item(const GArgs &a,
+                                                     const long i)
 {
     using V = typename Cplx<R>::T;
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long total = (long)a.ns * a.pj.natoms * kMaxProj;
     if (i >= total)
         return;
@@ -731,6 +744,12 @@ __global__ __launch_bounds__(256) void k_gather_finalize(GArgs a)
     reinterpret_cast<V *>(a.D)[i] = cmk<V>(e * re, e * im);
 }
 
+template <class R>
+__global__ __launch_bounds__(256) void k_gather_finalize(GArgs a)
+{
+    gather_finalize_item<R>(a, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // V_NL in on the hull: W[s][h] = sum over atoms a whose sphere holds hull
 // point h of sum_j P_j(r) rad(r) D[s][a][j] exp(-i k.T).  A workgroup takes
 // a chunk of 64 hull points and 4 * kApplySPW states (kApplySPW per
@@ -739,13 +758,13 @@ constexpr int kApplySPW = KS_APPLY_SPW;
 constexpr int kApplyStates = 4 * kApplySPW;
 
 template <class R>
-__global__ __launch_bounds__(256) void k_kbapply(GArgs a)
+__device__ __forceinline__ void kbapply_item(const GArgs &a, const int chunk,
+                                             const int grp)
 {
     using V = typename Cplx<R>::T;
-    const int chunk = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int s0 = blockIdx.y * kApplyStates + wave * kApplySPW;
+    const int s0 = grp * kApplyStates + wave * kApplySPW;
     const int h = chunk * kHullChunk + lane;
     const bool valid = h < a.pj.nhull;
     const int nx = a.geo.nx, ny = a.geo.ny, nz = a.geo.nz;
@@ -812,6 +831,12 @@ __global__ __launch_bounds__(256) void k_kbapply(GArgs a)
         }
 }
 
+template <class R>
+__global__ __launch_bounds__(256) void k_kbapply(GArgs a)
+{
+    kbapply_item<R>(a, blockIdx.x, blockIdx.y);
+}
+
 // ---------------------------------------------------------------------------
 // density: rho(g) = sum over sources in fixed order (density partials or
 // weighted |psi|^2); optional v = v_ion + v_x(rho); optional dipole partials
@@ -858,12 +883,16 @@ __global__ __launch_bounds__(kDensThreads) void k_density(DArgs a)
     }
 }
 
-// sum of nblocks dipole partials in fixed order, times h^3
+// sum of nblocks dipole partials in fixed order, times h^3; with a device
+// step counter, into out[3 * (step + 1) ...]
 __global__ __launch_bounds__(256) void k_dipole_finalize(const double *dpart,
                                                          int nblocks,
                                                          double h3,
-                                                         double *out)
+                                                         double *out,
+                                                         const int *step)
 {
+    if (step)
+        out += 3 * (*step + 1);
     __shared__ double sbuf[4 * 3];
     double d[3] = {0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
@@ -899,8 +928,11 @@ __global__ __launch_bounds__(256) void k_norm_partial(Geo G,
 
 __global__ __launch_bounds__(64) void k_norm_finalize(const double *part,
                                                       int ntiles, double h3,
-                                                      double *out)
+                                                      double *out,
+                                                      const int *step)
 {
+    if (step)
+        out += (size_t)gridDim.x * (*step + 1);
     __shared__ double sbuf[1];
     const int s = blockIdx.x;
     double acc[1] = {0.0};
@@ -1197,10 +1229,11 @@ hipError_t launch_density(const DArgs &a, hipStream_t st)
 }
 
 hipError_t launch_dipole_finalize(const double *dpart, int nblocks,
-                                  double h3, double *out, hipStream_t st)
+                                  double h3, double *out, hipStream_t st,
+                                  const int *step)
 {
     hipLaunchKernelGGL(k_dipole_finalize, dim3(1), dim3(256), 0, st, dpart,
-                       nblocks, h3, out);
+                       nblocks, h3, out, step);
     return hipGetLastError();
 }
 
@@ -1215,12 +1248,13 @@ hipError_t launch_norm_partial(const Geo &g, const double2 *psi, int ns,
 }
 
 hipError_t launch_norm_finalize(const double *normpart, int ns, int ntiles,
-                                double h3, double *out, hipStream_t st)
+                                double h3, double *out, hipStream_t st,
+                                const int *step)
 {
     if (ns <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_norm_finalize, dim3(ns), dim3(64), 0, st, normpart,
-                       ntiles, h3, out);
+                       ntiles, h3, out, step);
     return hipGetLastError();
 }
 
@@ -1268,6 +1302,272 @@ hipError_t launch_exchange_partial(const Geo &g, const double *rho,
 {
     hipLaunchKernelGGL(k_exchange_partial, dim3(density_blocks(g.N)),
                        dim3(256), 0, st, g, rho, part);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched (multi-job) passes.  One persistent launch covers the work items of
+// every job of a batch: workgroup b takes launch indices b, b + G, b + 2G,
+// ... (G, the grid size, a multiple of 8, so every index of one workgroup
+// stays on its XCD), remapped per XCD as above, and decodes (job, item)
+// from the job's item offset.  The pointers of Taylor pass p (exponential
+// e = (p-1)/4, term j = (p-1)%4 + 1) and the time of the pass come from the
+// job table and the job's device step counter, so a captured step replays
+// unchanged.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_job(const int *off, int njobs, int item)
+{
+    int j = 0;
+    while (j + 1 < njobs && item >= off[j + 1])
+        ++j;
+    return j;
+}
+
+// input of Taylor pass p: exponential 0 starts from psi, 1 from psi_half
+__device__ __forceinline__ const void *pass_input(const JobDev &J, int p)
+{
+    const int e = (p - 1) / 4, j = (p - 1) % 4 + 1;
+    if (j == 1)
+        return e == 0 ? (const void *)J.psi : (const void *)J.half;
+    return J.t[j - 2];
+}
+
+__device__ __forceinline__ HArgs pass_hargs(const JobDev &J, int p)
+{
+    HArgs a = J.h;
+    const int e = (p - 1) / 4, j = (p - 1) % 4 + 1;
+    const double4 Av = J.Atab[2 * *J.step + e];   // A(t0 + (step + e) dt)
+    a.A[0] = Av.x;
+    a.A[1] = Av.y;
+    a.A[2] = Av.z;
+    a.a2half = Av.w;
+    a.in = pass_input(J, p);
+    a.v = e == 0 ? J.vcur : (J.xc ? J.vpred : J.vion);
+    a.cre = 0.0;
+    a.cim = -0.5 * J.dt / j;
+    if (j < 4) {
+        a.out = J.t[j - 1];
+    } else {
+        a.out = e == 0 ? (void *)J.half : (void *)J.psi;
+        a.base = e == 0 ? J.psi : J.half;
+        a.t1 = J.t[0];
+        a.t2 = J.t[1];
+        a.npart = e == 0 ? (J.xc ? J.npart : nullptr)
+                         : (J.npart_end ? J.npart : nullptr);
+        a.normpart = e == 1 ? J.normpart_end : nullptr;
+    }
+    return a;
+}
+
+template <class R, class InT, class TT, int MODE, bool GRAD, int HM>
+__global__ __launch_bounds__(512) void k_hpsi_batch(BArgs b)
+{
+    const int total = b.off[b.njobs];
+    for (int L = blockIdx.x; L < total; L += gridDim.x) {
+        const int item = xcd_remap(L, total);
+        const int jb = find_job(b.off, b.njobs, item);
+        const HArgs a = pass_hargs(b.jobs[jb], b.pass);
+        hpsi_item<R, InT, TT, MODE, GRAD, HM>(a, item - b.off[jb]);
+        __syncthreads();   // LDS is reused by the next item
+    }
+}
+
+template <class R, class InT>
+__global__ __launch_bounds__(256) void k_gather_batch(BArgs b)
+{
+    const int total = b.off[b.njobs];
+    for (int L = blockIdx.x; L < total; L += gridDim.x) {
+        const int jb = find_job(b.off, b.njobs, L);
+        const JobDev &J = b.jobs[jb];
+        GArgs a = J.g;
+        a.in = pass_input(J, b.pass);
+        int r = L - b.off[jb];
+        const int ch = r % a.nchunk;
+        r /= a.nchunk;
+        const int ngrp = (a.ns + kGatherStates - 1) / kGatherStates;
+        const int grp = r % ngrp;
+        gather_item<R, InT>(a, r / ngrp, grp, ch);
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_gather_finalize_batch(BArgs b)
+{
+    const int total = b.off[b.njobs];
+    for (int L = blockIdx.x; L < total; L += gridDim.x) {
+        const int jb = find_job(b.off, b.njobs, L);
+        gather_finalize_item<R>(b.jobs[jb].g,
+                                (long)(L - b.off[jb]) * blockDim.x +
+                                    threadIdx.x);
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_kbapply_batch(BArgs b)
+{
+    const int total = b.off[b.njobs];
+    for (int L = blockIdx.x; L < total; L += gridDim.x) {
+        const int jb = find_job(b.off, b.njobs, L);
+        const GArgs &a = b.jobs[jb].g;
+        const int r = L - b.off[jb];
+        kbapply_item<R>(a, r % a.pj.nhchunk, r / a.pj.nhchunk);
+    }
+}
+
+__global__ void k_step_advance(int *const *steps, int njobs)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < njobs)
+        *steps[j] += 1;
+}
+
+__global__ void k_step_set(int *const *steps, int njobs, int value)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < njobs)
+        *steps[j] = value;
+}
+
+int batch_items(int kind, const JobDev &J)
+{
+    switch (kind) {
+    case kItemHpsi:
+        return J.h.ntile_y * J.h.nzc * J.stot;
+    case kItemGather:
+        return J.g.pj.natoms > 0
+                   ? J.g.pj.natoms *
+                         ((J.stot + kGatherStates - 1) / kGatherStates) *
+                         J.g.nchunk
+                   : 0;
+    case kItemGatherFin:
+        return J.g.pj.natoms > 0
+                   ? (int)(((long)J.stot * J.g.pj.natoms * kMaxProj + 255) /
+                           256)
+                   : 0;
+    case kItemApply:
+        return (J.g.pj.natoms > 0 && J.g.pj.nhull > 0)
+                   ? J.g.pj.nhchunk *
+                         ((J.stot + kApplyStates - 1) / kApplyStates)
+                   : 0;
+    }
+    return 0;
+}
+
+template <class R, class InT, class TT, int MODE, bool GRAD>
+static hipError_t go_hpsi_batch(const BArgs &b, int hm, size_t lds,
+                                int grid, hipStream_t st)
+{
+    switch (hm) {
+    case 2:
+        hipLaunchKernelGGL((k_hpsi_batch<R, InT, TT, MODE, GRAD, 2>),
+                           dim3(grid), dim3(512), lds, st, b);
+        break;
+    case 4:
+        hipLaunchKernelGGL((k_hpsi_batch<R, InT, TT, MODE, GRAD, 4>),
+                           dim3(grid), dim3(512), lds, st, b);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_hpsi_batch<R, InT, TT, MODE, GRAD, 8>),
+                           dim3(grid), dim3(512), lds, st, b);
+        break;
+    default:
+        hipLaunchKernelGGL((k_hpsi_batch<R, InT, TT, MODE, GRAD, 16>),
+                           dim3(grid), dim3(512), lds, st, b);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <class R, class InT, class TT, int MODE>
+static hipError_t go_hpsi_batch_g(const BArgs &b, bool grad, int hm,
+                                  size_t lds, int grid, hipStream_t st)
+{
+    return grad ? go_hpsi_batch<R, InT, TT, MODE, true>(b, hm, lds, grid, st)
+                : go_hpsi_batch<R, InT, TT, MODE, false>(b, hm, lds, grid,
+                                                         st);
+}
+
+hipError_t launch_pass_batch(bool mixed, const BArgs &b, bool grad, int hm,
+                             size_t lds, int grid, hipStream_t st)
+{
+    const int j = (b.pass - 1) % 4 + 1, e = (b.pass - 1) / 4;
+    if (!mixed) {
+        using D2 = double2;
+        if (j < 4)
+            return go_hpsi_batch_g<double, D2, D2, kTerm>(b, grad, hm, lds,
+                                                          grid, st);
+        return e == 0 ? go_hpsi_batch_g<double, D2, D2, kFinalPred>(
+                            b, grad, hm, lds, grid, st)
+                      : go_hpsi_batch_g<double, D2, D2, kFinal>(
+                            b, grad, hm, lds, grid, st);
+    }
+    if (j == 1)
+        return go_hpsi_batch_g<float, double2, float2, kTerm>(b, grad, hm,
+                                                              lds, grid, st);
+    if (j < 4)
+        return go_hpsi_batch_g<float, float2, float2, kTerm>(b, grad, hm, lds,
+                                                             grid, st);
+    return e == 0 ? go_hpsi_batch_g<float, float2, float2, kFinalPred>(
+                        b, grad, hm, lds, grid, st)
+                  : go_hpsi_batch_g<float, float2, float2, kFinal>(
+                        b, grad, hm, lds, grid, st);
+}
+
+hipError_t launch_projectors_batch(bool mixed, const BArgs &bg,
+                                   const BArgs &bf, const BArgs &ba,
+                                   int grid, hipStream_t st)
+{
+    const int j = (bg.pass - 1) % 4 + 1;
+    const bool f64 = !mixed || j == 1;
+    if (bg.off_total > 0) {
+        if (!mixed)
+            hipLaunchKernelGGL((k_gather_batch<double, double2>), dim3(grid),
+                               dim3(256), 0, st, bg);
+        else if (f64)
+            hipLaunchKernelGGL((k_gather_batch<float, double2>), dim3(grid),
+                               dim3(256), 0, st, bg);
+        else
+            hipLaunchKernelGGL((k_gather_batch<float, float2>), dim3(grid),
+                               dim3(256), 0, st, bg);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    if (bf.off_total > 0) {
+        if (!mixed)
+            hipLaunchKernelGGL((k_gather_finalize_batch<double>), dim3(grid),
+                               dim3(256), 0, st, bf);
+        else
+            hipLaunchKernelGGL((k_gather_finalize_batch<float>), dim3(grid),
+                               dim3(256), 0, st, bf);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    if (ba.off_total > 0) {
+        if (!mixed)
+            hipLaunchKernelGGL((k_kbapply_batch<double>), dim3(grid),
+                               dim3(256), 0, st, ba);
+        else
+            hipLaunchKernelGGL((k_kbapply_batch<float>), dim3(grid),
+                               dim3(256), 0, st, ba);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_step_advance(int *const *steps, int njobs, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_step_advance, dim3((njobs + 63) / 64), dim3(64), 0,
+                       st, steps, njobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_set(int *const *steps, int njobs, int value,
+                           hipStream_t st)
+{
+    hipLaunchKernelGGL(k_step_set, dim3((njobs + 63) / 64), dim3(64), 0, st,
+                       steps, njobs, value);
     return hipGetLastError();
 }
 

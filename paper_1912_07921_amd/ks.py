@@ -51,6 +51,19 @@ class ks_grid_desc(C.Structure):
     ]
 
 
+class ks_job(C.Structure):
+    _fields_ = [
+        ("grid", C.c_void_p),
+        ("d_psi", C.c_void_p),
+        ("d_vion", C.c_void_p),
+        ("dt", C.c_double),
+        ("t0", C.c_double),
+        ("d_dipole", C.c_void_p),
+        ("d_norms", C.c_void_p),
+        ("max_steps", C.c_int),
+    ]
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "ks_grid_create": (C.c_int, [C.POINTER(ks_grid_desc),
@@ -78,6 +91,13 @@ EXPORTS = {
     "ks_profile_begin": (C.c_int, [C.c_void_p, C.c_int]),
     "ks_profile_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
                                  C.POINTER(C.c_long)]),
+    "ks_batch_create": (C.c_int, [C.POINTER(ks_job), C.c_int, C.c_void_p,
+                                  C.POINTER(C.c_void_p)]),
+    "ks_batch_step": (C.c_int, [C.c_void_p, C.c_int]),
+    "ks_batch_set_graph": (C.c_int, [C.c_void_p, C.c_int]),
+    "ks_batch_steps_done": (C.c_int, [C.c_void_p, C.c_int,
+                                      C.POINTER(C.c_int)]),
+    "ks_batch_destroy": (C.c_int, [C.c_void_p]),
     "ks_last_error": (C.c_char_p, []),
 }
 
@@ -252,8 +272,35 @@ def ks_profile_end(h):
             enumerate(("hpsi", "gather", "reduce", "kbapply"))}
 
 
+def ks_batch_create(jobs, stream):
+    """jobs: sequence of ks_job.  Returns the batch handle."""
+    arr = (ks_job * len(jobs))(*jobs)
+    h = C.c_void_p()
+    _check(lib().ks_batch_create(arr, len(jobs), _stream_handle(stream),
+                                 C.byref(h)))
+    return h
+
+
+def ks_batch_step(b, nsteps):
+    return _check(lib().ks_batch_step(b, int(nsteps)))
+
+
+def ks_batch_set_graph(b, use_graph):
+    return _check(lib().ks_batch_set_graph(b, int(bool(use_graph))))
+
+
+def ks_batch_steps_done(b, job):
+    out = C.c_int()
+    _check(lib().ks_batch_steps_done(b, int(job), C.byref(out)))
+    return out.value
+
+
+def ks_batch_destroy(b):
+    return _check(lib().ks_batch_destroy(b))
+
+
 # ---------------------------------------------------------------------------
-# convenience object
+# convenience objects
 # ---------------------------------------------------------------------------
 class Grid:
     """A libks grid object plus its workspace tensor."""
@@ -386,3 +433,76 @@ class Grid:
         self._psi(psi)
         _dev(vion, self.torch.float64, self.N, "vion")
         return ks_energy(self.h, psi, vion, float(t))
+
+
+class Job:
+    """One member of a Batch: a Grid, its states (propagated in place), the
+    ionic potential and the time axis; dipole / norms traces are allocated
+    here with room for max_steps steps."""
+
+    def __init__(self, grid, psi, vion, dt, max_steps, t0=0.0, dipole=True,
+                 norms=True):
+        torch = grid.torch
+        grid._psi(psi)
+        _dev(vion, torch.float64, grid.N, "vion")
+        self.grid, self.psi, self.vion = grid, psi, vion
+        self.dt, self.t0, self.max_steps = float(dt), float(t0), int(max_steps)
+        self.dipole = (torch.zeros((max_steps + 1, 3), dtype=torch.float64,
+                                   device=grid.device) if dipole else None)
+        self.norms = (torch.zeros((max_steps + 1, grid.nk * grid.ns),
+                                  dtype=torch.float64, device=grid.device)
+                      if norms else None)
+
+    def c_struct(self):
+        j = ks_job()
+        j.grid = self.grid.h
+        j.d_psi = self.psi.data_ptr()
+        j.d_vion = self.vion.data_ptr()
+        j.dt = self.dt
+        j.t0 = self.t0
+        j.d_dipole = self.dipole.data_ptr() if self.dipole is not None else None
+        j.d_norms = self.norms.data_ptr() if self.norms is not None else None
+        j.max_steps = self.max_steps
+        return j
+
+
+class Batch:
+    """Jobs propagated together by ks_batch_* on a stream of its own (a
+    captured HIP graph needs a non-default stream).  Work is ordered after
+    the caller's current stream on entry and before it on return."""
+
+    def __init__(self, jobs, use_graph=True):
+        import torch
+        self.torch = torch
+        self.jobs = list(jobs)
+        self.stream = torch.cuda.Stream()
+        self._cur = torch.cuda.current_stream()
+        self.stream.wait_stream(self._cur)
+        self.h = ks_batch_create([j.c_struct() for j in self.jobs],
+                                 self.stream)
+        if not use_graph:
+            ks_batch_set_graph(self.h, 0)
+        self._cur.wait_stream(self.stream)
+
+    def step(self, nsteps=1):
+        cur = self.torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        ks_batch_step(self.h, nsteps)
+        cur.wait_stream(self.stream)
+
+    def steps_done(self, job):
+        return ks_batch_steps_done(self.h, job)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            ks_batch_destroy(self.h)
+            self.h = None
+            for j in self.jobs:
+                if j.grid.h is not None:
+                    j.grid.set_stream(self._cur)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
