@@ -23,6 +23,8 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -112,6 +114,61 @@ def run_gpu(w, precision, steps, warmup, torch):
     return sec, dip, n.cpu().numpy(), prof, g
 
 
+def serving_requests(torch, nreq, steps, rate):
+    """The serving mix: request inputs built on the GPU, then held in pinned
+    host memory as the payload each request brings (copied to HBM on
+    admission)."""
+    from paper_1912_07921_amd import workloads as W
+    from paper_1912_07921_amd.serving import Request
+    arrivals, make = W.c4_stream(nreq, rate=rate, nsteps=steps)
+    reqs = []
+    for i in range(nreq):
+        w = make(i, device="cuda")
+        reqs.append(Request(rid=i, arrival=float(arrivals[i]), spec=w.spec,
+                            vion=w.vion.cpu().pin_memory(),
+                            psi=w.psi0.cpu().pin_memory(), nsteps=steps,
+                            dt=w.dt, kick=w.kick))
+        del w
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return reqs
+
+
+def run_serving(torch, nreq, steps, budget_gib, slots, precision=0):
+    """Saturated run (every request waiting at t = 0) gives the capacity C
+    in requests/s; then Poisson arrivals at 0.8 C.  Each run reports p50/p99
+    per-(request, step) latency and aggregate point-states/s."""
+    from paper_1912_07921_amd.serving import Request, Server
+    from paper_1912_07921_amd import workloads as W
+    base = serving_requests(torch, nreq, steps, 1.0)
+    mean_ns = float(np.mean([r.pts_states for r in base]))
+
+    def fresh(arrivals):
+        return [Request(rid=r.rid, arrival=float(a), spec=r.spec,
+                        vion=r.vion, psi=r.psi, nsteps=r.nsteps, dt=r.dt,
+                        kick=r.kick) for r, a in zip(base, arrivals)]
+
+    out = dict(workload="c4 serving mix: grids {24,32,48,64,80}^3, states "
+                        "{4,...,64}, 2-12 atoms s+p, LDA exchange, kick "
+                        "0.01 z", requests=nreq, steps_per_request=steps,
+               mean_points_x_states=mean_ns, hbm_budget_gib=budget_gib,
+               slots=slots)
+    log(f"serving: saturated run, {nreq} requests x {steps} steps")
+    srv = Server(budget_gib * (1 << 30), max_slots=slots,
+                 precision=precision)
+    sat = srv.run(fresh(np.zeros(nreq)))
+    cap = nreq / sat["wall_s"]
+    out["saturated"] = sat
+    out["capacity_req_per_s"] = cap
+    lam = 0.8 * cap
+    arrivals, _ = W.c4_stream(nreq, rate=lam, nsteps=steps)
+    log(f"serving: Poisson arrivals at {lam:.2f} req/s (0.8 C)")
+    srv = Server(budget_gib * (1 << 30), max_slots=slots,
+                 precision=precision)
+    out["poisson_0.8C"] = dict(rate_req_per_s=lam, **srv.run(fresh(arrivals)))
+    return out
+
+
 def cpu_baseline(w, sample_steps):
     from oracle import oracle
     o = oracle.Oracle(w.spec)
@@ -140,6 +197,13 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 2 GiB device copy (counter calibration)")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-only", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=128)
+    ap.add_argument("--serving-steps", type=int, default=50,
+                    help="ETRS steps per request (the full mix asks 200)")
+    ap.add_argument("--serving-budget-gib", type=float, default=96.0)
+    ap.add_argument("--serving-slots", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the "
@@ -151,6 +215,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.calibrate_copy:
         calibrate_copy(torch)
+        return
+    if args.serving_only:
+        print(json.dumps(run_serving(torch, args.serving_requests,
+                                     args.serving_steps,
+                                     args.serving_budget_gib,
+                                     args.serving_slots)), flush=True)
         return
     log(f"workload {args.workload}: generating inputs")
     w = make_workload(args.workload)
@@ -219,6 +289,12 @@ def main():
         if dip64 is not None:
             mixed["dipole_err_vs_fp64"] = float(abs(dipm - dip64).max())
         out["mixed"] = mixed
+
+    if not args.no_serving:
+        out["serving"] = run_serving(torch, args.serving_requests,
+                                     args.serving_steps,
+                                     args.serving_budget_gib,
+                                     args.serving_slots)
 
     if not args.no_cpu:
         log(f"CPU oracle: {args.cpu_steps} steps")

@@ -192,6 +192,20 @@ int ks_get_launch(const ks_grid *g, int out[4]);
 int ks_profile_begin(ks_grid *g, int capacity);
 int ks_profile_end(ks_grid *g, double out_ms[4], long out_count[4]);
 
+/* Autotuner: time the H.psi pass (the Taylor-term pass that dominates a
+ * step: FP64 psi -> t1, or complex64 t -> t1 in the mixed form) on the
+ * caller's states `d_psi` ([nk][nstates][N] complex128, read only) over
+ * candidate launch shapes (tile rows x z-chunk: the default, the largest
+ * tile that fits 512 threads, an even split of ny, halves and quarters of
+ * it; z-chunks of nz, nz/2, ... down to 8 planes), `reps` timed launches
+ * each, and keep the fastest.  Results of every call are the same for every
+ * shape; only speed changes.  Synchronises the grid's stream.  Writes the
+ * chosen (tile rows, z-chunk) to out_shape and its time per pass in
+ * microseconds to *out_us (either may be NULL).  Overwrites the workspace's
+ * Taylor buffers; needs a workspace. */
+int ks_autotune(ks_grid *g, const void *d_psi, int reps, int out_shape[2],
+                double *out_us);
+
 /* ---- batched form ----
  * Several grid objects ("jobs") propagated together: every Taylor pass of
  * all jobs runs as one persistent H.psi launch over a job table (with one
@@ -211,10 +225,17 @@ typedef struct {
     double *d_dipole;      /* device (max_steps+1)*3 or NULL */
     double *d_norms;       /* device (max_steps+1)*nk*nstates or NULL */
     int max_steps;         /* steps the output buffers have room for */
+    int first_step;        /* steps the job has already taken (0: fresh) */
 } ks_job;
 
-/* Bind the jobs, build the device job table, and compute every job's
- * v(t0), dipole(t0) and norms(t0) (stream-ordered on `stream`). */
+/* Bind the jobs, build the device job table, and compute the v(t0),
+ * dipole(t0) and norms(t0) of every job with first_step 0 (stream-ordered on
+ * `stream`).  A job with first_step = m > 0 resumes a trajectory that an
+ * earlier batch (or ks_propagate_etrs) left after m steps: its states are
+ * psi(t0 + m dt), its grid still holds the potential from the end of step m,
+ * step s of the job uses t = t0 + s dt, and its outputs go to rows m+1, ...
+ * of d_dipole / d_norms.  The result is bitwise that of one uninterrupted
+ * run, so jobs may join and leave (continuous batching). */
 int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
                     ks_batch **out);
 

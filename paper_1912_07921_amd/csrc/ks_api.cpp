@@ -384,7 +384,9 @@ void layout(ks_grid *g)
         off += align256(std::max<size_t>(bytes, 16));
         return o;
     };
-    g->ntiles_max = std::max(g->ntile_y * g->nzc, g->norm_chunks);
+    // norm partials sized for the finest launch shape (one row, one plane
+    // per tile), so that the workspace does not depend on the shape
+    g->ntiles_max = std::max(g->geo.ny * g->geo.nz, g->norm_chunks);
     const size_t ndb = density_blocks((long)N);
     g->lay.t1 = take(tb);
     g->lay.t2 = take(tb);
@@ -921,6 +923,117 @@ int ks_set_launch(ks_grid *g, int tile_rows, int zchunk)
     return KS_OK;
 }
 
+int ks_autotune(ks_grid *g, const void *d_psi, int reps, int out_shape[2],
+                double *out_us)
+{
+    if (!g || !d_psi || reps < 1)
+        return fail(KS_E_ARG, "NULL grid or psi, or reps < 1");
+    int rc = need_ws(g);
+    if (rc)
+        return rc;
+    const Geo &G = g->geo;
+    const int S = g->stot;
+    const bool mx = g->mixed;
+    // candidate tile heights: the largest that fits 512 threads, the one
+    // that splits ny evenly into as many tiles, and halves / quarters
+    const int m = std::max(1, std::min(G.ny, 512 / G.nx));
+    std::vector<int> tys = {m, m - 1, m / 2, m / 4, (m * 3) / 4};
+    {
+        const int nt = (G.ny + m - 1) / m;
+        tys.push_back((G.ny + nt - 1) / nt);
+    }
+    // candidate z-chunks: the whole axis, halves down to 8 planes, and the
+    // default heuristic's choice
+    std::vector<int> zcs;
+    for (int z = G.nz; z >= 8; z = (z + 1) / 2) {
+        zcs.push_back(z);
+        if (z == 1)
+            break;
+    }
+    if (zcs.empty())
+        zcs.push_back(G.nz);
+    const int oldTY = g->TY, oldz = g->zchunk;
+    // valid W for the timed passes: projector coefficients of psi
+    GArgs ga = base_gargs(g);
+    ga.D = g->ws + g->lay.D;
+    ga.in = d_psi;
+    if (g->natoms > 0) {
+        KS_HIP(launch_gather(mx, true, ga, S, g->stream));
+        KS_HIP(launch_kbapply(mx, ga, S, g->stream));
+    }
+    hipEvent_t e0, e1;
+    KS_HIP(hipEventCreate(&e0));
+    KS_HIP(hipEventCreate(&e1));
+    int bestTY = oldTY, bestz = oldz;
+    double best = 1e300;
+    std::vector<std::pair<int, int>> tried;
+    auto run = [&](int ty, int zc) -> int {
+        for (auto &p : tried)
+            if (p.first == ty && p.second == zc)
+                return KS_OK;
+        tried.push_back({ty, zc});
+        if (set_tiles(g, ty, zc) != KS_OK)
+            return KS_OK;            // shape not allowed here: skip it
+        g_err.clear();
+        HArgs a = base_hargs(g);
+        a.v = g->d_v;
+        a.cre = 0.0;
+        a.cim = -0.01;
+        // FP64: psi -> t1.  Mixed: psi -> t2 once (FP64 input), then the
+        // dominant complex64 pass t2 -> t1 is timed.
+        const void *in = d_psi;
+        bool f64 = true;
+        if (mx) {
+            a.in = d_psi;
+            a.out = g->ws + g->lay.t2;
+            KS_HIP(launch_hpsi(kTerm, true, true, a, S, g->stream));
+            in = g->ws + g->lay.t2;
+            f64 = false;
+        }
+        a.in = in;
+        a.out = g->ws + g->lay.t1;
+        KS_HIP(launch_hpsi(kTerm, mx, f64, a, S, g->stream));   // warm
+        KS_HIP(hipEventRecord(e0, g->stream));
+        for (int r = 0; r < reps; ++r)
+            KS_HIP(launch_hpsi(kTerm, mx, f64, a, S, g->stream));
+        KS_HIP(hipEventRecord(e1, g->stream));
+        KS_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        KS_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const double us = 1e3 * ms / reps;
+        if (us < best) {
+            best = us;
+            bestTY = g->TY;
+            bestz = g->zchunk;
+        }
+        return KS_OK;
+    };
+    rc = KS_OK;
+    // the default shape first, then every candidate pair
+    rc = run(oldTY, oldz);
+    for (int ty : tys) {
+        if (rc || ty < 1 || ty > m)
+            continue;
+        for (int zc : zcs)
+            if (!rc)
+                rc = run(ty, zc);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_tiles(g, rc ? oldTY : bestTY, rc ? oldz : bestz);
+    layout(g);
+    if (rc)
+        return rc;
+    g_err.clear();
+    if (out_shape) {
+        out_shape[0] = g->TY;
+        out_shape[1] = g->zchunk;
+    }
+    if (out_us)
+        *out_us = best;
+    return KS_OK;
+}
+
 int ks_get_launch(const ks_grid *g, int out[4])
 {
     if (!g || !out)
@@ -1218,8 +1331,13 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
         if (g->mixed != mixed)
             return fail(KS_E_ARG, "jobs of one batch share the precision");
         if (!std::isfinite(jb.dt) || !std::isfinite(jb.t0) ||
-            jb.max_steps < 0)
-            return fail(KS_E_ARG, "job %d: bad dt, t0 or max_steps", i);
+            jb.max_steps < 0 || jb.first_step < 0 ||
+            jb.first_step > jb.max_steps)
+            return fail(KS_E_ARG, "job %d: bad dt, t0, first_step or "
+                        "max_steps", i);
+        if (jb.first_step > 0 && !g->vloc_set)
+            return fail(KS_E_STATE, "job %d resumes at step %d but its grid "
+                        "holds no potential", i, jb.first_step);
         if (jb.d_dipole && (g->geo.per[0] || g->geo.per[1] || g->geo.per[2]))
             return fail(KS_E_UNSUPPORTED, "job %d: dipole of a periodic "
                         "grid", i);
@@ -1332,10 +1450,14 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
     b->grid_proj = pgrid(std::max({b->off_total[kItemGather],
                                    b->off_total[kItemGatherFin],
                                    b->off_total[kItemApply]}), 2048);
-    // initial potential, dipole and norms of every job (eager)
+    // initial potential, dipole and norms of every job that starts at step
+    // 0; a resumed job keeps the potential its grid holds from the end of
+    // its last step (eager)
     for (int i = 0; i < njobs; ++i) {
         ks_grid *g = b->grids[i];
         const ks_job &jb = b->jobs[i];
+        if (jb.first_step > 0)
+            continue;
         const double h3 = g->geo.h[0] * g->geo.h[1] * g->geo.h[2];
         DArgs a;
         a.geo = g->geo;
@@ -1367,11 +1489,22 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
         }
         g->vloc_set = true;
     }
-    if (launch_step_set(b->d_steps, njobs, 0, b->stream) != hipSuccess) {
+    std::vector<int> first(njobs);
+    for (int i = 0; i < njobs; ++i)
+        first[i] = jobs[i].first_step;
+    int *d_first = nullptr;
+    if ((rc = batch_alloc(b, &d_first, njobs))) {
+        ks_batch_destroy(b);
+        return rc;
+    }
+    if (hipMemcpy(d_first, first.data(), njobs * sizeof(int),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        launch_step_set(b->d_steps, njobs, d_first, b->stream) !=
+            hipSuccess) {
         ks_batch_destroy(b);
         return fail(KS_E_HIP, "batch initialisation failed");
     }
-    b->steps_done.assign(njobs, 0);
+    b->steps_done = first;
     *out = b;
     return KS_OK;
 }

@@ -191,7 +191,7 @@ hipError_t launch_projectors_batch(bool mixed, const BArgs &bg,
                                    const BArgs &bf, const BArgs &ba,
                                    int grid, hipStream_t st);
 hipError_t launch_step_advance(int *const *steps, int njobs, hipStream_t st);
-hipError_t launch_step_set(int *const *steps, int njobs, int value,
+hipError_t launch_step_set(int *const *steps, int njobs, const int *values,
                            hipStream_t st);
 
 }  // namespace ks

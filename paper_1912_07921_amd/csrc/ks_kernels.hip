@@ -1421,11 +1421,11 @@ __global__ void k_step_advance(int *const *steps, int njobs)
         *steps[j] += 1;
 }
 
-__global__ void k_step_set(int *const *steps, int njobs, int value)
+__global__ void k_step_set(int *const *steps, int njobs, const int *values)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j < njobs)
-        *steps[j] = value;
+        *steps[j] = values[j];
 }
 
 int batch_items(int kind, const JobDev &J)
@@ -1563,11 +1563,11 @@ hipError_t launch_step_advance(int *const *steps, int njobs, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_step_set(int *const *steps, int njobs, int value,
+hipError_t launch_step_set(int *const *steps, int njobs, const int *values,
                            hipStream_t st)
 {
     hipLaunchKernelGGL(k_step_set, dim3((njobs + 63) / 64), dim3(64), 0, st,
-                       steps, njobs, value);
+                       steps, njobs, values);
     return hipGetLastError();
 }
 

@@ -61,6 +61,7 @@ class ks_job(C.Structure):
         ("d_dipole", C.c_void_p),
         ("d_norms", C.c_void_p),
         ("max_steps", C.c_int),
+        ("first_step", C.c_int),
     ]
 
 
@@ -91,6 +92,8 @@ EXPORTS = {
     "ks_profile_begin": (C.c_int, [C.c_void_p, C.c_int]),
     "ks_profile_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
                                  C.POINTER(C.c_long)]),
+    "ks_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int,
+                              C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "ks_batch_create": (C.c_int, [C.POINTER(ks_job), C.c_int, C.c_void_p,
                                   C.POINTER(C.c_void_p)]),
     "ks_batch_step": (C.c_int, [C.c_void_p, C.c_int]),
@@ -272,6 +275,14 @@ def ks_profile_end(h):
             enumerate(("hpsi", "gather", "reduce", "kbapply"))}
 
 
+def ks_autotune(h, psi, reps=3):
+    """Returns (tile_rows, zchunk, microseconds per H.psi pass)."""
+    shape = (C.c_int * 2)()
+    us = C.c_double()
+    _check(lib().ks_autotune(h, _ptr(psi), int(reps), shape, C.byref(us)))
+    return shape[0], shape[1], us.value
+
+
 def ks_batch_create(jobs, stream):
     """jobs: sequence of ks_job.  Returns the batch handle."""
     arr = (ks_job * len(jobs))(*jobs)
@@ -305,7 +316,8 @@ def ks_batch_destroy(b):
 class Grid:
     """A libks grid object plus its workspace tensor."""
 
-    def __init__(self, spec, precision=KS_FP64, stream=None, device=None):
+    def __init__(self, spec, precision=KS_FP64, stream=None, device=None,
+                 workspace=True):
         import torch
         self.torch = torch
         self.device = torch.device(device or "cuda")
@@ -314,8 +326,15 @@ class Grid:
         self.nk = len(spec.kw)
         self.ns = int(spec.nstates)
         self.precision = precision
+        self.ws = None
         self.h, self._keep = ks_grid_create(spec, precision, stream)
-        self._alloc_ws()
+        if workspace:
+            self._alloc_ws()
+
+    def ensure_workspace(self):
+        """Lend the workspace now (a Grid made with workspace=False)."""
+        if self.ws is None:
+            self._alloc_ws()
 
     def _alloc_ws(self):
         torch = self.torch
@@ -423,6 +442,12 @@ class Grid:
     def get_launch(self):
         return ks_get_launch(self.h)
 
+    def autotune(self, psi, reps=3):
+        """Pick the fastest launch shape on these states; returns
+        (tile_rows, zchunk, us per pass)."""
+        self._psi(psi)
+        return ks_autotune(self.h, psi, reps)
+
     def profile_begin(self, capacity=100000):
         ks_profile_begin(self.h, capacity)
 
@@ -447,6 +472,7 @@ class Job:
         _dev(vion, torch.float64, grid.N, "vion")
         self.grid, self.psi, self.vion = grid, psi, vion
         self.dt, self.t0, self.max_steps = float(dt), float(t0), int(max_steps)
+        self.first_step = 0        # steps taken in earlier batches
         self.dipole = (torch.zeros((max_steps + 1, 3), dtype=torch.float64,
                                    device=grid.device) if dipole else None)
         self.norms = (torch.zeros((max_steps + 1, grid.nk * grid.ns),
@@ -463,6 +489,7 @@ class Job:
         j.d_dipole = self.dipole.data_ptr() if self.dipole is not None else None
         j.d_norms = self.norms.data_ptr() if self.norms is not None else None
         j.max_steps = self.max_steps
+        j.first_step = self.first_step
         return j
 
 
@@ -494,7 +521,11 @@ class Batch:
         return ks_batch_steps_done(self.h, job)
 
     def close(self):
+        """Free the batch; each job's first_step becomes the steps it has
+        taken, so it can join a later batch and continue."""
         if getattr(self, "h", None) is not None:
+            for i, j in enumerate(self.jobs):
+                j.first_step = ks_batch_steps_done(self.h, i)
             ks_batch_destroy(self.h)
             self.h = None
             for j in self.jobs:

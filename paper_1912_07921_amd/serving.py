@@ -1,0 +1,218 @@
+"""Serving form: continuous batching of many real-time TDDFT propagation
+requests on one GPU.
+
+Requests (a system, its initial states, a number of ETRS steps) arrive over
+time.  A request is admitted, first come first served, when a job slot is
+free and its HBM footprint (states, the grid's workspace, v_ion, its dipole
+and norm traces) fits the budget next to the jobs already resident; its
+states and potentials then stay in HBM until its last step.  All resident
+jobs advance together through one libks batch (ks_batch_*: one persistent
+H.psi launch per Taylor pass over every job, one step captured as a HIP
+graph).  When a job joins or leaves, the batch is rebuilt and every job
+resumes where it stopped; the trajectory of each request is bitwise the
+one it has when propagated alone.
+
+Latency of a (request, step) pair is the wall time from the launch of the
+batch step that advanced it to that step's completion on the GPU.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import ks
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float            # seconds (wall clock) or steps (step clock)
+    spec: object
+    vion: object              # host or device float64 tensor [N]
+    psi: object               # host or device complex128 tensor
+    nsteps: int
+    dt: float
+    kick: float = 0.0
+    # filled in by the server
+    t_admit: float = None
+    t_done: float = None
+    dipole: np.ndarray = None
+    norms: np.ndarray = None
+    final_psi: np.ndarray = None
+    step_latency: list = field(default_factory=list)
+
+    @property
+    def pts_states(self):
+        return self.spec.npoints * self.spec.nk * self.spec.nstates
+
+
+class _Active:
+    def __init__(self, req, grid, job):
+        self.req, self.grid, self.job = req, grid, job
+        self.fp = 0
+
+
+class Server:
+    """Continuous-batching propagation server on one GPU.
+
+    hbm_budget: bytes of HBM the resident jobs may hold together.
+    max_slots: most jobs in one batch.
+    clock: "wall" (arrivals in seconds since run() starts) or "steps"
+        (arrivals in batch steps taken: a deterministic schedule).
+    keep_states: copy each request's final states to the host.
+    tune: run the launch-shape autotuner on each admitted grid.
+    """
+
+    def __init__(self, hbm_budget, max_slots=64, precision=ks.KS_FP64,
+                 clock="wall", keep_states=False, tune=False,
+                 device="cuda"):
+        import torch
+        self.torch = torch
+        self.budget = int(hbm_budget)
+        self.max_slots = int(max_slots)
+        self.precision = precision
+        self.clock = clock
+        self.keep_states = keep_states
+        self.tune = tune
+        self.device = torch.device(device)
+        self.stats = {}
+
+    # ---- footprint ----
+    def _footprint(self, req, grid):
+        N, S = req.spec.npoints, req.spec.nk * req.spec.nstates
+        return (16 * N * S + grid.workspace_bytes + 8 * N +
+                8 * (req.nsteps + 1) * (3 + S) + 4096)
+
+    def _admit(self, req, grid, now):
+        torch = self.torch
+        grid.ensure_workspace()
+        psi = req.psi.to(self.device, non_blocking=True).contiguous()
+        vion = req.vion.to(self.device, non_blocking=True).contiguous()
+        if req.kick:
+            grid.kick(psi, req.kick)
+        if self.tune:
+            grid.autotune(psi)
+        job = ks.Job(grid, psi, vion, req.dt, req.nsteps, t0=0.0,
+                     dipole=not any(req.spec.periodic), norms=True)
+        req.t_admit = now
+        a = _Active(req, grid, job)
+        a.fp = self._footprint(req, grid)
+        del torch
+        return a
+
+    def _retire(self, a, now):
+        r = a.req
+        j = a.job
+        r.t_done = now
+        r.dipole = j.dipole.cpu().numpy() if j.dipole is not None else None
+        r.norms = j.norms.cpu().numpy()
+        if self.keep_states:
+            r.final_psi = j.psi.cpu().numpy()
+        a.grid.close()
+        a.job = None
+
+    # ---- main loop ----
+    def run(self, requests):
+        """Serve `requests` (sorted by arrival) to completion; returns the
+        statistics dict (also in self.stats)."""
+        torch = self.torch
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        waiting = deque()        # (request, grid) arrived, not admitted
+        active = []
+        used = 0
+        batch = None
+        steps_taken = 0
+        rebuilds = 0
+        max_active = 0
+        lat = []
+        work = 0.0
+        busy = 0.0
+        t_start = time.perf_counter()
+
+        def now():
+            if self.clock == "steps":
+                return float(steps_taken)
+            return time.perf_counter() - t_start
+
+        t_first = None
+        while pending or waiting or active:
+            tnow = now()
+            while pending and pending[0].arrival <= tnow:
+                r = pending.popleft()
+                g = ks.Grid(r.spec, precision=self.precision,
+                            device=self.device, workspace=False)
+                fp = self._footprint(r, g)
+                if fp > self.budget:
+                    g.close()
+                    raise ValueError(f"request {r.rid} needs {fp} bytes, "
+                                     f"more than the budget {self.budget}")
+                waiting.append((r, g, fp))
+            changed = False
+            while (waiting and len(active) < self.max_slots and
+                   used + waiting[0][2] <= self.budget):
+                r, g, fp = waiting.popleft()
+                active.append(self._admit(r, g, tnow))
+                used += active[-1].fp
+                changed = True
+            if not active:
+                if self.clock == "steps":
+                    steps_taken += 1      # idle tick
+                elif pending:
+                    time.sleep(max(0.0, min(pending[0].arrival - now(),
+                                            0.001)))
+                continue
+            if changed or batch is None:
+                if batch is not None:
+                    batch.close()
+                batch = ks.Batch([a.job for a in active])
+                rebuilds += 1
+            max_active = max(max_active, len(active))
+            if t_first is None:
+                t_first = time.perf_counter()
+            t0 = time.perf_counter()
+            batch.step(1)
+            torch.cuda.current_stream().synchronize()
+            dt_step = time.perf_counter() - t0
+            busy += dt_step
+            steps_taken += 1
+            done = []
+            for a in active:
+                a.req.step_latency.append(dt_step)
+                lat.append(dt_step)
+                work += 8.0 * a.req.pts_states
+                if batch.steps_done(active.index(a)) >= a.req.nsteps:
+                    done.append(a)
+            if done:
+                batch.close()
+                batch = None
+                tn = now()
+                for a in done:
+                    self._retire(a, tn)
+                    used -= a.fp
+                    active.remove(a)
+        if batch is not None:
+            batch.close()
+        t_end = time.perf_counter()
+        wall = t_end - (t_first if t_first is not None else t_end)
+        lat_ms = 1e3 * np.asarray(lat) if lat else np.zeros(1)
+        reqs = list(requests)
+        waits = [r.t_admit - r.arrival for r in reqs if r.t_admit is not None]
+        self.stats = dict(
+            requests=len(reqs),
+            request_steps=len(lat),
+            batch_steps=int(steps_taken),
+            rebuilds=rebuilds,
+            max_concurrent=max_active,
+            p50_step_ms=float(np.percentile(lat_ms, 50)),
+            p99_step_ms=float(np.percentile(lat_ms, 99)),
+            mean_step_ms=float(lat_ms.mean()),
+            wall_s=wall,
+            gpu_busy_frac=busy / wall if wall > 0 else 0.0,
+            value=work / wall if wall > 0 else 0.0,
+            unit="grid-point·states/s",
+            mean_queue_wait=float(np.mean(waits)) if waits else 0.0,
+        )
+        return self.stats

@@ -313,6 +313,82 @@ def serving_request(rng, grids=(24, 32, 48, 64, 80),
                     nsteps=nsteps, kick=0.01)
 
 
+# --------------------------------------------------------------------------
+# the same request inputs built on a GPU (torch), for serving runs that need
+# hundreds of them: identical random draws, the contractions, envelope,
+# erf potential and orthonormalisation done by torch on `device`.  Values
+# equal the CPU path's up to rounding.
+# --------------------------------------------------------------------------
+def _torch_axes(spec, torch, device):
+    x, y, z = grid_xyz(spec)
+    t = lambda a: torch.from_numpy(a).to(device)
+    return t(x), t(y), t(z)
+
+
+def vion_erf_device(spec, device, rloc=0.5):
+    import torch
+    x, y, z = _torch_axes(spec, torch, device)
+    v = torch.zeros((spec.n[2], spec.n[1], spec.n[0]), dtype=torch.float64,
+                    device=device)
+    lim = 2.0 / (rloc * np.sqrt(np.pi))
+    for a in range(spec.natoms):
+        X, Y, Zc = (float(c) for c in spec.pos[a])
+        r = torch.sqrt((z[:, None, None] - Zc) ** 2 + (y[None, :, None] - Y) ** 2
+                       + (x[None, None, :] - X) ** 2)
+        safe = torch.where(r > 1e-12, r, torch.ones_like(r))
+        f = torch.where(r > 1e-12, torch.special.erf(r / rloc) / safe,
+                        torch.full_like(r, lim))
+        v -= float(spec.Z[a]) * f
+    return v.reshape(-1)
+
+
+def smooth_random_states_device(spec, rng, nstates, device, mmax=3):
+    """smooth_random_states for a zero-boundary grid, built on `device`."""
+    import torch
+    x, y, z = _torch_axes(spec, torch, device)
+    L = [spec.n[i] * spec.h[i] for i in range(3)]
+    ms = torch.arange(-mmax, mmax + 1, dtype=torch.float64, device=device)
+    ex = torch.exp(2j * np.pi * torch.outer(ms, x) / L[0])
+    ey = torch.exp(2j * np.pi * torch.outer(ms, y) / L[1])
+    ez = torch.exp(2j * np.pi * torch.outer(ms, z) / L[2])
+    nm = len(ms)
+    c = (rng.standard_normal((nstates, nm, nm, nm))
+         + 1j * rng.standard_normal((nstates, nm, nm, nm))) / np.sqrt(2)
+    c = torch.from_numpy(c).to(device)
+    t = torch.tensordot(c, ez, dims=([3], [0]))
+    t = torch.tensordot(t, ey, dims=([2], [0]))
+    f = torch.tensordot(t, ex, dims=([1], [0]))
+    R = 0.5 * min(L)
+    w = R / 2
+    env = torch.exp(-(z[:, None, None] ** 2 + y[None, :, None] ** 2
+                      + x[None, None, :] ** 2) / (2 * w * w))
+    psi = (f * env).reshape(nstates, -1)
+    G = (psi @ psi.conj().T) * _grid_dvol(spec)
+    Lc = torch.linalg.cholesky(G)
+    return torch.linalg.solve_triangular(Lc, psi, upper=False)
+
+
+def serving_request_device(rng, device, grids=(24, 32, 48, 64, 80),
+                           states=(4, 8, 16, 32, 64), nsteps=200):
+    """serving_request with v_ion and the states built on `device`:
+    (Workload with vion / psi0 as device tensors)."""
+    n = int(rng.choice(np.array(grids)))
+    ns = int(rng.choice(np.array(states)))
+    natoms = int(rng.integers(2, 13))
+    h = 0.2
+    seed = int(rng.integers(0, 2 ** 31))
+    r = np.random.Generator(np.random.PCG64(seed))
+    pos, Z = _atoms_in_ball(r, natoms, 0.3 * 0.5 * n * h)
+    E = r.uniform(-2.0, 2.0, (natoms, 3))
+    spec = SystemSpec(n=(n, n, n), h=(h,) * 3, nstates=ns, pos=pos, Z=Z,
+                      lmax=np.full(natoms, 1), rc=np.full(natoms, 2.0),
+                      sigma=np.full(natoms, 0.5), E=E, xc=1)
+    v = vion_erf_device(spec, device)
+    psi = smooth_random_states_device(spec, r, ns, device).reshape(1, ns, -1)
+    return Workload(f"req_{n}_{ns}_{natoms}", spec, v, psi, dt=0.005,
+                    nsteps=nsteps, kick=0.01)
+
+
 def c4_stream(nreq=256, rate=1.0, **kw):
     """(arrival times, request generator) for the serving mix."""
     rng = np.random.Generator(np.random.PCG64(SEED_BASE + 4))
@@ -320,8 +396,10 @@ def c4_stream(nreq=256, rate=1.0, **kw):
     arrivals = np.cumsum(gaps) - gaps[0]
     seeds = rng.integers(0, 2 ** 31, nreq)
 
-    def make(i):
+    def make(i, device=None):
         r = np.random.Generator(np.random.PCG64(int(seeds[i])))
+        if device is not None:
+            return serving_request_device(r, device, **kw)
         return serving_request(r, **kw)
 
     return arrivals, make

@@ -191,3 +191,31 @@ def test_batch_error_paths(torch_cuda):
     with pytest.raises(ks.KSError) as e:
         ks.ks_batch_create([], torch.cuda.current_stream())
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_autotune_changes_speed_only(torch_cuda, prec):
+    """The autotuner picks a valid launch shape; H.psi and a propagation are
+    bitwise those of the default shape."""
+    torch = torch_cuda
+    from paper_1912_07921_amd import ks
+    spec, v, psi = W.tiny(n=(40, 27, 33), h=(0.25, 0.25, 0.25), nstates=3,
+                          natoms=3, lmax=2, rc=1.3, sigma=0.4)
+    psi = normalised(spec, psi)
+    ref = ks.Grid(spec, precision=prec)
+    ref.update_vlocal(dev(torch, v))
+    p_ref = dev(torch, psi)
+    h_ref = ref.apply_h(p_ref[0]).cpu().numpy()
+    d_ref, n_ref = ref.propagate_etrs(p_ref, dev(torch, v), 3, 0.01)
+    g = ks.Grid(spec, precision=prec)
+    p = dev(torch, psi)
+    ty, zc, us = g.autotune(p, reps=2)
+    sh = g.get_launch()
+    assert (sh["tile_rows"], sh["zchunk"]) == (ty, zc)
+    assert 1 <= ty <= 27 and 1 <= zc <= 33 and us > 0
+    g.update_vlocal(dev(torch, v))
+    assert np.array_equal(g.apply_h(p[0]).cpu().numpy(), h_ref)
+    d, n = g.propagate_etrs(p, dev(torch, v), 3, 0.01)
+    assert np.array_equal(p.cpu().numpy(), p_ref.cpu().numpy())
+    assert np.array_equal(d.cpu().numpy(), d_ref.cpu().numpy())
+    assert np.array_equal(n.cpu().numpy(), n_ref.cpu().numpy())

@@ -1,0 +1,72 @@
+"""Serving form on the GPU: requests of different grids and state counts
+joining and leaving one continuously rebuilt batch must each end bitwise
+where they end when propagated alone (ks_propagate_etrs), dipole and norm
+traces included; admission respects the slot count and the HBM budget."""
+import numpy as np
+import pytest
+
+from paper_1912_07921_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def make_requests(torch, arrivals, nsteps):
+    from paper_1912_07921_amd.serving import Request
+    reqs = []
+    for i, (t, ns) in enumerate(zip(arrivals, nsteps)):
+        rng = np.random.Generator(np.random.PCG64(W.SEED_BASE + 400 + i))
+        w = W.serving_request(rng, grids=(24, 32), states=(4, 8),
+                              nsteps=ns)
+        reqs.append(Request(rid=i, arrival=float(t), spec=w.spec,
+                            vion=torch.from_numpy(w.vion),
+                            psi=torch.from_numpy(w.psi0.copy()),
+                            nsteps=ns, dt=w.dt, kick=w.kick))
+    return reqs
+
+
+def alone(torch, r):
+    from paper_1912_07921_amd import ks
+    g = ks.Grid(r.spec)
+    psi = r.psi.cuda().contiguous()
+    g.kick(psi, r.kick)
+    d, n = g.propagate_etrs(psi, r.vion.cuda(), r.nsteps, r.dt)
+    return psi.cpu().numpy(), d.cpu().numpy(), n.cpu().numpy()
+
+
+@pytest.mark.parametrize("slots,budget_mb", [(3, 1 << 16), (8, 40)])
+def test_each_request_same_alone_and_in_the_mix(torch_cuda, slots,
+                                                budget_mb):
+    torch = torch_cuda
+    from paper_1912_07921_amd.serving import Server
+    arrivals = [0, 0, 2, 3, 3, 7, 20]
+    nsteps = [6, 9, 4, 7, 5, 3, 2]
+    reqs = make_requests(torch, arrivals, nsteps)
+    srv = Server(budget_mb << 20, max_slots=slots, clock="steps",
+                 keep_states=True)
+    st = srv.run(reqs)
+    assert st["requests"] == len(reqs)
+    assert st["request_steps"] == sum(nsteps)
+    assert st["max_concurrent"] <= slots
+    assert st["rebuilds"] >= 3
+    assert st["p99_step_ms"] >= st["p50_step_ms"] > 0
+    for r in reqs:
+        assert r.t_admit >= r.arrival
+        p, d, n = alone(torch, r)
+        assert np.array_equal(r.final_psi, p), r.rid
+        assert np.array_equal(r.dipole, d), r.rid
+        assert np.array_equal(r.norms, n), r.rid
+
+
+def test_budget_below_one_request_is_refused(torch_cuda):
+    torch = torch_cuda
+    from paper_1912_07921_amd.serving import Server
+    reqs = make_requests(torch, [0], [2])
+    with pytest.raises(ValueError):
+        Server(1 << 20, clock="steps").run(reqs)
