@@ -363,9 +363,9 @@ def smooth_random_states_device(spec, rng, nstates, device, mmax=3):
     env = torch.exp(-(z[:, None, None] ** 2 + y[None, :, None] ** 2
                       + x[None, None, :] ** 2) / (2 * w * w))
     psi = (f * env).reshape(nstates, -1)
-    G = (psi @ psi.conj().T) * _grid_dvol(spec)
-    Lc = torch.linalg.cholesky(G)
-    return torch.linalg.solve_triangular(Lc, psi, upper=False)
+    G = ((psi @ psi.conj().T) * _grid_dvol(spec)).cpu().numpy()
+    Linv = np.linalg.inv(np.linalg.cholesky(G))       # nstates x nstates
+    return torch.from_numpy(Linv).to(device) @ psi
 
 
 def serving_request_device(rng, device, grids=(24, 32, 48, 64, 80),

@@ -195,8 +195,10 @@ def test_batch_error_paths(torch_cuda):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_autotune_changes_speed_only(torch_cuda, prec):
-    """The autotuner picks a valid launch shape; H.psi and a propagation are
-    bitwise those of the default shape."""
+    """The autotuner picks a valid launch shape; H.psi, the propagated
+    states and the dipoles are bitwise those of the default shape.  The norm
+    diagnostics sum per-tile partials, so their last bits follow the tiling
+    (1e-14)."""
     torch = torch_cuda
     from paper_1912_07921_amd import ks
     spec, v, psi = W.tiny(n=(40, 27, 33), h=(0.25, 0.25, 0.25), nstates=3,
@@ -218,4 +220,4 @@ def test_autotune_changes_speed_only(torch_cuda, prec):
     d, n = g.propagate_etrs(p, dev(torch, v), 3, 0.01)
     assert np.array_equal(p.cpu().numpy(), p_ref.cpu().numpy())
     assert np.array_equal(d.cpu().numpy(), d_ref.cpu().numpy())
-    assert np.array_equal(n.cpu().numpy(), n_ref.cpu().numpy())
+    assert np.abs(n.cpu().numpy() - n_ref.cpu().numpy()).max() < 1e-14
