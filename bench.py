@@ -38,13 +38,18 @@ METRIC = ("H·ψ grid-point·states/s + HBM GB/s frac; serving p50/p99 step, "
 
 
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SRC = os.path.join(ROOT, "paper_1912_07921_amd", "csrc",
-                          "ks_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1912_07921_amd", "csrc")
+KERNEL_SOURCES = ["ks_device.h", "ks_internal.h", "ks_hpsi.hip",
+                  "ks_batch.hip", "ks_kernels.hip"]
 
 
 def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sources that determine the device code."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def recorded_traffic(workload):
@@ -86,14 +91,17 @@ def make_workload(name):
     return {"c1": W.c1, "c2": W.c2, "c3": W.c3, "c5": W.c5}[name]()
 
 
-def run_gpu(w, precision, steps, warmup, torch):
-    """(seconds for `steps` steps, dipole trace, profile, grid)."""
+def run_gpu(w, precision, steps, warmup, torch, tune=True):
+    """(seconds for `steps` steps, dipole trace, profile, grid, launch
+    shape)."""
     from paper_1912_07921_amd import ks
     g = ks.Grid(w.spec, precision=precision)
     psi = torch.from_numpy(w.psi0.copy()).cuda()
     vion = torch.from_numpy(w.vion).cuda()
     if w.kick:
         g.kick(psi, w.kick)
+    if tune:
+        g.autotune(psi, reps=3)
     periodic = any(w.spec.periodic)
     if warmup:
         g.propagate_etrs(psi, vion, warmup, w.dt, dipole=not periodic,
@@ -111,7 +119,7 @@ def run_gpu(w, precision, steps, warmup, torch):
     torch.cuda.synchronize()
     sec = e0.elapsed_time(e1) / 1e3
     dip = d.cpu().numpy() if d is not None else None
-    return sec, dip, n.cpu().numpy(), prof, g
+    return sec, dip, n.cpu().numpy(), prof, g, g.get_launch()
 
 
 def serving_requests(torch, nreq, steps, rate):
@@ -134,10 +142,13 @@ def serving_requests(torch, nreq, steps, rate):
     return reqs
 
 
-def run_serving(torch, nreq, steps, budget_gib, slots, precision=0):
-    """Saturated run (every request waiting at t = 0) gives the capacity C
-    in requests/s; then Poisson arrivals at 0.8 C.  Each run reports p50/p99
-    per-(request, step) latency and aggregate point-states/s."""
+def run_serving(torch, nreq, steps, budget_gib, slots):
+    """FP64 and FP32-mixed serving of the same requests.  A saturated run
+    (every request waiting at t = 0) gives the FP64 capacity C in
+    requests/s; both precisions are then run with Poisson arrivals at 0.8 C.
+    Each run reports p50/p99 per-(request, step) latency and aggregate
+    point-states/s; the mixed runs also report their largest dipole
+    deviation from the FP64 run of the same request."""
     from paper_1912_07921_amd.serving import Request, Server
     from paper_1912_07921_amd import workloads as W
     base = serving_requests(torch, nreq, steps, 1.0)
@@ -148,24 +159,37 @@ def run_serving(torch, nreq, steps, budget_gib, slots, precision=0):
                         vion=r.vion, psi=r.psi, nsteps=r.nsteps, dt=r.dt,
                         kick=r.kick) for r, a in zip(base, arrivals)]
 
+    def serve(precision, arrivals):
+        srv = Server(budget_gib * (1 << 30), max_slots=slots,
+                     precision=precision)
+        reqs = fresh(arrivals)
+        st = srv.run(reqs)
+        return st, {r.rid: r.dipole for r in reqs}
+
     out = dict(workload="c4 serving mix: grids {24,32,48,64,80}^3, states "
                         "{4,...,64}, 2-12 atoms s+p, LDA exchange, kick "
                         "0.01 z", requests=nreq, steps_per_request=steps,
                mean_points_x_states=mean_ns, hbm_budget_gib=budget_gib,
                slots=slots)
-    log(f"serving: saturated run, {nreq} requests x {steps} steps")
-    srv = Server(budget_gib * (1 << 30), max_slots=slots,
-                 precision=precision)
-    sat = srv.run(fresh(np.zeros(nreq)))
+    log(f"serving FP64: saturated run, {nreq} requests x {steps} steps")
+    sat, d64 = serve(0, np.zeros(nreq))
     cap = nreq / sat["wall_s"]
-    out["saturated"] = sat
-    out["capacity_req_per_s"] = cap
     lam = 0.8 * cap
     arrivals, _ = W.c4_stream(nreq, rate=lam, nsteps=steps)
-    log(f"serving: Poisson arrivals at {lam:.2f} req/s (0.8 C)")
-    srv = Server(budget_gib * (1 << 30), max_slots=slots,
-                 precision=precision)
-    out["poisson_0.8C"] = dict(rate_req_per_s=lam, **srv.run(fresh(arrivals)))
+    log(f"serving FP64: Poisson arrivals at {lam:.2f} req/s (0.8 C)")
+    poi, _ = serve(0, arrivals)
+    out["fp64"] = {"saturated": sat, "capacity_req_per_s": cap,
+                   "poisson_0.8C": dict(rate_req_per_s=lam, **poi)}
+    log("serving mixed: saturated run")
+    msat, dmx = serve(1, np.zeros(nreq))
+    log(f"serving mixed: Poisson arrivals at {lam:.2f} req/s")
+    mpoi, _ = serve(1, arrivals)
+    err = max(float(np.abs(dmx[k] - d64[k]).max()) for k in d64)
+    out["mixed"] = {"saturated": msat,
+                    "capacity_req_per_s": nreq / msat["wall_s"],
+                    "poisson_0.8C": dict(rate_req_per_s=lam, **mpoi),
+                    "speedup_vs_fp64_saturated": msat["value"] / sat["value"],
+                    "dipole_err_vs_fp64_max": err}
     return out
 
 
@@ -198,6 +222,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 2 GiB device copy (counter calibration)")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch shape (no autotuner)")
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=128)
     ap.add_argument("--serving-steps", type=int, default=50,
@@ -228,7 +254,9 @@ def main():
     units = 8.0 * N * S
 
     log(f"FP64: {args.warmup} warmup + {args.steps} timed steps")
-    sec, dip64, nrm64, prof, _ = run_gpu(w, 0, args.steps, args.warmup, torch)
+    sec, dip64, nrm64, prof, _, shape = run_gpu(w, 0, args.steps,
+                                                args.warmup, torch,
+                                                not args.no_tune)
     value = units * args.steps / sec
     hp_ms, hp_n = prof["hpsi"]
     avg_ms = hp_ms / max(hp_n, 1)
@@ -241,7 +269,8 @@ def main():
                     traffic=traffic,
                     algorithmic_bytes_per_launch=bytes_per_launch,
                     kernel="k_hpsi (H.psi stencil pass)",
-                    kernel_avg_us=round(1e3 * avg_ms, 2))
+                    kernel_avg_us=round(1e3 * avg_ms, 2),
+                    launch_shape=shape)
     kernel_times = {k: dict(total_ms=round(v[0], 3), launches=v[1],
                             avg_us=round(1e3 * v[0] / max(v[1], 1), 2))
                     for k, v in prof.items()}
@@ -275,8 +304,9 @@ def main():
 
     if not args.no_mixed:
         log(f"mixed: {args.warmup} warmup + {args.steps} timed steps")
-        msec, dipm, nrmm, mprof, _ = run_gpu(w, 1, args.steps, args.warmup,
-                                             torch)
+        msec, dipm, nrmm, mprof, _, mshape = run_gpu(w, 1, args.steps,
+                                                     args.warmup, torch,
+                                                     not args.no_tune)
         mh_ms, mh_n = mprof["hpsi"]
         mavg = mh_ms / max(mh_n, 1)
         mach = STEP_BYTES[1] / 8.0 * N * S / (mavg / 1e3) / 1e9
@@ -285,7 +315,8 @@ def main():
                      speedup_vs_fp64=sec / msec,
                      roofline_achieved_GBs=round(mach, 1),
                      roofline_frac=round(mach / HBM_PEAK_GBS, 4),
-                     norm_drift_max=float(abs(nrmm - nrm64).max()))
+                     norm_drift_max=float(abs(nrmm - nrm64).max()),
+                     launch_shape=mshape)
         if dip64 is not None:
             mixed["dipole_err_vs_fp64"] = float(abs(dipm - dip64).max())
         out["mixed"] = mixed

@@ -325,45 +325,59 @@ size_t lds_for(const ks_grid *g, int TY, int zchunk)
                           g->mixed);
 }
 
-// Launch shape: rows per tile TY (a workgroup has about 512 threads) and
-// planes per z-chunk (the full z extent unless that leaves fewer than ~4
-// workgroups per CU).  Either may be forced (> 0) by the caller.
+// Launch shape: rows per tile TY (up to 512 threads, one or two rows per
+// thread) and planes per z-chunk (the full z extent unless that leaves fewer
+// than ~4 workgroups per CU).  Either may be forced (> 0) by the caller.
+bool tile_ok(const ks_grid *g, int TY)
+{
+    const Geo &G = g->geo;
+    if (TY < 1 || TY > G.ny || G.nx * TY > 2 * kRowThreads)
+        return false;
+    const int nthr = hpsi_threads(G.nx, TY);
+    if (nthr > kRowThreads)
+        return false;
+    // the kernel holds at most 16 halo loads per thread and plane (8 when
+    // it marches two rows per thread)
+    const int dyn = 2 * kHalf * G.nx +
+                    (G.per[0] ? 2 * kHalf * (TY + 2 * kHalf) : 0);
+    const int hm = (dyn + nthr - 1) / nthr;
+    return hm <= (hpsi_rpt(G.nx, TY) == 2 ? 8 : 16);
+}
+
 int set_tiles(ks_grid *g, int TY, int zchunk)
 {
     const Geo &G = g->geo;
     if (TY <= 0) {
-        // about 512 threads per workgroup: the 8 halo rows are then at most
-        // twice the tile's own rows
-        TY = std::max(1, std::min(G.ny, 512 / G.nx));
-        while (TY > 1 && lds_for(g, TY, G.nz) > kLdsBudget)
+        // the tallest tile that fits the threads and the default LDS share:
+        // the 8 halo rows are then the smallest fraction of what it loads.
+        // Two rows per thread pay off in FP64; the mixed form keeps one
+        // (its shorter registers already give enough loads in flight).
+        const int rows_per_thread = g->mixed ? 1 : 2;
+        TY = std::max(1, std::min(G.ny,
+                                  rows_per_thread * kRowThreads / G.nx));
+        while (TY > 1 && (!tile_ok(g, TY) ||
+                          lds_for(g, TY, std::min(G.nz, 16)) > kLdsDefault))
             --TY;
     }
-    if (TY > G.ny || G.nx * TY > 512)
+    if (!tile_ok(g, TY))
         return fail(KS_E_ARG, "tile height %d invalid for nx=%d ny=%d", TY,
                     G.nx, G.ny);
     const int ntile_y = (G.ny + TY - 1) / TY;
     if (zchunk <= 0) {
+        // about two workgroups per CU over the launch, chunks of at least
+        // 32 planes (the z-halo of 8 planes stays a small fraction)
         const long per_state = ntile_y;
-        int nzc = (int)std::max<long>(1, 1024 / std::max<long>(1, per_state *
-                                                                   g->stot));
-        nzc = std::min(nzc, std::max(1, G.nz / 16));
+        int nzc = (int)std::max<long>(1, 512 / std::max<long>(1, per_state *
+                                                                  g->stot));
+        nzc = std::min(nzc, std::max(1, G.nz / 32));
         zchunk = (G.nz + nzc - 1) / nzc;
-        while (zchunk > 1 && lds_for(g, TY, zchunk) > kLdsBudget)
+        while (zchunk > 1 && lds_for(g, TY, zchunk) > kLdsDefault)
             zchunk = (zchunk + 1) / 2;
     }
     zchunk = std::min(zchunk, G.nz);
     if (lds_for(g, TY, zchunk) > kLdsBudget)
         return fail(KS_E_UNSUPPORTED, "tile needs %zu bytes of LDS",
                     lds_for(g, TY, zchunk));
-    {
-        // the kernel holds at most 16 halo loads per thread and plane
-        const int nthr = hpsi_threads(G.nx, TY);
-        const int dyn = 2 * kHalf * G.nx +
-                        (G.per[0] ? 2 * kHalf * (TY + 2 * kHalf) : 0);
-        if ((dyn + nthr - 1) / nthr > 16)
-            return fail(KS_E_UNSUPPORTED, "tile height %d too small for "
-                        "nx=%d", TY, G.nx);
-    }
     const int nzc = (G.nz + zchunk - 1) / zchunk;
     if ((long)ntile_y * nzc * g->stot >= (1L << 31))
         return fail(KS_E_UNSUPPORTED, "too many workgroups");
@@ -936,8 +950,10 @@ int ks_autotune(ks_grid *g, const void *d_psi, int reps, int out_shape[2],
     const bool mx = g->mixed;
     // candidate tile heights: the largest that fits 512 threads, the one
     // that splits ny evenly into as many tiles, and halves / quarters
-    const int m = std::max(1, std::min(G.ny, 512 / G.nx));
-    std::vector<int> tys = {m, m - 1, m / 2, m / 4, (m * 3) / 4};
+    const int m = std::max(1, std::min(G.ny, 2 * kRowThreads / G.nx));
+    std::vector<int> tys = {m,         m - 1,         m / 2,
+                            m / 4,     (m * 3) / 4,
+                            std::max(1, std::min(G.ny, kRowThreads / G.nx))};
     {
         const int nt = (G.ny + m - 1) / m;
         tys.push_back((G.ny + nt - 1) / nt);
@@ -1208,7 +1224,7 @@ struct ks_batch {
     std::vector<JobDev> hjobs;
     hipStream_t stream = nullptr;
     bool mixed = false, grad = false;
-    int hm = 2;
+    int hm = 2, rpt = 1;
     size_t lds = 0;
     int grid_hpsi = 0, grid_proj = 0;
     std::vector<void *> owned;
@@ -1259,8 +1275,8 @@ int batch_enqueue_step(ks_batch *b)
                                            batch_args(b, kItemApply, p),
                                            b->grid_proj, st));
             KS_HIP(launch_pass_batch(b->mixed, batch_args(b, kItemHpsi, p),
-                                     b->grad, b->hm, b->lds, b->grid_hpsi,
-                                     st));
+                                     b->grad, b->hm, b->rpt, b->lds,
+                                     b->grid_hpsi, st));
         }
         if (e == 0)
             for (size_t i = 0; i < b->grids.size(); ++i) {
@@ -1380,7 +1396,13 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
         if (g->laser[0] != 0.0)
             b->grad = true;
         b->hm = std::max(b->hm, hpsi_halo_per_thread(g->geo, g->TY, 512));
+        b->rpt = std::max(b->rpt, hpsi_rpt(g->geo.nx, g->TY));
         b->lds = std::max(b->lds, lds_for(g, g->TY, g->zchunk));
+    }
+    if (b->rpt == 2 && b->hm > 8) {
+        ks_batch_destroy(b);
+        return fail(KS_E_UNSUPPORTED, "batch halo too large for two-row "
+                    "tiles");
     }
     int rc;
     std::vector<int *> steps(njobs);

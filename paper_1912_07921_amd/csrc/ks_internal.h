@@ -85,8 +85,14 @@ struct HArgs {
     int TY = 1, zchunk = 1, ntile_y = 1, nzc = 1;
 };
 
-// LDS available to one workgroup of the H.psi kernel.
-constexpr size_t kLdsBudget = 65536;
+// LDS one workgroup may use (gfx950: 160 KiB per workgroup), and the most
+// the default launch shape asks for.
+constexpr size_t kLdsBudget = 163840;
+constexpr size_t kLdsDefault = 98304;
+
+// Threads of one row set of the H.psi kernel: a tile of TY rows with
+// nx * TY above this is marched two rows per thread.
+constexpr int kRowThreads = 512;
 
 struct GArgs {
     Geo geo;
@@ -116,6 +122,7 @@ struct DArgs {
 };
 
 // Launch shape of the H.psi kernel.
+int hpsi_rpt(int nx, int TY);
 int hpsi_threads(int nx, int TY);
 int hpsi_halo_per_thread(const Geo &g, int TY, int nthr);
 size_t hpsi_lds_bytes(int nx, int TY, int zchunk, bool mixed);
@@ -186,7 +193,7 @@ struct BArgs {
 
 int batch_items(int kind, const JobDev &J);
 hipError_t launch_pass_batch(bool mixed, const BArgs &b, bool grad, int hm,
-                             size_t lds, int grid, hipStream_t st);
+                             int rpt, size_t lds, int grid, hipStream_t st);
 hipError_t launch_projectors_batch(bool mixed, const BArgs &bg,
                                    const BArgs &bf, const BArgs &ba,
                                    int grid, hipStream_t st);

@@ -1,716 +1,10 @@
-// gfx950 kernels of the real-time TDDFT hot path.
-//
-// H.psi = -1/2 Lap psi + (v + |A|^2/2) psi - i A.grad psi + V_NL psi on a
-// uniform grid (section "Periodic systems": finite-difference Laplacian and
-// gradient; eq. Hamiltonian_dipole: one-body potential; section
-// "Magneto-optics": non-local pseudopotentials; section "t-SURFF": uniform
-// vector potential), applied to batches of resident states (sections "Memory
-// layout" and "GPUs").
-//
-// Stencil design (HBM bound: 32 B moved per point and state in FP64):
-//  - a workgroup owns a tile of full x-rows (nx x TY) of one state and marches
-//    along z over a chunk of planes;
-//  - each thread keeps the 9-deep z-column of its point in registers, so every
-//    value is loaded from memory once per pass (plus the y-halo rows);
-//  - the current xy plane (with 4 halo rows on each side) is staged in LDS for
-//    the x and y neighbours; x-rows are read as consecutive 16-byte complex
-//    values across the wavefront (coalesced);
-//  - the KB scatter is fused into the single store of the output; the Taylor
-//    recurrence scale, the final Taylor sum, the ETRS predictor and the
-//    density/norm partial sums are fused into the epilogue.
-#include "ks_internal.h"
-
-#include <hip/hip_runtime.h>
+// Projector, density, dipole, norm, kick, Gram and exchange kernels and
+// their launchers.
+#include "ks_device.h"
 
 #include <algorithm>
 
 namespace ks {
-
-// Half-width-4 central weights: Laplacian (c0..c4) and gradient (d1..d4).
-__constant__ double kLap[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0,
-                               8.0 / 315.0, -1.0 / 560.0};
-__constant__ double kGrad[5] = {0.0, 4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0,
-                                -1.0 / 280.0};
-
-template <class R> struct Cplx;
-template <> struct Cplx<double> { using T = double2; };
-template <> struct Cplx<float> { using T = float2; };
-
-template <class V> __device__ __forceinline__ V czero()
-{
-    V r;
-    r.x = 0;
-    r.y = 0;
-    return r;
-}
-template <class V> __device__ __forceinline__ V cmk(double a, double b)
-{
-    V r;
-    r.x = a;
-    r.y = b;
-    return r;
-}
-template <class V> __device__ __forceinline__ V cadd(V a, V b)
-{
-    V r;
-    r.x = a.x + b.x;
-    r.y = a.y + b.y;
-    return r;
-}
-template <class V> __device__ __forceinline__ V csub(V a, V b)
-{
-    V r;
-    r.x = a.x - b.x;
-    r.y = a.y - b.y;
-    return r;
-}
-template <class V, class S> __device__ __forceinline__ V cscale(V a, S s)
-{
-    V r;
-    r.x = a.x * s;
-    r.y = a.y * s;
-    return r;
-}
-template <class V> __device__ __forceinline__ V cmul(V a, V b)
-{
-    V r;
-    r.x = a.x * b.x - a.y * b.y;
-    r.y = a.x * b.y + a.y * b.x;
-    return r;
-}
-// a * conj(b)
-template <class V> __device__ __forceinline__ V cmulc(V a, V b)
-{
-    V r;
-    r.x = a.x * b.x + a.y * b.y;
-    r.y = a.y * b.x - a.x * b.y;
-    return r;
-}
-
-template <class R, class T> __device__ __forceinline__ typename Cplx<R>::T
-ldc(const T *p, long i)
-{
-    T v = p[i];
-    typename Cplx<R>::T r;
-    r.x = (R)v.x;
-    r.y = (R)v.y;
-    return r;
-}
-
-// Streaming stores and loads of data touched once per pass (the H.psi
-// outputs, the Taylor terms read by the final pass): non-temporal, so they
-// do not evict the plane and halo lines that neighbouring workgroups reuse
-// from L2.
-#ifndef KS_NT_STORE
-#define KS_NT_STORE 1
-#endif
-#ifndef KS_NT_LOAD
-#define KS_NT_LOAD 1
-#endif
-typedef double nd2_t __attribute__((ext_vector_type(2)));
-typedef float nf2_t __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ void st_stream(double2 *p, double x, double y)
-{
-#if KS_NT_STORE
-    nd2_t v = {x, y};
-    __builtin_nontemporal_store(v, reinterpret_cast<nd2_t *>(p));
-#else
-    *p = make_double2(x, y);
-#endif
-}
-__device__ __forceinline__ void st_stream(float2 *p, float x, float y)
-{
-#if KS_NT_STORE
-    nf2_t v = {x, y};
-    __builtin_nontemporal_store(v, reinterpret_cast<nf2_t *>(p));
-#else
-    *p = make_float2(x, y);
-#endif
-}
-__device__ __forceinline__ void st_stream(double *p, double x)
-{
-#if KS_NT_STORE
-    __builtin_nontemporal_store(x, p);
-#else
-    *p = x;
-#endif
-}
-__device__ __forceinline__ double2 ld_stream(const double2 *p)
-{
-#if KS_NT_LOAD
-    const nd2_t v = __builtin_nontemporal_load(reinterpret_cast<const nd2_t *>(p));
-    return make_double2(v.x, v.y);
-#else
-    return *p;
-#endif
-}
-__device__ __forceinline__ float2 ld_stream(const float2 *p)
-{
-#if KS_NT_LOAD
-    const nf2_t v = __builtin_nontemporal_load(reinterpret_cast<const nf2_t *>(p));
-    return make_float2(v.x, v.y);
-#else
-    return *p;
-#endif
-}
-
-__device__ __forceinline__ int floordiv(int a, int n)
-{
-    return a >= 0 ? a / n : -((-a + n - 1) / n);
-}
-
-template <class T> __device__ __forceinline__ T wave_sum(T v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-        v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Deterministic block reduction of NV values; result valid in thread 0.
-template <class T, int NV>
-__device__ __forceinline__ void block_sum(T (&v)[NV], T *sbuf)
-{
-    const int tid = threadIdx.x;
-    const int nw = (blockDim.x + 63) >> 6;
-#pragma unroll
-    for (int i = 0; i < NV; ++i)
-        v[i] = wave_sum(v[i]);
-    if ((tid & 63) == 0)
-#pragma unroll
-        for (int i = 0; i < NV; ++i)
-            sbuf[(tid >> 6) * NV + i] = v[i];
-    __syncthreads();
-    if (tid == 0)
-        for (int i = 0; i < NV; ++i) {
-            T s = 0;
-            for (int w = 0; w < nw; ++w)
-                s += sbuf[w * NV + i];
-            v[i] = s;
-        }
-}
-
-
-// ---------------------------------------------------------------------------
-// Bloch phases.  kph[k][a] = exp(i k_a L_a) is tabulated on the host; a wrap
-// by w cells along axis a multiplies by kph[k][a]^w (|w| is 1 except on
-// axes shorter than the stencil).
-// ---------------------------------------------------------------------------
-template <class V>
-__device__ __forceinline__ V phase_pow(const double2 *kph, int axis, int w)
-{
-    V ph = cmk<V>(kph[axis].x, kph[axis].y);
-    if (w < 0) {
-        ph.y = -ph.y;
-        w = -w;
-    }
-    V r = ph;
-    for (int i = 1; i < w; ++i)
-        r = cmul(r, ph);
-    return r;
-}
-
-template <class V>
-__device__ __forceinline__ V shift_phase(const double2 *kph, int code)
-{
-    // lattice shift packed as three signed bytes (x, y, z)
-    V r = cmk<V>(1.0, 0.0);
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        const int t = (int)(signed char)((code >> (8 * ax)) & 0xff);
-        if (t)
-            r = cmul(r, phase_pow<V>(kph, ax, t));
-    }
-    return r;
-}
-
-__device__ __forceinline__ double axis_coord(int n, double h, int per, int i)
-{
-    return per ? i * h : (i - 0.5 * (n - 1)) * h;
-}
-
-// ---------------------------------------------------------------------------
-// Workgroups are handed to the 8 XCDs round robin in launch order; remap the
-// launch index so that each XCD receives a contiguous range of work items
-// (neighbouring y-tiles of the same state, which share halo rows in that
-// XCD's L2).
-// ---------------------------------------------------------------------------
-#ifndef KS_XCD_REMAP
-#define KS_XCD_REMAP 1
-#endif
-__device__ __forceinline__ int xcd_remap(int L, int nblk)
-{
-    if (!KS_XCD_REMAP)
-        return L;
-    constexpr int X = 8;
-    const int per = nblk / X, rem = nblk % X;
-    const int x = L % X, i = L / X;
-    return x * per + min(x, rem) + i;
-}
-
-// ---------------------------------------------------------------------------
-// H.psi with a fused epilogue.  R: arithmetic precision; InT: storage type of
-// the input states; TT: storage type of t-terms (t1, t2, term outputs);
-// GRAD: the velocity-gauge term -i A.grad is present; HM: halo loads per
-// thread and plane.
-//
-// LDS holds the current xy plane of the tile padded by 4 rows above and below
-// and 4 columns left and right: the neighbours' values, zeros (zero
-// boundary; written once) or Bloch-wrapped values.  The stencil reads its x
-// and y neighbours there without branches; the z neighbours come from a
-// per-thread register queue.  Per z-plane: one barrier, two plane buffers
-// alternating.  Every stream is fetched two planes ahead of its use: the
-// halo of plane z+2, the own column of plane z+6, the potential and the KB
-// term of plane z+2 are in flight while plane z is computed.  The KB term
-// V_NL in is precomputed on the hull rows (k_kbapply) and added with one
-// coalesced read.
-// ---------------------------------------------------------------------------
-extern __shared__ double2 smem_d2[];
-
-// One work item of the H.psi pass described by `a`: work item w is
-// (launch state, z-chunk, y-tile).  The whole workgroup takes part.
-template <class R, class InT, class TT, int MODE, bool GRAD, int HM>
-__device__ __forceinline__ void hpsi_item(const HArgs &a, const int w)
-{
-    using V = typename Cplx<R>::T;
-    unsigned char *smem_raw = reinterpret_cast<unsigned char *>(smem_d2);
-
-    const int nx = a.geo.nx, ny = a.geo.ny, nz = a.geo.nz;
-    const int P = nx * ny;
-    const long N = a.geo.N;
-    const int ntiles = a.ntile_y * a.nzc;
-    const int sl = w / ntiles;
-    const int tile = w - sl * ntiles;
-    const int zc = tile / a.ntile_y;
-    const int tile_y = tile - zc * a.ntile_y;
-    const int sg = a.sg0 + sl;
-    const int kk = sg / a.nstates;
-    const double2 *kph = a.kph + 3 * kk;
-    const int perx = a.geo.per[0], pery = a.geo.per[1], perz = a.geo.per[2];
-
-    const int TY = a.TY;
-    const int y0 = tile_y * TY;
-    const int rows = min(TY, ny - y0);
-    const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
-    const int x = tid % nx;
-    const int yl = tid / nx;
-    const bool act = yl < rows;
-    const int y = y0 + (act ? yl : 0);
-    const int z0 = zc * a.zchunk;
-    const int z1 = min(nz, z0 + a.zchunk);
-    const int RS = nx + 2 * kHalf;                  // LDS row stride
-    const int own = (yl + kHalf) * RS + x + kHalf;  // LDS slot of the point
-    const int po = y * nx + x;                      // offset within a plane
-
-    const int plane = (TY + 2 * kHalf) * RS;
-    V *buf0 = reinterpret_cast<V *>(smem_raw);
-    V *buf1 = buf0 + plane;
-    V *sPh = buf1 + plane;        // x/y wrap phases, 81 entries
-    V *sPz = sPh + 81;            // z wrap phases, 9 entries
-    int4 *sRow = reinterpret_cast<int4 *>(sPz + 9);   // hull rows of tile
-
-    const InT *in = reinterpret_cast<const InT *>(a.in) + (size_t)sl * N;
-    const bool proj = a.rowinfo != nullptr;
-    const V *Wst = reinterpret_cast<const V *>(a.W) + (size_t)sl * a.nhull;
-
-    // ---- Bloch phases of x/y wraps by -4..4 cells: sPh[(wy+4)*9 + wx+4],
-    // of z wraps: sPz[wz+4]; hull rows of this tile: sRow[(z-z0)*TY + yl] ----
-    for (int t = tid; t < 81 + 9; t += nthr) {
-        V ph;
-        if (t < 81) {
-            const int wx = t % 9 - 4, wy = t / 9 - 4;
-            ph = cmk<V>(1.0, 0.0);
-            if (wx)
-                ph = cmul(ph, phase_pow<V>(kph, 0, wx));
-            if (wy)
-                ph = cmul(ph, phase_pow<V>(kph, 1, wy));
-        } else {
-            const int wz = t - 81 - 4;
-            ph = wz ? phase_pow<V>(kph, 2, wz) : cmk<V>(1.0, 0.0);
-        }
-        sPh[t] = ph;
-    }
-    if (proj)
-        for (int t = tid; t < (z1 - z0) * TY; t += nthr) {
-            const int zz = z0 + t / TY, r = t % TY;
-            sRow[t] = r < rows ? a.rowinfo[zz * ny + y0 + r]
-                               : make_int4(1, 0, 0, 0);
-        }
-
-    // ---- halo of the padded plane: 8 rows of nx and 8 columns of rows+8.
-    // Both buffers start zeroed, which holds every entry outside a
-    // zero-boundary axis for all planes.  The other ("dynamic") entries are
-    // loaded per plane: the in-grid (or wrapped) halo rows, and on a
-    // periodic x axis the wrapped columns of every row with content.
-    // Dynamic entry d goes to this thread when d = tid + i * nthr, i < HM.
-    // hoff: offset within a plane (-1: none); hpk: LDS slot | phase id << 20
-    // (id 40: no wrap) ----
-    for (int t = tid; t < 2 * plane; t += nthr)
-        buf0[t] = czero<V>();
-    const int u0 = pery ? 0 : max(0, kHalf - y0);   // first dynamic top row
-    const int nup = kHalf - u0;
-    const int nlow = pery ? kHalf : max(0, min(kHalf, ny - (y0 + rows)));
-    const int ndy = (nup + nlow) * nx;
-    const int r_lo = u0, r_hi = rows + kHalf + nlow;
-    const int ndyn = ndy + (perx ? (r_hi - r_lo) * 2 * kHalf : 0);
-    int hoff[HM], hpk[HM];
-#pragma unroll
-    for (int i = 0; i < HM; ++i) {
-        const int d = tid + i * nthr;
-        hoff[i] = -1;
-        hpk[i] = 0;
-        if (d >= ndyn)
-            continue;
-        int r, xs, slot;
-        if (d < ndy) {
-            int hx;
-            if (d < nup * nx) {
-                r = u0 + d / nx;
-                hx = d - (d / nx) * nx;
-            } else {
-                const int d1 = d - nup * nx;
-                r = rows + kHalf + d1 / nx;
-                hx = d1 - (d1 / nx) * nx;
-            }
-            xs = hx;
-            slot = r * RS + hx + kHalf;
-        } else {
-            const int d2 = d - ndy;
-            const int cc = d2 % (2 * kHalf);
-            r = r_lo + d2 / (2 * kHalf);
-            xs = cc < kHalf ? cc - kHalf : nx + cc - kHalf;
-            slot = r * RS + (cc < kHalf ? cc : nx + cc);
-        }
-        int ys = y0 - kHalf + r;
-        int wy = 0, wx = 0;
-        if (ys < 0 || ys >= ny) {
-            wy = floordiv(ys, ny);
-            ys -= wy * ny;
-        }
-        if (xs < 0 || xs >= nx) {
-            wx = floordiv(xs, nx);
-            xs -= wx * nx;
-        }
-        hoff[i] = ys * nx + xs;
-        hpk[i] = slot | (((wy + 4) * 9 + wx + 4) << 20);
-    }
-    __syncthreads();   // zeroed buffers, phase tables and hull rows ready
-
-    // halo entry i of plane zq (in range)
-    auto halo_val = [&](int i, int zq) -> V {
-        V v = ldc<R>(in, (long)zq * P + hoff[i]);
-        const int pid = hpk[i] >> 20;
-        if (pid != 40)
-            v = cmul(v, sPh[pid]);
-        return v;
-    };
-    // own column value of plane zq (any integer)
-    auto col_val = [&](int zq) -> V {
-        if (zq >= 0 && zq < nz)
-            return ldc<R>(in, (long)zq * P + po);
-        if (!perz)
-            return czero<V>();
-        const int wz = floordiv(zq, nz);
-        return cmul(ldc<R>(in, (long)(zq - wz * nz) * P + po),
-                    sPz[wz + 4]);
-    };
-    // projector term at this point of plane zq (z0 <= zq < z1)
-    auto kb_val = [&](int zq) -> V {
-        V v = czero<V>();
-        if (proj && act) {
-            const int4 ri = sRow[(zq - z0) * TY + yl];
-            if (x >= ri.x && x <= ri.y)
-                v = Wst[ri.z + x - ri.x];
-        }
-        return v;
-    };
-    auto v_val = [&](int zq) -> double {
-        return act ? a.v[(long)zq * P + po] : 0.0;
-    };
-
-    // ---- prologue ----
-    V q[2 * kHalf + 1];
-#pragma unroll
-    for (int m = 0; m <= 2 * kHalf; ++m)
-        q[m] = act ? col_val(z0 - kHalf + m) : czero<V>();
-    if (act)
-        buf0[own] = q[kHalf];
-#pragma unroll
-    for (int i = 0; i < HM; ++i)
-        if (hoff[i] >= 0)
-            buf0[hpk[i] & 0xfffff] = halo_val(i, z0);
-    // streams one and two planes ahead
-    V hvA[HM];
-#pragma unroll
-    for (int i = 0; i < HM; ++i)
-        hvA[i] = (z0 + 1 < z1 && hoff[i] >= 0) ? halo_val(i, z0 + 1)
-                                               : czero<V>();
-    V nqA = (z0 + 1 < z1 && act) ? col_val(z0 + kHalf + 1) : czero<V>();
-    V kb = kb_val(z0);
-    V kbA = z0 + 1 < z1 ? kb_val(z0 + 1) : czero<V>();
-    double vc = v_val(z0);
-    double vA = z0 + 1 < z1 ? v_val(z0 + 1) : 0.0;
-
-    R LC[5], GD[5];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-        LC[m] = (R)kLap[m];
-        GD[m] = (R)kGrad[m];
-    }
-    const R ih2x = (R)(1.0 / (a.geo.h[0] * a.geo.h[0]));
-    const R ih2y = (R)(1.0 / (a.geo.h[1] * a.geo.h[1]));
-    const R ih2z = (R)(1.0 / (a.geo.h[2] * a.geo.h[2]));
-    const R c0sum = LC[0] * (ih2x + ih2y + ih2z);
-    const R Ax = (R)(a.A[0] / a.geo.h[0]), Ay = (R)(a.A[1] / a.geo.h[1]),
-            Az = (R)(a.A[2] / a.geo.h[2]);
-    const V cs = cmk<V>(a.cre, a.cim);
-    const double w_occ = (MODE == kFinal || MODE == kFinalPred)
-                             ? a.wocc[sg] : 0.0;
-    double nrm = 0.0;
-    V *cur = buf0, *nxt = buf1;
-    for (int z = z0; z < z1; ++z) {
-        const bool more2 = z + 2 < z1;
-        // two planes ahead: in flight during this plane and the next one
-        V hvB[HM];
-#pragma unroll
-        for (int i = 0; i < HM; ++i)
-            hvB[i] = (more2 && hoff[i] >= 0) ? halo_val(i, z + 2)
-                                             : czero<V>();
-        const V nqB = (z + 1 < z1 && act) ? col_val(z + kHalf + 2)
-                                          : czero<V>();
-        const V kbB = more2 ? kb_val(z + 2) : czero<V>();
-        const double vB = more2 ? v_val(z + 2) : 0.0;
-        __syncthreads();
-        if (act) {
-            const V c = q[kHalf];
-            const V *rp = cur + own;
-            V sx = czero<V>(), sy = czero<V>(), sz = czero<V>();
-            V gx = czero<V>(), gy = czero<V>(), gz = czero<V>();
-#pragma unroll
-            for (int m = 1; m <= kHalf; ++m) {
-                const V xp = rp[m], xn = rp[-m];
-                const V yp = rp[m * RS], yn = rp[-m * RS];
-                const V zp = q[kHalf + m], zn = q[kHalf - m];
-                sx = cadd(sx, cscale(cadd(xp, xn), LC[m]));
-                sy = cadd(sy, cscale(cadd(yp, yn), LC[m]));
-                sz = cadd(sz, cscale(cadd(zp, zn), LC[m]));
-                if constexpr (GRAD) {
-                    gx = cadd(gx, cscale(csub(xp, xn), GD[m]));
-                    gy = cadd(gy, cscale(csub(yp, yn), GD[m]));
-                    gz = cadd(gz, cscale(csub(zp, zn), GD[m]));
-                }
-            }
-            const long g = (long)z * P + po;
-            V lap = cadd(cadd(cscale(sx, ih2x), cscale(sy, ih2y)),
-                         cscale(sz, ih2z));
-            lap = cadd(lap, cscale(c, c0sum));
-            const R vv = (R)(vc + a.a2half);
-            V hp = cadd(cscale(lap, (R)-0.5), cscale(c, vv));
-            if constexpr (GRAD) {
-                // -i A.grad
-                const V gr = cadd(cadd(cscale(gx, Ax), cscale(gy, Ay)),
-                                  cscale(gz, Az));
-                hp.x += gr.y;
-                hp.y -= gr.x;
-            }
-            hp = cadd(hp, kb);
-            if constexpr (MODE == kApply) {
-                st_stream(reinterpret_cast<double2 *>(a.out) +
-                              (size_t)sl * N + g, (double)hp.x, (double)hp.y);
-            } else if constexpr (MODE == kTerm) {
-                const V t = cmul(cs, hp);
-                st_stream(reinterpret_cast<TT *>(a.out) + (size_t)sl * N + g,
-                          t.x, t.y);
-            } else {
-                const V t4 = cmul(cs, hp);
-                const size_t i = (size_t)sl * N + g;
-                const double2 bb = ld_stream(a.base + i);
-                const TT u1 = ld_stream(reinterpret_cast<const TT *>(a.t1) + i);
-                const TT u2 = ld_stream(reinterpret_cast<const TT *>(a.t2) + i);
-                const double re = bb.x + (double)u1.x + (double)u2.x +
-                                  (double)c.x + (double)t4.x;
-                const double im = bb.y + (double)u1.y + (double)u2.y +
-                                  (double)c.y + (double)t4.y;
-                st_stream(reinterpret_cast<double2 *>(a.out) + i, re, im);
-                if constexpr (MODE == kFinalPred) {
-                    const double pr = bb.x + 2.0 * u1.x + 4.0 * u2.x +
-                                      8.0 * c.x + 16.0 * (double)t4.x;
-                    const double pi = bb.y + 2.0 * u1.y + 4.0 * u2.y +
-                                      8.0 * c.y + 16.0 * (double)t4.y;
-                    if (a.npart)
-                        st_stream(a.npart + i, w_occ * (pr * pr + pi * pi));
-                } else {
-                    const double sq = re * re + im * im;
-                    if (a.npart)
-                        st_stream(a.npart + i, w_occ * sq);
-                    nrm += sq;
-                }
-            }
-        }
-        // plane z+1 into the other buffer (free: its last readers passed
-        // this iteration's barrier)
-        if (z + 1 < z1) {
-            if (act)
-                nxt[own] = q[kHalf + 1];
-#pragma unroll
-            for (int i = 0; i < HM; ++i)
-                if (hoff[i] >= 0)
-                    nxt[hpk[i] & 0xfffff] = hvA[i];
-        }
-#pragma unroll
-        for (int m = 0; m < 2 * kHalf; ++m)
-            q[m] = q[m + 1];
-        q[2 * kHalf] = nqA;
-        nqA = nqB;
-#pragma unroll
-        for (int i = 0; i < HM; ++i)
-            hvA[i] = hvB[i];
-        kb = kbA;
-        kbA = kbB;
-        vc = vA;
-        vA = vB;
-        V *t = cur;
-        cur = nxt;
-        nxt = t;
-    }
-    if constexpr (MODE == kFinal) {
-        if (!a.normpart)
-            return;
-        __syncthreads();
-        double vals[1] = {nrm};
-        block_sum<double, 1>(vals, reinterpret_cast<double *>(smem_raw));
-        if (tid == 0)
-            a.normpart[(size_t)sl * ntiles + tile] = vals[0];
-    }
-}
-
-template <class R, class InT, class TT, int MODE, bool GRAD, int HM>
-__global__ __launch_bounds__(512) void k_hpsi(HArgs a)
-{
-    hpsi_item<R, InT, TT, MODE, GRAD, HM>(a, xcd_remap(blockIdx.x, gridDim.x));
-}
-
-// ---------------------------------------------------------------------------
-// KB projectors.  p_j(r) = N_j P_j(r) rad(r) with the real solid harmonics
-// P = (1; x, y, z; xy, yz, zx, x^2 - y^2, 3z^2 - r^2) and
-// rad = exp(-r^2 / (2 sigma^2)) (1 - r^2 / rc^2)^2, evaluated here without
-// N_j (which the coefficients carry).
-// ---------------------------------------------------------------------------
-template <class R>
-__device__ __forceinline__ void proj_shape(double dx, double dy, double dz,
-                                           double r2, double2 ar, int np,
-                                           R p[kMaxProj])
-{
-    const double wv = 1.0 - r2 * ar.y;
-    const R rad = (R)(exp(-r2 * ar.x) * wv * wv);
-    const R X = (R)dx, Y = (R)dy, Z = (R)dz;
-    p[0] = rad;
-    p[1] = rad * X;
-    p[2] = rad * Y;
-    p[3] = rad * Z;
-    p[4] = rad * X * Y;
-    p[5] = rad * Y * Z;
-    p[6] = rad * Z * X;
-    p[7] = rad * (X * X - Y * Y);
-    p[8] = rad * ((R)3 * Z * Z - (X * X + Y * Y + Z * Z));
-    for (int j = np; j < kMaxProj; ++j)
-        p[j] = 0;
-}
-
-// Stage 1 of the gather: S_j = sum_pt P_j(r) rad(r) exp(i k.T) in(pt) over
-// chunks of kGatherChunk sphere points.  A workgroup takes one atom, one
-// chunk and 4 * kGatherSPW states: wavefront w handles kGatherSPW states,
-// each lane a point, so the projector shape is evaluated once per point and
-// wavefront.
-#ifndef KS_GATHER_CHUNK
-#define KS_GATHER_CHUNK 512
-#endif
-#ifndef KS_GATHER_SPW
-#define KS_GATHER_SPW 2
-#endif
-#ifndef KS_APPLY_SPW
-#define KS_APPLY_SPW 4
-#endif
-constexpr int kGatherChunk = KS_GATHER_CHUNK;
-constexpr int kGatherSPW = KS_GATHER_SPW;   // states per wavefront
-constexpr int kGatherStates = 4 * kGatherSPW;
-
-template <class R, class InT>
-__device__ __forceinline__ void gather_item(const GArgs &a, const int at,
-                                            const int grp, const int ch)
-{
-    using V = typename Cplx<R>::T;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int s0 = grp * kGatherStates + wave * kGatherSPW;
-    const int np = a.pj.nproj[at];
-    const int npt = a.pj.npts[at];
-    const long io = a.pj.ioff[at];
-    const double4 ap = a.pj.apos[at];
-    const double2 ar = a.pj.arad[at];
-    const int nx = a.geo.nx, ny = a.geo.ny, nz = a.geo.nz;
-    const double Lx = nx * a.geo.h[0], Ly = ny * a.geo.h[1],
-                 Lz = nz * a.geo.h[2];
-    const int p0 = ch * kGatherChunk;
-    const int p1 = min(npt, p0 + kGatherChunk);
-    R acc[kGatherSPW][2 * kMaxProj];
-#pragma unroll
-    for (int q = 0; q < kGatherSPW; ++q)
-#pragma unroll
-        for (int j = 0; j < 2 * kMaxProj; ++j)
-            acc[q][j] = 0;
-    for (int pt = p0 + lane; pt < p1; pt += 64) {
-        const int g = a.pj.sidx[io + pt];
-        const int pk = a.pj.sxyz[io + pt];
-        const int code = a.pj.sshift[io + pt];
-        const int ix = pk & 0x3ff, iy = (pk >> 10) & 0x3ff, iz = pk >> 20;
-        const int tx = (int)(signed char)(code & 0xff);
-        const int ty = (int)(signed char)((code >> 8) & 0xff);
-        const int tz = (int)(signed char)((code >> 16) & 0xff);
-        const double dx = axis_coord(nx, a.geo.h[0], a.geo.per[0], ix) +
-                          tx * Lx - ap.x;
-        const double dy = axis_coord(ny, a.geo.h[1], a.geo.per[1], iy) +
-                          ty * Ly - ap.y;
-        const double dz = axis_coord(nz, a.geo.h[2], a.geo.per[2], iz) +
-                          tz * Lz - ap.z;
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        R p[kMaxProj];
-        proj_shape<R>(dx, dy, dz, r2, ar, np, p);
-#pragma unroll
-        for (int q = 0; q < kGatherSPW; ++q) {
-            const int sl = s0 + q;
-            if (sl >= a.ns)
-                break;
-            V val = ldc<R>(reinterpret_cast<const InT *>(a.in) +
-                               (size_t)sl * a.geo.N, g);
-            if (code) {
-                const int kk = (a.sg0 + sl) / a.nstates;
-                val = cmul(val, shift_phase<V>(a.kph + 3 * kk, code));
-            }
-#pragma unroll
-            for (int j = 0; j < kMaxProj; ++j) {
-                acc[q][2 * j] += p[j] * val.x;
-                acc[q][2 * j + 1] += p[j] * val.y;
-            }
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < kGatherSPW; ++q) {
-        const int sl = s0 + q;
-#pragma unroll
-        for (int j = 0; j < 2 * kMaxProj; ++j)
-            acc[q][j] = wave_sum(acc[q][j]);
-        if (lane == 0 && sl < a.ns) {
-            V *part = reinterpret_cast<V *>(a.Dpart) +
-                      (((size_t)sl * a.pj.natoms + at) * a.nchunk + ch) *
-                          kMaxProj;
-            for (int j = 0; j < kMaxProj; ++j)
-                part[j] = cmk<V>(acc[q][2 * j], acc[q][2 * j + 1]);
-        }
-    }
-}
 
 template <class R, class InT>
 __global__ __launch_bounds__(256) void k_gather(GArgs a)
@@ -718,117 +12,10 @@ __global__ __launch_bounds__(256) void k_gather(GArgs a)
     gather_item<R, InT>(a, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
-// Stage 2: D[s][a][j] = N_j^2 h^3 E_{a,l(j)} sum over chunks (in order).
-template <class R>
-__device__ __forceinline__ void gather_finalize_item(const GArgs &a,
-                                                     const long i)
-{
-    using V = typename Cplx<R>::T;
-    const long total = (long)a.ns * a.pj.natoms * kMaxProj;
-    if (i >= total)
-        return;
-    const int j = (int)(i % kMaxProj);
-    const long sa = i / kMaxProj;           // s * natoms + atom
-    const int at = (int)(sa % a.pj.natoms);
-    const int nch = (a.pj.npts[at] + kGatherChunk - 1) / kGatherChunk;
-    const V *part = reinterpret_cast<const V *>(a.Dpart) +
-                    (size_t)sa * a.nchunk * kMaxProj + j;
-    R re = 0, im = 0;
-    for (int c = 0; c < nch; ++c) {
-        V v = part[(size_t)c * kMaxProj];
-        re += v.x;
-        im += v.y;
-    }
-    const R e = (j < a.pj.nproj[at]) ? (R)a.pj.EjN2[at * kMaxProj + j]
-                                     : (R)0;
-    reinterpret_cast<V *>(a.D)[i] = cmk<V>(e * re, e * im);
-}
-
 template <class R>
 __global__ __launch_bounds__(256) void k_gather_finalize(GArgs a)
 {
     gather_finalize_item<R>(a, (long)blockIdx.x * blockDim.x + threadIdx.x);
-}
-
-// V_NL in on the hull: W[s][h] = sum over atoms a whose sphere holds hull
-// point h of sum_j P_j(r) rad(r) D[s][a][j] exp(-i k.T).  A workgroup takes
-// a chunk of 64 hull points and 4 * kApplySPW states (kApplySPW per
-// wavefront); atoms in index order (deterministic).
-constexpr int kApplySPW = KS_APPLY_SPW;
-constexpr int kApplyStates = 4 * kApplySPW;
-
-template <class R>
-__device__ __forceinline__ void kbapply_item(const GArgs &a, const int chunk,
-                                             const int grp)
-{
-    using V = typename Cplx<R>::T;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int s0 = grp * kApplyStates + wave * kApplySPW;
-    const int h = chunk * kHullChunk + lane;
-    const bool valid = h < a.pj.nhull;
-    const int nx = a.geo.nx, ny = a.geo.ny, nz = a.geo.nz;
-    const int perx = a.geo.per[0], pery = a.geo.per[1], perz = a.geo.per[2];
-    const double Lx = nx * a.geo.h[0], Ly = ny * a.geo.h[1],
-                 Lz = nz * a.geo.h[2];
-    const int pk = valid ? a.pj.hxyz[h] : 0;
-    const double xc = axis_coord(nx, a.geo.h[0], perx, pk & 0x3ff);
-    const double yc = axis_coord(ny, a.geo.h[1], pery, (pk >> 10) & 0x3ff);
-    const double zc = axis_coord(nz, a.geo.h[2], perz, pk >> 20);
-    V acc[kApplySPW];
-#pragma unroll
-    for (int q = 0; q < kApplySPW; ++q)
-        acc[q] = czero<V>();
-    const int c0 = a.pj.hc_off[chunk], c1 = a.pj.hc_off[chunk + 1];
-    for (int ci = c0; ci < c1; ++ci) {
-        const int at = a.pj.hc_atoms[ci];
-        const double4 ap = a.pj.apos[at];
-        double dx = xc - ap.x, dy = yc - ap.y, dz = zc - ap.z;
-        int mx = 0, my = 0, mz = 0;
-        if (perx) {
-            mx = (int)rint(dx / Lx);
-            dx -= mx * Lx;
-        }
-        if (pery) {
-            my = (int)rint(dy / Ly);
-            dy -= my * Ly;
-        }
-        if (perz) {
-            mz = (int)rint(dz / Lz);
-            dz -= mz * Lz;
-        }
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (!valid || !(r2 < ap.w))
-            continue;
-        const int np = a.pj.nproj[at];
-        R p[kMaxProj];
-        proj_shape<R>(dx, dy, dz, r2, a.pj.arad[at], np, p);
-        const int code = (mx & 0xff) | ((my & 0xff) << 8) | ((mz & 0xff) << 16);
-#pragma unroll
-        for (int q = 0; q < kApplySPW; ++q) {
-            const int sl = s0 + q;
-            if (sl >= a.ns)
-                break;
-            const V *D = reinterpret_cast<const V *>(a.D) +
-                         ((size_t)sl * a.pj.natoms + at) * kMaxProj;
-            V t = czero<V>();
-            for (int j = 0; j < np; ++j)
-                t = cadd(t, cscale(D[j], p[j]));
-            if (code) {
-                const int kk = (a.sg0 + sl) / a.nstates;
-                t = cmul(t, shift_phase<V>(a.kph + 3 * kk, code));
-            }
-            acc[q] = cadd(acc[q], t);
-        }
-    }
-    if (valid)
-#pragma unroll
-        for (int q = 0; q < kApplySPW; ++q) {
-            const int sl = s0 + q;
-            if (sl < a.ns)
-                reinterpret_cast<V *>(a.W)[(size_t)sl * a.pj.nhull + h] =
-                    acc[q];
-        }
 }
 
 template <class R>
@@ -1074,99 +261,6 @@ __global__ __launch_bounds__(256) void k_exchange_partial(Geo G,
         part[blockIdx.x] = acc[0];
 }
 
-// ---------------------------------------------------------------------------
-// launchers
-// ---------------------------------------------------------------------------
-int hpsi_threads(int nx, int TY)
-{
-    const int want = std::max(nx * TY, 64);
-    return ((want + 63) / 64) * 64;
-}
-
-int hpsi_halo_per_thread(const Geo &g, int TY, int nthr)
-{
-    // dynamic halo entries (in-grid rows, and wrapped columns on a
-    // periodic x axis) of a full tile
-    const int dyn = 2 * kHalf * g.nx + (g.per[0] ? 2 * kHalf * (TY + 2 * kHalf)
-                                                  : 0);
-    const int hm = (dyn + nthr - 1) / nthr;
-    return hm <= 2 ? 2 : (hm <= 4 ? 4 : (hm <= 8 ? 8 : 16));
-}
-
-size_t hpsi_lds_bytes(int nx, int TY, int zchunk, bool mixed)
-{
-    const size_t v = mixed ? 8 : 16;
-    return 2 * (size_t)(TY + 2 * kHalf) * (nx + 2 * kHalf) * v + 90 * v +
-           (size_t)zchunk * TY * sizeof(int4);
-}
-
-template <class R, class InT, class TT, int MODE, bool GRAD>
-static hipError_t go_hpsi2(const HArgs &a, int ns, hipStream_t st)
-{
-    const int nthr = hpsi_threads(a.geo.nx, a.TY);
-    const size_t lds = hpsi_lds_bytes(a.geo.nx, a.TY, a.zchunk,
-                                      sizeof(R) == 4);
-    dim3 grid((unsigned)(a.ntile_y * a.nzc * ns));
-    switch (hpsi_halo_per_thread(a.geo, a.TY, nthr)) {
-    case 2:
-        hipLaunchKernelGGL((k_hpsi<R, InT, TT, MODE, GRAD, 2>), grid,
-                           dim3(nthr), lds, st, a);
-        break;
-    case 4:
-        hipLaunchKernelGGL((k_hpsi<R, InT, TT, MODE, GRAD, 4>), grid,
-                           dim3(nthr), lds, st, a);
-        break;
-    case 8:
-        hipLaunchKernelGGL((k_hpsi<R, InT, TT, MODE, GRAD, 8>), grid,
-                           dim3(nthr), lds, st, a);
-        break;
-    default:
-        hipLaunchKernelGGL((k_hpsi<R, InT, TT, MODE, GRAD, 16>), grid,
-                           dim3(nthr), lds, st, a);
-        break;
-    }
-    return hipGetLastError();
-}
-
-template <class R, class InT, class TT, int MODE>
-static hipError_t go_hpsi(const HArgs &a, int ns, hipStream_t st)
-{
-    const bool grad = (a.A[0] != 0.0) || (a.A[1] != 0.0) || (a.A[2] != 0.0);
-    return grad ? go_hpsi2<R, InT, TT, MODE, true>(a, ns, st)
-                : go_hpsi2<R, InT, TT, MODE, false>(a, ns, st);
-}
-
-hipError_t launch_hpsi(int mode, bool mixed, bool in_is_f64, const HArgs &a,
-                       int ns, hipStream_t st)
-{
-    if (ns <= 0)
-        return hipSuccess;
-    if (!mixed) {
-        switch (mode) {
-        case kApply: return go_hpsi<double, double2, double2, kApply>(a, ns, st);
-        case kTerm: return go_hpsi<double, double2, double2, kTerm>(a, ns, st);
-        case kFinal: return go_hpsi<double, double2, double2, kFinal>(a, ns, st);
-        case kFinalPred:
-            return go_hpsi<double, double2, double2, kFinalPred>(a, ns, st);
-        }
-    } else if (in_is_f64) {
-        switch (mode) {
-        case kApply: return go_hpsi<float, double2, float2, kApply>(a, ns, st);
-        case kTerm: return go_hpsi<float, double2, float2, kTerm>(a, ns, st);
-        default: break;
-        }
-    } else {
-        switch (mode) {
-        case kTerm: return go_hpsi<float, float2, float2, kTerm>(a, ns, st);
-        case kFinal: return go_hpsi<float, float2, float2, kFinal>(a, ns, st);
-        case kFinalPred:
-            return go_hpsi<float, float2, float2, kFinalPred>(a, ns, st);
-        default: break;
-        }
-    }
-    return hipErrorInvalidValue;
-}
-
 int gather_chunks(int max_npts)
 {
     return std::max(1, (max_npts + kGatherChunk - 1) / kGatherChunk);
@@ -1302,272 +396,6 @@ hipError_t launch_exchange_partial(const Geo &g, const double *rho,
 {
     hipLaunchKernelGGL(k_exchange_partial, dim3(density_blocks(g.N)),
                        dim3(256), 0, st, g, rho, part);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Batched (multi-job) passes.  One persistent launch covers the work items of
-// every job of a batch: workgroup b takes launch indices b, b + G, b + 2G,
-// ... (G, the grid size, a multiple of 8, so every index of one workgroup
-// stays on its XCD), remapped per XCD as above, and decodes (job, item)
-// from the job's item offset.  The pointers of Taylor pass p (exponential
-// e = (p-1)/4, term j = (p-1)%4 + 1) and the time of the pass come from the
-// job table and the job's device step counter, so a captured step replays
-// unchanged.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int find_job(const int *off, int njobs, int item)
-{
-    int j = 0;
-    while (j + 1 < njobs && item >= off[j + 1])
-        ++j;
-    return j;
-}
-
-// input of Taylor pass p: exponential 0 starts from psi, 1 from psi_half
-__device__ __forceinline__ const void *pass_input(const JobDev &J, int p)
-{
-    const int e = (p - 1) / 4, j = (p - 1) % 4 + 1;
-    if (j == 1)
-        return e == 0 ? (const void *)J.psi : (const void *)J.half;
-    return J.t[j - 2];
-}
-
-__device__ __forceinline__ HArgs pass_hargs(const JobDev &J, int p)
-{
-    HArgs a = J.h;
-    const int e = (p - 1) / 4, j = (p - 1) % 4 + 1;
-    const double4 Av = J.Atab[2 * *J.step + e];   // A(t0 + (step + e) dt)
-    a.A[0] = Av.x;
-    a.A[1] = Av.y;
-    a.A[2] = Av.z;
-    a.a2half = Av.w;
-    a.in = pass_input(J, p);
-    a.v = e == 0 ? J.vcur : (J.xc ? J.vpred : J.vion);
-    a.cre = 0.0;
-    a.cim = -0.5 * J.dt / j;
-    if (j < 4) {
-        a.out = J.t[j - 1];
-    } else {
-        a.out = e == 0 ? (void *)J.half : (void *)J.psi;
-        a.base = e == 0 ? J.psi : J.half;
-        a.t1 = J.t[0];
-        a.t2 = J.t[1];
-        a.npart = e == 0 ? (J.xc ? J.npart : nullptr)
-                         : (J.npart_end ? J.npart : nullptr);
-        a.normpart = e == 1 ? J.normpart_end : nullptr;
-    }
-    return a;
-}
-
-template <class R, class InT, class TT, int MODE, bool GRAD, int HM>
-__global__ __launch_bounds__(512) void k_hpsi_batch(BArgs b)
-{
-    const int total = b.off[b.njobs];
-    for (int L = blockIdx.x; L < total; L += gridDim.x) {
-        const int item = xcd_remap(L, total);
-        const int jb = find_job(b.off, b.njobs, item);
-        const HArgs a = pass_hargs(b.jobs[jb], b.pass);
-        hpsi_item<R, InT, TT, MODE, GRAD, HM>(a, item - b.off[jb]);
-        __syncthreads();   // LDS is reused by the next item
-    }
-}
-
-template <class R, class InT>
-__global__ __launch_bounds__(256) void k_gather_batch(BArgs b)
-{
-    const int total = b.off[b.njobs];
-    for (int L = blockIdx.x; L < total; L += gridDim.x) {
-        const int jb = find_job(b.off, b.njobs, L);
-        const JobDev &J = b.jobs[jb];
-        GArgs a = J.g;
-        a.in = pass_input(J, b.pass);
-        int r = L - b.off[jb];
-        const int ch = r % a.nchunk;
-        r /= a.nchunk;
-        const int ngrp = (a.ns + kGatherStates - 1) / kGatherStates;
-        const int grp = r % ngrp;
-        gather_item<R, InT>(a, r / ngrp, grp, ch);
-    }
-}
-
-template <class R>
-__global__ __launch_bounds__(256) void k_gather_finalize_batch(BArgs b)
-{
-    const int total = b.off[b.njobs];
-    for (int L = blockIdx.x; L < total; L += gridDim.x) {
-        const int jb = find_job(b.off, b.njobs, L);
-        gather_finalize_item<R>(b.jobs[jb].g,
-                                (long)(L - b.off[jb]) * blockDim.x +
-                                    threadIdx.x);
-    }
-}
-
-template <class R>
-__global__ __launch_bounds__(256) void k_kbapply_batch(BArgs b)
-{
-    const int total = b.off[b.njobs];
-    for (int L = blockIdx.x; L < total; L += gridDim.x) {
-        const int jb = find_job(b.off, b.njobs, L);
-        const GArgs &a = b.jobs[jb].g;
-        const int r = L - b.off[jb];
-        kbapply_item<R>(a, r % a.pj.nhchunk, r / a.pj.nhchunk);
-    }
-}
-
-__global__ void k_step_advance(int *const *steps, int njobs)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < njobs)
-        *steps[j] += 1;
-}
-
-__global__ void k_step_set(int *const *steps, int njobs, const int *values)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < njobs)
-        *steps[j] = values[j];
-}
-
-int batch_items(int kind, const JobDev &J)
-{
-    switch (kind) {
-    case kItemHpsi:
-        return J.h.ntile_y * J.h.nzc * J.stot;
-    case kItemGather:
-        return J.g.pj.natoms > 0
-                   ? J.g.pj.natoms *
-                         ((J.stot + kGatherStates - 1) / kGatherStates) *
-                         J.g.nchunk
-                   : 0;
-    case kItemGatherFin:
-        return J.g.pj.natoms > 0
-                   ? (int)(((long)J.stot * J.g.pj.natoms * kMaxProj + 255) /
-                           256)
-                   : 0;
-    case kItemApply:
-        return (J.g.pj.natoms > 0 && J.g.pj.nhull > 0)
-                   ? J.g.pj.nhchunk *
-                         ((J.stot + kApplyStates - 1) / kApplyStates)
-                   : 0;
-    }
-    return 0;
-}
-
-template <class R, class InT, class TT, int MODE, bool GRAD>
-static hipError_t go_hpsi_batch(const BArgs &b, int hm, size_t lds,
-                                int grid, hipStream_t st)
-{
-    switch (hm) {
-    case 2:
-        hipLaunchKernelGGL((k_hpsi_batch<R, InT, TT, MODE, GRAD, 2>),
-                           dim3(grid), dim3(512), lds, st, b);
-        break;
-    case 4:
-        hipLaunchKernelGGL((k_hpsi_batch<R, InT, TT, MODE, GRAD, 4>),
-                           dim3(grid), dim3(512), lds, st, b);
-        break;
-    case 8:
-        hipLaunchKernelGGL((k_hpsi_batch<R, InT, TT, MODE, GRAD, 8>),
-                           dim3(grid), dim3(512), lds, st, b);
-        break;
-    default:
-        hipLaunchKernelGGL((k_hpsi_batch<R, InT, TT, MODE, GRAD, 16>),
-                           dim3(grid), dim3(512), lds, st, b);
-        break;
-    }
-    return hipGetLastError();
-}
-
-template <class R, class InT, class TT, int MODE>
-static hipError_t go_hpsi_batch_g(const BArgs &b, bool grad, int hm,
-                                  size_t lds, int grid, hipStream_t st)
-{
-    return grad ? go_hpsi_batch<R, InT, TT, MODE, true>(b, hm, lds, grid, st)
-                : go_hpsi_batch<R, InT, TT, MODE, false>(b, hm, lds, grid,
-                                                         st);
-}
-
-hipError_t launch_pass_batch(bool mixed, const BArgs &b, bool grad, int hm,
-                             size_t lds, int grid, hipStream_t st)
-{
-    const int j = (b.pass - 1) % 4 + 1, e = (b.pass - 1) / 4;
-    if (!mixed) {
-        using D2 = double2;
-        if (j < 4)
-            return go_hpsi_batch_g<double, D2, D2, kTerm>(b, grad, hm, lds,
-                                                          grid, st);
-        return e == 0 ? go_hpsi_batch_g<double, D2, D2, kFinalPred>(
-                            b, grad, hm, lds, grid, st)
-                      : go_hpsi_batch_g<double, D2, D2, kFinal>(
-                            b, grad, hm, lds, grid, st);
-    }
-    if (j == 1)
-        return go_hpsi_batch_g<float, double2, float2, kTerm>(b, grad, hm,
-                                                              lds, grid, st);
-    if (j < 4)
-        return go_hpsi_batch_g<float, float2, float2, kTerm>(b, grad, hm, lds,
-                                                             grid, st);
-    return e == 0 ? go_hpsi_batch_g<float, float2, float2, kFinalPred>(
-                        b, grad, hm, lds, grid, st)
-                  : go_hpsi_batch_g<float, float2, float2, kFinal>(
-                        b, grad, hm, lds, grid, st);
-}
-
-hipError_t launch_projectors_batch(bool mixed, const BArgs &bg,
-                                   const BArgs &bf, const BArgs &ba,
-                                   int grid, hipStream_t st)
-{
-    const int j = (bg.pass - 1) % 4 + 1;
-    const bool f64 = !mixed || j == 1;
-    if (bg.off_total > 0) {
-        if (!mixed)
-            hipLaunchKernelGGL((k_gather_batch<double, double2>), dim3(grid),
-                               dim3(256), 0, st, bg);
-        else if (f64)
-            hipLaunchKernelGGL((k_gather_batch<float, double2>), dim3(grid),
-                               dim3(256), 0, st, bg);
-        else
-            hipLaunchKernelGGL((k_gather_batch<float, float2>), dim3(grid),
-                               dim3(256), 0, st, bg);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess)
-            return e;
-    }
-    if (bf.off_total > 0) {
-        if (!mixed)
-            hipLaunchKernelGGL((k_gather_finalize_batch<double>), dim3(grid),
-                               dim3(256), 0, st, bf);
-        else
-            hipLaunchKernelGGL((k_gather_finalize_batch<float>), dim3(grid),
-                               dim3(256), 0, st, bf);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess)
-            return e;
-    }
-    if (ba.off_total > 0) {
-        if (!mixed)
-            hipLaunchKernelGGL((k_kbapply_batch<double>), dim3(grid),
-                               dim3(256), 0, st, ba);
-        else
-            hipLaunchKernelGGL((k_kbapply_batch<float>), dim3(grid),
-                               dim3(256), 0, st, ba);
-        return hipGetLastError();
-    }
-    return hipSuccess;
-}
-
-hipError_t launch_step_advance(int *const *steps, int njobs, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_step_advance, dim3((njobs + 63) / 64), dim3(64), 0,
-                       st, steps, njobs);
-    return hipGetLastError();
-}
-
-hipError_t launch_step_set(int *const *steps, int njobs, const int *values,
-                           hipStream_t st)
-{
-    hipLaunchKernelGGL(k_step_set, dim3((njobs + 63) / 64), dim3(64), 0, st,
-                       steps, njobs, values);
     return hipGetLastError();
 }
 

@@ -283,7 +283,9 @@ def test_apply_h_independent_of_launch_shape(torch_cuda, oracle_mod):
     ref = g.apply_h(dpsi).cpu().numpy()
     want = oracle_mod.Oracle(spec).apply_h(v, psi[0])
     assert rel_err(ref, want) < 1e-12
-    for ty, zc in [(1, 0), (2, 5), (3, 33), (7, 1), (12, 16), (12, 0)]:
+    # 12 rows: one row per thread; 20 and 24 rows: two rows per thread
+    for ty, zc in [(1, 0), (2, 5), (3, 33), (7, 1), (12, 16), (12, 0),
+                   (20, 0), (24, 7)]:
         g.set_launch(ty, zc)
         got = g.apply_h(dpsi).cpu().numpy()
         assert np.array_equal(got, ref), (ty, zc)
