@@ -554,3 +554,79 @@ def test_energy_of_oscillator_states(oracle_mod):
     psi = W.ho_states(spec, w, np.random.default_rng(2))[None]
     e = oracle_mod.Oracle(spec).energy(psi, v)
     assert abs(e - (2.0 * 0.75 + 1.75 * 1.25)) < 4e-6
+
+
+# --------------------------------------------------------------------------
+# the stencil weights read off the oracle against the published table
+# --------------------------------------------------------------------------
+def _golden_weights():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        "fd_weights_half_width_4.txt")
+    w = {1: {}, 2: {}}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        d, m, num, den = (int(t) for t in line.split())
+        w[d][m] = num / den
+    return w
+
+
+def test_stencil_weights_match_fornberg_table(oracle_mod):
+    """H applied to a unit impulse on a zero-boundary grid with v = 0 gives
+    -1/2 c_|m| / h^2 at offset m along each axis; with A = (a, 0, 0) the
+    part odd in a gives -i a d_m / h.  Both must equal the printed weights
+    of Fornberg (1988), Table 1, order 8 (tests/golden)."""
+    gw = _golden_weights()
+    n, h = (17, 15, 13), (0.3, 0.4, 0.5)
+    spec = _spec(n, h)
+    o = oracle_mod.Oracle(spec)
+    c = (n[0] // 2, n[1] // 2, n[2] // 2)
+    psi = np.zeros(spec.npoints, np.complex128)
+    idx = lambda x, y, z: (z * n[1] + y) * n[0] + x
+    psi[idx(*c)] = 1.0
+    v = np.zeros(spec.npoints)
+    hp = o.apply_h(v, psi)[0]
+    # centre: -1/2 c0 (1/hx^2 + 1/hy^2 + 1/hz^2)
+    want0 = -0.5 * gw[2][0] * sum(1.0 / hh ** 2 for hh in h)
+    assert abs(hp[idx(*c)].real - want0) < 1e-12 * abs(want0)
+    for ax in range(3):
+        for m in range(1, 5):
+            for sgn in (1, -1):
+                p = list(c)
+                p[ax] += sgn * m
+                got = hp[idx(*p)]
+                want = -0.5 * gw[2][m] / h[ax] ** 2
+                assert abs(got - want) < 1e-12 * abs(want), (ax, m, sgn)
+    a = 0.37
+    hpp = o.apply_h(v, psi, A=np.array([a, 0.0, 0.0]))[0]
+    hpm = o.apply_h(v, psi, A=np.array([-a, 0.0, 0.0]))[0]
+    odd = 0.5 * (hpp - hpm)          # the -i A.grad part
+    for m in range(1, 5):
+        for sgn in (1, -1):
+            p = list(c)
+            p[0] += sgn * m
+            # (-i a d/dx psi)(x0 + s m h) picks psi(x0) with weight -s d_m
+            want = -1j * a * (-sgn * gw[1][m]) / h[0]
+            assert abs(odd[idx(*p)] - want) < 1e-12 * abs(want), (m, sgn)
+    assert abs(odd[idx(*c)]) < 1e-15
+
+
+def test_laser_vector_potential_envelope(oracle_mod):
+    """A(t) vanishes outside [0, T], reaches A0 cos(w T/2) pol at the
+    envelope peak T/2, and A(t)/cos(w t) is symmetric about T/2 (the sin^2
+    envelope)."""
+    T, w0, A0 = 7.0, 0.9, 0.2
+    pol = np.array([0.36, 0.48, 0.8])
+    spec = _spec((6, 6, 6), (0.5, 0.5, 0.5), laser=(A0, w0, T, *pol))
+    o = oracle_mod.Oracle(spec)
+    for t in (-0.5, T + 1e-9, T + 3.0):
+        assert np.all(np.asarray(o.laser_A(t)) == 0.0), t
+    assert np.allclose(o.laser_A(T / 2), A0 * np.cos(w0 * T / 2) * pol,
+                       atol=1e-15)
+    for t in (0.3, 1.7, 2.9):
+        a1 = np.asarray(o.laser_A(t)) / np.cos(w0 * t)
+        a2 = np.asarray(o.laser_A(T - t)) / np.cos(w0 * (T - t))
+        assert np.allclose(a1, a2, rtol=1e-13, atol=1e-16), t
+        # direction is the polarisation
+        assert np.allclose(np.cross(o.laser_A(t), pol), 0.0, atol=1e-16)
