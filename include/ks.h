@@ -170,11 +170,13 @@ int ks_energy(ks_grid *g, const void *d_psi, const double *d_vion, double t,
               double *out_host);
 
 /* Launch shape of the H.psi kernel: a workgroup owns tile_rows full x-rows
- * of one state and marches through zchunk z-planes.  0 keeps the library's
- * choice for that parameter.  KS_E_ARG / KS_E_UNSUPPORTED if the shape does
- * not fit (nx * tile_rows <= 512, LDS); KS_E_OOM (and the workspace is
- * dropped) if the current workspace is too small for it.  Results do not
- * depend on the shape. */
+ * of one state and marches through zchunk z-planes; with nx * tile_rows
+ * above 512 each thread marches two rows.  0 keeps the library's choice for
+ * that parameter.  KS_E_ARG / KS_E_UNSUPPORTED if the shape does not fit
+ * (at most 512 threads of nx * ceil(tile_rows / rows per thread), 160 KiB of
+ * LDS, 16 halo loads per thread).  The workspace size does not depend on the
+ * shape.  States, dipoles and densities do not depend on the shape; the norm
+ * diagnostics sum per-tile partials, so their last bits do. */
 int ks_set_launch(ks_grid *g, int tile_rows, int zchunk);
 
 /* out[0] = tile_rows, out[1] = zchunk, out[2] = workgroups per H.psi launch
@@ -196,8 +198,9 @@ int ks_profile_end(ks_grid *g, double out_ms[4], long out_count[4]);
  * step: FP64 psi -> t1, or complex64 t -> t1 in the mixed form) on the
  * caller's states `d_psi` ([nk][nstates][N] complex128, read only) over
  * candidate launch shapes (tile rows x z-chunk: the default, the largest
- * tile that fits 512 threads, an even split of ny, halves and quarters of
- * it; z-chunks of nz, nz/2, ... down to 8 planes), `reps` timed launches
+ * tile (two rows per thread), the tallest of one row per thread, an even
+ * split of ny, halves and quarters; z-chunks of nz, nz/2, ... down to 8
+ * planes), `reps` timed launches
  * each, and keep the fastest.  Results of every call are the same for every
  * shape; only speed changes.  Synchronises the grid's stream.  Writes the
  * chosen (tile rows, z-chunk) to out_shape and its time per pass in
