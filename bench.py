@@ -91,16 +91,19 @@ def make_workload(name):
     return {"c1": W.c1, "c2": W.c2, "c3": W.c3, "c5": W.c5}[name]()
 
 
-def run_gpu(w, precision, steps, warmup, torch, tune=True):
+def run_gpu(w, precision, steps, warmup, torch, tune=True, shape=None):
     """(seconds for `steps` steps, dipole trace, profile, grid, launch
-    shape)."""
+    shape).  The launch shape is `shape` (tile rows, z-chunk) if given, else
+    the autotuner's choice (tune) or the default."""
     from paper_1912_07921_amd import ks
     g = ks.Grid(w.spec, precision=precision)
     psi = torch.from_numpy(w.psi0.copy()).cuda()
     vion = torch.from_numpy(w.vion).cuda()
     if w.kick:
         g.kick(psi, w.kick)
-    if tune:
+    if shape:
+        g.set_launch(*shape)
+    elif tune:
         g.autotune(psi, reps=3)
     periodic = any(w.spec.periodic)
     if warmup:
@@ -224,6 +227,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shape (no autotuner)")
+    ap.add_argument("--shape", default="",
+                    help="FP64 launch shape 'tile_rows,zchunk' instead of "
+                         "the autotuner's (profiling runs)")
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=128)
     ap.add_argument("--serving-steps", type=int, default=50,
@@ -254,9 +260,11 @@ def main():
     units = 8.0 * N * S
 
     log(f"FP64: {args.warmup} warmup + {args.steps} timed steps")
+    fixed = tuple(int(v) for v in args.shape.split(",")) if args.shape \
+        else None
     sec, dip64, nrm64, prof, _, shape = run_gpu(w, 0, args.steps,
                                                 args.warmup, torch,
-                                                not args.no_tune)
+                                                not args.no_tune, fixed)
     value = units * args.steps / sec
     hp_ms, hp_n = prof["hpsi"]
     avg_ms = hp_ms / max(hp_n, 1)
