@@ -677,6 +677,7 @@ __device__ __forceinline__ void gather_item(const GArgs &a, const int at,
                                             const int grp, const int ch)
 {
     using V = typename Cplx<R>::T;
+    constexpr int U = kGatherChunk / 64;      // points per lane
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int s0 = grp * kGatherStates + wave * kGatherSPW;
@@ -690,20 +691,43 @@ __device__ __forceinline__ void gather_item(const GArgs &a, const int at,
                  Lz = nz * a.geo.h[2];
     const int p0 = ch * kGatherChunk;
     const int p1 = min(npt, p0 + kGatherChunk);
+    // all loads of the chunk are issued before any is used: the point
+    // tables first, then the states at those points
+    int gi[U], pk[U], code[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int pt = p0 + lane + 64 * u;
+        const bool ok = pt < p1;
+        gi[u] = ok ? a.pj.sidx[io + pt] : -1;
+        pk[u] = ok ? a.pj.sxyz[io + pt] : 0;
+        code[u] = ok ? a.pj.sshift[io + pt] : 0;
+    }
+    V val[U][kGatherSPW];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < kGatherSPW; ++q) {
+            const int sl = s0 + q;
+            val[u][q] = (gi[u] >= 0 && sl < a.ns)
+                            ? ldc<R>(reinterpret_cast<const InT *>(a.in) +
+                                         (size_t)sl * a.geo.N, gi[u])
+                            : czero<V>();
+        }
     R acc[kGatherSPW][2 * kMaxProj];
 #pragma unroll
     for (int q = 0; q < kGatherSPW; ++q)
 #pragma unroll
         for (int j = 0; j < 2 * kMaxProj; ++j)
             acc[q][j] = 0;
-    for (int pt = p0 + lane; pt < p1; pt += 64) {
-        const int g = a.pj.sidx[io + pt];
-        const int pk = a.pj.sxyz[io + pt];
-        const int code = a.pj.sshift[io + pt];
-        const int ix = pk & 0x3ff, iy = (pk >> 10) & 0x3ff, iz = pk >> 20;
-        const int tx = (int)(signed char)(code & 0xff);
-        const int ty = (int)(signed char)((code >> 8) & 0xff);
-        const int tz = (int)(signed char)((code >> 16) & 0xff);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (gi[u] < 0)
+            continue;
+        const int ix = pk[u] & 0x3ff, iy = (pk[u] >> 10) & 0x3ff,
+                  iz = pk[u] >> 20;
+        const int tx = (int)(signed char)(code[u] & 0xff);
+        const int ty = (int)(signed char)((code[u] >> 8) & 0xff);
+        const int tz = (int)(signed char)((code[u] >> 16) & 0xff);
         const double dx = axis_coord(nx, a.geo.h[0], a.geo.per[0], ix) +
                           tx * Lx - ap.x;
         const double dy = axis_coord(ny, a.geo.h[1], a.geo.per[1], iy) +
@@ -718,31 +742,44 @@ __device__ __forceinline__ void gather_item(const GArgs &a, const int at,
             const int sl = s0 + q;
             if (sl >= a.ns)
                 break;
-            V val = ldc<R>(reinterpret_cast<const InT *>(a.in) +
-                               (size_t)sl * a.geo.N, g);
-            if (code) {
+            V v = val[u][q];
+            if (code[u]) {
                 const int kk = (a.sg0 + sl) / a.nstates;
-                val = cmul(val, shift_phase<V>(a.kph + 3 * kk, code));
+                v = cmul(v, shift_phase<V>(a.kph + 3 * kk, code[u]));
             }
 #pragma unroll
             for (int j = 0; j < kMaxProj; ++j) {
-                acc[q][2 * j] += p[j] * val.x;
-                acc[q][2 * j + 1] += p[j] * val.y;
+                acc[q][2 * j] += p[j] * v.x;
+                acc[q][2 * j + 1] += p[j] * v.y;
             }
         }
     }
+    // sum over the 64 lanes by a transpose through LDS: column c of the
+    // workgroup (wave, state, projector, re/im) gets the lanes' values as
+    // rows; thread c then adds its column in lane order (deterministic)
+    constexpr int kCols = 4 * kGatherSPW * 2 * kMaxProj;
+    __shared__ R red[kCols][65];
+    __syncthreads();               // the previous item's reads are done
 #pragma unroll
-    for (int q = 0; q < kGatherSPW; ++q) {
-        const int sl = s0 + q;
+    for (int q = 0; q < kGatherSPW; ++q)
 #pragma unroll
         for (int j = 0; j < 2 * kMaxProj; ++j)
-            acc[q][j] = wave_sum(acc[q][j]);
-        if (lane == 0 && sl < a.ns) {
-            V *part = reinterpret_cast<V *>(a.Dpart) +
-                      (((size_t)sl * a.pj.natoms + at) * a.nchunk + ch) *
-                          kMaxProj;
-            for (int j = 0; j < kMaxProj; ++j)
-                part[j] = cmk<V>(acc[q][2 * j], acc[q][2 * j + 1]);
+            red[(wave * kGatherSPW + q) * 2 * kMaxProj + j][lane] = acc[q][j];
+    __syncthreads();
+    const int c = threadIdx.x;
+    if (c < kCols) {
+        R sum = 0;
+        for (int r = 0; r < 64; ++r)
+            sum += red[c][r];
+        const int w = c / (2 * kMaxProj * kGatherSPW);
+        const int q = (c / (2 * kMaxProj)) % kGatherSPW;
+        const int jj = c % (2 * kMaxProj);
+        const int sl = grp * kGatherStates + w * kGatherSPW + q;
+        if (sl < a.ns) {
+            R *part = reinterpret_cast<R *>(a.Dpart) +
+                      2 * ((((size_t)sl * a.pj.natoms + at) * a.nchunk + ch) *
+                           kMaxProj);
+            part[jj] = sum;        // (j, re/im) interleaved as in V
         }
     }
 }
@@ -776,18 +813,33 @@ __device__ __forceinline__ void gather_finalize_item(const GArgs &a,
 // V_NL in on the hull: W[s][h] = sum over atoms a whose sphere holds hull
 // point h of sum_j P_j(r) rad(r) D[s][a][j] exp(-i k.T).  A workgroup takes
 // a chunk of 64 hull points and 4 * kApplySPW states (kApplySPW per
-// wavefront); atoms in index order (deterministic).
+// wavefront); atoms in index order (deterministic).  The atoms of the chunk
+// (centre, radii, projector count) and their coefficients for the
+// workgroup's states are staged in LDS, kApplyAtoms at a time, with one
+// round of coalesced loads, so the atom loop reads only LDS.
 constexpr int kApplySPW = KS_APPLY_SPW;
 constexpr int kApplyStates = 4 * kApplySPW;
+constexpr int kApplyAtoms = 12;
+
+template <class R> struct ApplyLds {
+    using V = typename Cplx<R>::T;
+    double4 apos[kApplyAtoms];
+    double2 arad[kApplyAtoms];
+    int np[kApplyAtoms];
+    V D[kApplyAtoms][kApplyStates][kMaxProj];
+};
 
 template <class R>
 __device__ __forceinline__ void kbapply_item(const GArgs &a, const int chunk,
                                              const int grp)
 {
     using V = typename Cplx<R>::T;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int s0 = grp * kApplyStates + wave * kApplySPW;
+    __shared__ ApplyLds<R> sh;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int sb = grp * kApplyStates;               // first state of the WG
+    const int s0 = sb + wave * kApplySPW;
     const int h = chunk * kHullChunk + lane;
     const bool valid = h < a.pj.nhull;
     const int nx = a.geo.nx, ny = a.geo.ny, nz = a.geo.nz;
@@ -803,45 +855,66 @@ __device__ __forceinline__ void kbapply_item(const GArgs &a, const int chunk,
     for (int q = 0; q < kApplySPW; ++q)
         acc[q] = czero<V>();
     const int c0 = a.pj.hc_off[chunk], c1 = a.pj.hc_off[chunk + 1];
-    for (int ci = c0; ci < c1; ++ci) {
-        const int at = a.pj.hc_atoms[ci];
-        const double4 ap = a.pj.apos[at];
-        double dx = xc - ap.x, dy = yc - ap.y, dz = zc - ap.z;
-        int mx = 0, my = 0, mz = 0;
-        if (perx) {
-            mx = (int)rint(dx / Lx);
-            dx -= mx * Lx;
+    for (int b0 = c0; b0 < c1; b0 += kApplyAtoms) {
+        const int nb = min(kApplyAtoms, c1 - b0);
+        __syncthreads();              // the previous batch has been read
+        if (tid < nb) {
+            const int at = a.pj.hc_atoms[b0 + tid];
+            sh.apos[tid] = a.pj.apos[at];
+            sh.arad[tid] = a.pj.arad[at];
+            sh.np[tid] = a.pj.nproj[at];
         }
-        if (pery) {
-            my = (int)rint(dy / Ly);
-            dy -= my * Ly;
+        for (int t = tid; t < nb * kApplyStates * kMaxProj; t += blockDim.x) {
+            const int i = t / (kApplyStates * kMaxProj);
+            const int r = t - i * (kApplyStates * kMaxProj);
+            const int q = r / kMaxProj, j = r - q * kMaxProj;
+            const int at = a.pj.hc_atoms[b0 + i];
+            const int sl = sb + q;
+            sh.D[i][q][j] = sl < a.ns ? reinterpret_cast<const V *>(a.D)[
+                                            ((size_t)sl * a.pj.natoms + at) *
+                                                kMaxProj + j]
+                                      : czero<V>();
         }
-        if (perz) {
-            mz = (int)rint(dz / Lz);
-            dz -= mz * Lz;
-        }
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (!valid || !(r2 < ap.w))
-            continue;
-        const int np = a.pj.nproj[at];
-        R p[kMaxProj];
-        proj_shape<R>(dx, dy, dz, r2, a.pj.arad[at], np, p);
-        const int code = (mx & 0xff) | ((my & 0xff) << 8) | ((mz & 0xff) << 16);
-#pragma unroll
-        for (int q = 0; q < kApplySPW; ++q) {
-            const int sl = s0 + q;
-            if (sl >= a.ns)
-                break;
-            const V *D = reinterpret_cast<const V *>(a.D) +
-                         ((size_t)sl * a.pj.natoms + at) * kMaxProj;
-            V t = czero<V>();
-            for (int j = 0; j < np; ++j)
-                t = cadd(t, cscale(D[j], p[j]));
-            if (code) {
-                const int kk = (a.sg0 + sl) / a.nstates;
-                t = cmul(t, shift_phase<V>(a.kph + 3 * kk, code));
+        __syncthreads();
+        for (int i = 0; i < nb; ++i) {
+            const double4 ap = sh.apos[i];
+            double dx = xc - ap.x, dy = yc - ap.y, dz = zc - ap.z;
+            int mx = 0, my = 0, mz = 0;
+            if (perx) {
+                mx = (int)rint(dx / Lx);
+                dx -= mx * Lx;
             }
-            acc[q] = cadd(acc[q], t);
+            if (pery) {
+                my = (int)rint(dy / Ly);
+                dy -= my * Ly;
+            }
+            if (perz) {
+                mz = (int)rint(dz / Lz);
+                dz -= mz * Lz;
+            }
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (!valid || !(r2 < ap.w))
+                continue;
+            const int np = sh.np[i];
+            R p[kMaxProj];
+            proj_shape<R>(dx, dy, dz, r2, sh.arad[i], np, p);
+            const int code =
+                (mx & 0xff) | ((my & 0xff) << 8) | ((mz & 0xff) << 16);
+#pragma unroll
+            for (int q = 0; q < kApplySPW; ++q) {
+                const int sl = s0 + q;
+                if (sl >= a.ns)
+                    break;
+                const V *D = sh.D[i][wave * kApplySPW + q];
+                V t = czero<V>();
+                for (int j = 0; j < np; ++j)
+                    t = cadd(t, cscale(D[j], p[j]));
+                if (code) {
+                    const int kk = (a.sg0 + sl) / a.nstates;
+                    t = cmul(t, shift_phase<V>(a.kph + 3 * kk, code));
+                }
+                acc[q] = cadd(acc[q], t);
+            }
         }
     }
     if (valid)

@@ -9,8 +9,19 @@
 
 namespace ks {
 
+// Occupancy hint (waves per SIMD the register allocation must allow); 0
+// leaves the choice to the compiler.
+#ifndef KS_HPSI_MIN_WAVES
+#define KS_HPSI_MIN_WAVES 0
+#endif
+#if KS_HPSI_MIN_WAVES > 0
+#define KS_HPSI_ATTR __attribute__((amdgpu_waves_per_eu(KS_HPSI_MIN_WAVES)))
+#else
+#define KS_HPSI_ATTR
+#endif
+
 template <class R, class InT, class TT, int MODE, bool GRAD, int HM, int RPT>
-__global__ __launch_bounds__(512) void k_hpsi(HArgs a)
+__global__ __launch_bounds__(512) KS_HPSI_ATTR void k_hpsi(HArgs a)
 {
     hpsi_item<R, InT, TT, MODE, GRAD, HM, RPT>(a,
                                                xcd_remap(blockIdx.x,
