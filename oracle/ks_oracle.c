@@ -62,6 +62,12 @@
  *       correlation.
  *   R8  Density n = sum_k w_k sum_s f_s |psi_ks|^2; dipole d = h^3 sum r n.
  *   R9  Kick: psi <- exp(i kappa z) psi.
+ *   R10 CFM4 (the order-four commutator-free Magnus propagator): H(t1),
+ *       H(t2) take A(t_i) exactly and the local potential extrapolated
+ *       from the potentials at the ends of the most recent steps (cubic
+ *       through four points; through the points available in the first
+ *       three steps of a run, so the run starts at lower order).  Each
+ *       exponential is Taylor-4 of a H(t1) + b H(t2) with step dt.
  *
  * Layout: psi is complex double, [nk][nstates][nz][ny][nx], x fastest.
  */
@@ -639,6 +645,122 @@ int orc_propagate_etrs(const orc_system *S, cplx *psi, const double *vion,
     free(u);
     free(half);
     free(pred);
+    return 0;
+}
+
+/*
+ * Lagrange weights for the value at x of the polynomial through the points
+ * x_j = -j (j = 0 .. h-1), i.e. extrapolation from the h most recent steps
+ * (unit step) to the offset x: L_j(x) = prod_{m != j} (x + m) / (m - j).
+ */
+static void lagrange_back(int h, double x, double *L)
+{
+    for (int j = 0; j < h; ++j) {
+        double w = 1.0;
+        for (int m = 0; m < h; ++m)
+            if (m != j)
+                w *= (x + m) / (double)(m - j);
+        L[j] = w;
+    }
+}
+
+/*
+ * CFM4 propagation (section "New propagators for real-time TDDFT", the
+ * order-four commutator-free Magnus expansion with two exponentials):
+ *   psi(t+dt) = exp(-i dt (a1 H(t1) + a2 H(t2)))
+ *               exp(-i dt (a2 H(t1) + a1 H(t2))) psi(t),
+ *   a1,2 = (3 -+ 2 sqrt 3)/12, t1,2 = t + (1/2 -+ sqrt(3)/6) dt.
+ * H(t_i) uses A(t_i) exactly and a local potential extrapolated from the
+ * potentials v(t), v(t - dt), ... of the most recent steps (up to four
+ * points: the cubic through them; fewer at the start of a run, R10-CFM).
+ * Each exponential is a Taylor-4 series (R5) of the operator
+ * a H(t1) + b H(t2) applied literally as a H(t1) psi + b H(t2) psi, with
+ * the step dt.  v is rebuilt from n(psi) at the end of every step.
+ * Arguments as for orc_propagate_etrs.
+ */
+int orc_propagate_cfm4(const orc_system *S, cplx *psi, const double *vion,
+                       int nsteps, double dt, double t0, double *dipole,
+                       double *norms)
+{
+    long N = S->N;
+    int ns = S->d.nstates, nk = S->d.nk;
+    size_t M = (size_t)ns * N;
+    const double a1 = (3.0 - 2.0 * sqrt(3.0)) / 12.0;
+    const double a2 = (3.0 + 2.0 * sqrt(3.0)) / 12.0;
+    const double c1 = 0.5 - sqrt(3.0) / 6.0, c2 = 0.5 + sqrt(3.0) / 6.0;
+    double *rho = malloc(sizeof(double) * N);
+    double *hist = malloc(sizeof(double) * N * 4);   /* v(t - j dt) */
+    double *v1 = malloc(sizeof(double) * N);
+    double *v2 = malloc(sizeof(double) * N);
+    cplx *term = malloc(sizeof(cplx) * M);
+    cplx *h1 = malloc(sizeof(cplx) * M);
+    cplx *h2 = malloc(sizeof(cplx) * M);
+    cplx *acc = malloc(sizeof(cplx) * M);
+    int nhist = 0;
+
+    orc_density(S, psi, rho);
+    orc_vlocal(S, vion, S->d.xc ? rho : NULL, hist);
+    nhist = 1;
+    if (dipole)
+        orc_dipole(S, rho, dipole);
+    if (norms)
+        orc_norms(S, psi, norms);
+    for (int step = 0; step < nsteps; ++step) {
+        double t = t0 + step * dt;
+        double A1[3], A2[3], L1[4], L2[4];
+        orc_laser_A(S, t + c1 * dt, A1);
+        orc_laser_A(S, t + c2 * dt, A2);
+        lagrange_back(nhist, c1, L1);
+        lagrange_back(nhist, c2, L2);
+        for (long g = 0; g < N; ++g) {
+            double s1 = 0.0, s2 = 0.0;
+            for (int j = 0; j < nhist; ++j) {
+                s1 += L1[j] * hist[(size_t)j * N + g];
+                s2 += L2[j] * hist[(size_t)j * N + g];
+            }
+            v1[g] = s1;
+            v2[g] = s2;
+        }
+        /* the right-hand exponential first: weights (a2, a1), then (a1, a2) */
+        const double wa[2] = {a2, a1}, wb[2] = {a1, a2};
+        for (int e = 0; e < 2; ++e) {
+            for (int k = 0; k < nk; ++k) {
+                cplx *pk = psi + (size_t)k * M;
+                memcpy(term, pk, sizeof(cplx) * M);
+                memcpy(acc, pk, sizeof(cplx) * M);
+                for (int p = 1; p <= 4; ++p) {
+                    orc_apply_h(S, v1, k, A1, ns, term, h1);
+                    orc_apply_h(S, v2, k, A2, ns, term, h2);
+                    for (size_t i = 0; i < M; ++i) {
+                        term[i] = (-I * dt / p) * (wa[e] * h1[i] +
+                                                   wb[e] * h2[i]);
+                        acc[i] += term[i];
+                    }
+                }
+                memcpy(pk, acc, sizeof(cplx) * M);
+            }
+        }
+        /* v(t + dt) from the new density, newest first in the history */
+        for (int j = (nhist < 4 ? nhist : 3); j > 0; --j)
+            memcpy(hist + (size_t)j * N, hist + (size_t)(j - 1) * N,
+                   sizeof(double) * N);
+        if (nhist < 4)
+            ++nhist;
+        orc_density(S, psi, rho);
+        orc_vlocal(S, vion, S->d.xc ? rho : NULL, hist);
+        if (dipole)
+            orc_dipole(S, rho, dipole + 3 * (step + 1));
+        if (norms)
+            orc_norms(S, psi, norms + (size_t)(step + 1) * nk * ns);
+    }
+    free(rho);
+    free(hist);
+    free(v1);
+    free(v2);
+    free(term);
+    free(h1);
+    free(h2);
+    free(acc);
     return 0;
 }
 

@@ -85,6 +85,9 @@ def _load():
         lib.orc_propagate_etrs.restype = C.c_int
         lib.orc_propagate_etrs.argtypes = [vp, vp, vp, C.c_int, C.c_double,
                                            C.c_double, vp, vp]
+        lib.orc_propagate_cfm4.restype = C.c_int
+        lib.orc_propagate_cfm4.argtypes = [vp, vp, vp, C.c_int, C.c_double,
+                                           C.c_double, vp, vp]
         lib.orc_num_threads.restype = C.c_int
         _lib = lib
     return _lib
@@ -259,6 +262,22 @@ class Oracle:
         dip = np.zeros((nsteps + 1, 3))
         nrm = np.zeros((nsteps + 1, self.nk * self.ns))
         rc = self._lib.orc_propagate_etrs(self._h, _ptr(psi), _ptr(vion),
+                                          int(nsteps), float(dt), float(t0),
+                                          _ptr(dip), _ptr(nrm))
+        if rc != 0:
+            raise RuntimeError("oracle propagation failed")
+        return psi, dip, nrm
+
+    def propagate_cfm4(self, psi, vion, nsteps, dt, t0=0.0):
+        """CFM4 (two Taylor-4 exponentials of Magnus-combined
+        Hamiltonians per step).  Returns (psi, dipole, norms) as
+        propagate_etrs."""
+        psi = self._c128(psi, self.nk * self.ns).reshape(
+            self.nk, self.ns, self.N).copy()
+        vion = _f64(vion)
+        dip = np.zeros((nsteps + 1, 3))
+        nrm = np.zeros((nsteps + 1, self.nk * self.ns))
+        rc = self._lib.orc_propagate_cfm4(self._h, _ptr(psi), _ptr(vion),
                                           int(nsteps), float(dt), float(t0),
                                           _ptr(dip), _ptr(nrm))
         if rc != 0:

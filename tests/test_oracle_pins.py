@@ -630,3 +630,89 @@ def test_laser_vector_potential_envelope(oracle_mod):
         assert np.allclose(a1, a2, rtol=1e-13, atol=1e-16), t
         # direction is the polarisation
         assert np.allclose(np.cross(o.laser_A(t), pol), 0.0, atol=1e-16)
+
+
+# --------------------------------------------------------------------------
+# CFM4 (section "New propagators for real-time TDDFT": order-four
+# commutator-free Magnus expansion with two exponentials)
+# --------------------------------------------------------------------------
+def test_cfm4_closed_form_for_a_constant_hamiltonian(oracle_mod):
+    """With H constant, a1 + a2 = 1/2 makes each CFM4 exponential
+    exp(-i dt/2 H); in Taylor-4 an eigenvector is multiplied by
+    T4(-i E dt/2)^2 per step."""
+    n, h, w, dt, nsteps = 24, 0.3, 0.5, 0.01, 20
+    U = _discrete_ho_eigvecs(oracle_mod, n, h, w)
+    g0, g1 = U[:, 0], U[:, 1]
+    states = [np.einsum("z,y,x->zyx", g0, g0, g0),
+              np.einsum("z,y,x->zyx", g0, g1, g0)]
+    spec = _spec((n, n, n), (h, h, h), nstates=2, xc=0)
+    v = W.vion_harmonic(spec, w)
+    psi0 = np.array([s.reshape(-1) / np.sqrt(np.sum(s * s) * h ** 3)
+                     for s in states]).astype(np.complex128)
+    psi0 *= np.exp(1j * np.array([0.9, -0.4]))[:, None]
+    o = oracle_mod.Oracle(spec)
+    E = np.real(np.sum(psi0.conj() * o.apply_h(v, psi0), axis=1)) * h ** 3
+    psi, dip, nrm = o.propagate_cfm4(psi0, v, nsteps, dt)
+    fac = _t4(-1j * E * dt / 2) ** (2 * nsteps)
+    assert np.abs(psi[0] - fac[:, None] * psi0).max() < 1e-12
+
+
+def _cfm4_errors(oracle_mod, xc, steps_list, T=0.4):
+    spec, v, psi = W.tiny(n=(7, 6, 6), h=(0.5, 0.5, 0.5), nstates=2,
+                          natoms=1, lmax=1, rc=1.2, sigma=0.4, xc=xc,
+                          laser=(0.6, 2.5, 3.0, 0.3, 0.0, 0.9))
+    o = oracle_mod.Oracle(spec)
+    h3 = np.prod(spec.h)
+    psi = psi / np.sqrt(np.sum(np.abs(psi) ** 2, axis=2, keepdims=True) * h3)
+    v = 0.2 * v
+    t0 = 0.7
+    ref = _rk4_reference_t0(o, psi, v, T / 1600, 1600, t0)
+    errs = []
+    for nsteps in steps_list:
+        out = o.propagate_cfm4(psi, v, nsteps, T / nsteps, t0)[0]
+        errs.append(np.sqrt(np.sum(np.abs(out - ref) ** 2) * h3))
+    return errs
+
+
+def _rk4_reference_t0(o, psi0, vion, dt, nsteps, t0):
+    nk, ns, N = psi0.shape
+
+    def rhs(psi, t):
+        rho = o.density(psi)
+        v = o.vlocal(vion, rho)
+        A = o.laser_A(t)
+        out = np.empty_like(psi)
+        for k in range(nk):
+            out[k] = -1j * o.apply_h(v, psi[k], k=k, A=A)
+        return out
+
+    psi = psi0.copy()
+    for i in range(nsteps):
+        t = t0 + i * dt
+        k1 = rhs(psi, t)
+        k2 = rhs(psi + 0.5 * dt * k1, t + 0.5 * dt)
+        k3 = rhs(psi + 0.5 * dt * k2, t + 0.5 * dt)
+        k4 = rhs(psi + dt * k3, t + dt)
+        psi = psi + dt / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    return psi
+
+
+def test_cfm4_is_fourth_order_for_a_driven_linear_system(oracle_mod):
+    """Time-dependent H (laser, no density dependence): the error against
+    an independent RK4 solution at a tiny step falls by about 2^4 per
+    halving of dt; an error in a1, a2, t1, t2 or in the order of the two
+    exponentials leaves second order or worse."""
+    errs = _cfm4_errors(oracle_mod, 0, (8, 16, 32))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert r1 > 13 and r2 > 13, errs
+
+
+def test_cfm4_nonlinear_converges(oracle_mod):
+    """With exchange from the density (potential extrapolated from past
+    steps, from fewer points in the first three steps) the trajectory still
+    converges to the RK4 solution, at least at second order (the first
+    step's constant extrapolation bounds the global order)."""
+    errs = _cfm4_errors(oracle_mod, 1, (8, 16, 32))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert r1 > 3.5 and r2 > 3.5, errs
+    assert errs[2] < 1e-3, errs
