@@ -143,6 +143,20 @@ int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
                       int nsteps, double dt, double t0, double *d_dipole,
                       double *d_norms);
 
+/* CFM4 propagation (section "New propagators for real-time TDDFT": the
+ * order-four commutator-free Magnus expansion with two exponentials,
+ *   psi(t+dt) = exp(-i dt (a1 H(t1) + a2 H(t2)))
+ *               exp(-i dt (a2 H(t1) + a1 H(t2))) psi(t),
+ * a1,2 = (3 -+ 2 sqrt 3)/12, t1,2 = t + (1/2 -+ sqrt(3)/6) dt).  H(t_i)
+ * takes A(t_i) and the local potential extrapolated from the potentials at
+ * the ends of the most recent steps of this call (cubic through four; fewer
+ * in its first three steps).  Each exponential is Taylor-4 with 4 H.psi, so
+ * a step costs 8 H.psi like an ETRS step.  Arguments, outputs, errors and
+ * the grid's potential afterwards as for ks_propagate_etrs. */
+int ks_propagate_cfm4(ks_grid *g, void *d_psi, const double *d_vion,
+                      int nsteps, double dt, double t0, double *d_dipole,
+                      double *d_norms);
+
 /* d_rho[g] = sum_k w_k sum_s f_s |psi_ks(g)|^2 over all nk*nstates states
  * (section "Local domains", n = sum of densities). */
 int ks_density(ks_grid *g, const void *d_psi, double *d_rho);

@@ -75,7 +75,7 @@ struct ks_grid {
     size_t ws_bytes = 0;
     struct {
         size_t t1, t2, t3, half, npart, normpart, D, W, Dpart, rho, vpred,
-            dpart, gpart, dotpart, xpart, step, total;
+            dpart, gpart, dotpart, xpart, step, vhist, veff, total;
     } lay{};
     int ntiles_max = 64;
     int nchunk = 1;
@@ -419,6 +419,8 @@ void layout(ks_grid *g)
     g->lay.dotpart = take(S * g->norm_chunks * 16);
     g->lay.xpart = take(ndb * 8);
     g->lay.step = take(sizeof(int));
+    g->lay.vhist = take(4 * N * 8);
+    g->lay.veff = take(N * 8);
     g->lay.total = off;
 }
 
@@ -506,9 +508,28 @@ int need_ws(const ks_grid *g)
 // step tau applied to all states in `in`: t_j = (-i tau / j) H t_{j-1};
 // the last pass writes out = in + t1 + t2 + t3 + t4 (mode kFinal) or also the
 // predictor density (kFinalPred).
+// Weights of the polynomial through the values at x_j = -j (j < h, unit
+// steps back from now) evaluated at x: extrapolation of the potential.
+void lagrange_back(int h, double x, double L[4])
+{
+    for (int j = 0; j < h; ++j) {
+        double w = 1.0;
+        for (int m = 0; m < h; ++m)
+            if (m != j)
+                w *= (x + m) / (double)(m - j);
+        L[j] = w;
+    }
+}
+
+double half_a2(const double A[3])
+{
+    return 0.5 * (A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+}
+
 int taylor_exponential(ks_grid *g, const double2 *in, double2 *out,
-                       const double *v, const double A[3], double tau,
-                       int final_mode, double *npart, double *normpart)
+                       const double *v, const double A[3], double a2half,
+                       double tau, int final_mode, double *npart,
+                       double *normpart)
 {
     const int S = g->stot;
     const bool mx = g->mixed;
@@ -519,7 +540,7 @@ int taylor_exponential(ks_grid *g, const double2 *in, double2 *out,
     a.A[0] = A[0];
     a.A[1] = A[1];
     a.A[2] = A[2];
-    a.a2half = 0.5 * (A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+    a.a2half = a2half;
     GArgs ga = base_gargs(g);
     ga.D = D;
     const void *cur = in;
@@ -1156,7 +1177,8 @@ int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
         laser_A(g, t, At);
         laser_A(g, t + dt, An);
         // exponential 1: H_t, tau = dt/2; predictor density when xc is on
-        rc = taylor_exponential(g, psi, half, g->d_v, At, 0.5 * dt,
+        rc = taylor_exponential(g, psi, half, g->d_v, At, half_a2(At),
+                                0.5 * dt,
                                 g->xc ? kFinalPred : kFinal,
                                 g->xc ? npart : nullptr, nullptr);
         if (rc)
@@ -1176,7 +1198,8 @@ int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
             vnext = vpred;
         }
         // exponential 2: H_{t+dt}, tau = dt/2, from psi_half into psi
-        rc = taylor_exponential(g, half, psi, vnext, An, 0.5 * dt, kFinal,
+        rc = taylor_exponential(g, half, psi, vnext, An, half_a2(An),
+                                0.5 * dt, kFinal,
                                 want_n_end ? npart : nullptr,
                                 d_norms ? normpart : nullptr);
         if (rc)
@@ -1205,6 +1228,143 @@ int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
                                         g->stream));
         }
     }
+    return KS_OK;
+}
+
+int ks_propagate_cfm4(ks_grid *g, void *d_psi, const double *d_vion,
+                      int nsteps, double dt, double t0, double *d_dipole,
+                      double *d_norms)
+{
+    if (!g || !d_psi || !d_vion)
+        return fail(KS_E_ARG, "NULL argument");
+    if (nsteps < 0)
+        return fail(KS_E_ARG, "nsteps < 0");
+    if (!std::isfinite(dt) || !std::isfinite(t0))
+        return fail(KS_E_ARG, "dt and t0 must be finite");
+    if (d_dipole && (g->geo.per[0] || g->geo.per[1] || g->geo.per[2]))
+        return fail(KS_E_UNSUPPORTED, "dipole of a periodic grid");
+    int rc = need_ws(g);
+    if (rc)
+        return rc;
+    double2 *psi = static_cast<double2 *>(d_psi);
+    double2 *half = wsp<double2>(g, g->lay.half);
+    double *npart = wsp<double>(g, g->lay.npart);
+    double *normpart = wsp<double>(g, g->lay.normpart);
+    double *rho = wsp<double>(g, g->lay.rho);
+    double *dpart = wsp<double>(g, g->lay.dpart);
+    double *veff = wsp<double>(g, g->lay.veff);
+    double *vh[4];
+    for (int j = 0; j < 4; ++j)
+        vh[j] = wsp<double>(g, g->lay.vhist) + (size_t)j * g->geo.N;
+    const double h3 = g->geo.h[0] * g->geo.h[1] * g->geo.h[2];
+    const int S = g->stot;
+    const int ntiles = g->ntile_y * g->nzc;
+    const int ndb = density_blocks(g->geo.N);
+    const double a1 = (3.0 - 2.0 * std::sqrt(3.0)) / 12.0;
+    const double a2 = (3.0 + 2.0 * std::sqrt(3.0)) / 12.0;
+    const double c1 = 0.5 - std::sqrt(3.0) / 6.0;
+    const double c2 = 0.5 + std::sqrt(3.0) / 6.0;
+    // history ring: hist[0] is v at the current time, hist[j] j steps back
+    int ring[4] = {0, 1, 2, 3};
+    int nhist = 0;
+    // v(t0) from n(psi(t0)); d(t0); norms(t0)
+    {
+        DArgs a;
+        a.geo = g->geo;
+        a.nsrc = S;
+        a.psi = psi;
+        a.wocc = g->d_wocc;
+        a.rho = rho;
+        a.vion = d_vion;
+        a.vout = vh[ring[0]];
+        a.xc = g->xc;
+        a.dpart = d_dipole ? dpart : nullptr;
+        KS_HIP(launch_density(a, g->stream));
+        if (d_dipole)
+            KS_HIP(launch_dipole_finalize(dpart, ndb, h3, d_dipole,
+                                          g->stream));
+        if (d_norms) {
+            KS_HIP(launch_norm_partial(g->geo, psi, S, g->norm_chunks,
+                                       normpart, g->stream));
+            KS_HIP(launch_norm_finalize(normpart, S, g->norm_chunks, h3,
+                                        d_norms, g->stream));
+        }
+        nhist = 1;
+    }
+    const bool want_n_end = true;   // v(t + dt) feeds the extrapolation
+    for (int step = 0; step < nsteps; ++step) {
+        const double t = t0 + step * dt;
+        double A1[3], A2[3], L1[4], L2[4];
+        laser_A(g, t + c1 * dt, A1);
+        laser_A(g, t + c2 * dt, A2);
+        lagrange_back(nhist, c1, L1);
+        lagrange_back(nhist, c2, L2);
+        // exp(-i dt (a H1 + b H2)) = exp(-i dt/2 H_w) with H_w the
+        // combination of weights 2a, 2b (summing to one): potential, vector
+        // potential and |A|^2/2 combine linearly
+        const double wts[2][2] = {{2.0 * a2, 2.0 * a1}, {2.0 * a1, 2.0 * a2}};
+        for (int e = 0; e < 2; ++e) {
+            const double w1 = wts[e][0], w2 = wts[e][1];
+            double W[4] = {0, 0, 0, 0};
+            const double *src[4] = {nullptr, nullptr, nullptr, nullptr};
+            for (int j = 0; j < nhist; ++j) {
+                W[j] = w1 * L1[j] + w2 * L2[j];
+                src[j] = vh[ring[j]];
+            }
+            {
+                Timed tm(g, 2);
+                KS_HIP(launch_vcombine(g->geo.N, nhist, src, W, veff,
+                                       g->stream));
+            }
+            double Aw[3];
+            for (int d = 0; d < 3; ++d)
+                Aw[d] = w1 * A1[d] + w2 * A2[d];
+            const double a2w = w1 * half_a2(A1) + w2 * half_a2(A2);
+            rc = e == 0 ? taylor_exponential(g, psi, half, veff, Aw, a2w,
+                                             0.5 * dt, kFinal, nullptr,
+                                             nullptr)
+                        : taylor_exponential(g, half, psi, veff, Aw, a2w,
+                                             0.5 * dt, kFinal,
+                                             want_n_end ? npart : nullptr,
+                                             d_norms ? normpart : nullptr);
+            if (rc)
+                return rc;
+        }
+        // v(t + dt) from the new density becomes the newest history entry
+        const int slot = ring[3];
+        for (int j = 3; j > 0; --j)
+            ring[j] = ring[j - 1];
+        ring[0] = slot;
+        if (nhist < 4)
+            ++nhist;
+        {
+            DArgs a;
+            a.geo = g->geo;
+            a.nsrc = S;
+            a.npart = npart;
+            a.rho = rho;
+            a.vion = d_vion;
+            a.vout = vh[ring[0]];
+            a.xc = g->xc;
+            a.dpart = d_dipole ? dpart : nullptr;
+            Timed tm(g, 2);
+            KS_HIP(launch_density(a, g->stream));
+            if (d_dipole)
+                KS_HIP(launch_dipole_finalize(dpart, ndb, h3,
+                                              d_dipole + 3 * (step + 1),
+                                              g->stream));
+        }
+        if (d_norms) {
+            Timed tm(g, 2);
+            KS_HIP(launch_norm_finalize(normpart, S, ntiles, h3,
+                                        d_norms + (size_t)(step + 1) * S,
+                                        g->stream));
+        }
+    }
+    // the grid's potential is v at the final time
+    KS_HIP(hipMemcpyAsync(g->d_v, vh[ring[0]], sizeof(double) * g->geo.N,
+                          hipMemcpyDeviceToDevice, g->stream));
+    g->vloc_set = true;
     return KS_OK;
 }
 

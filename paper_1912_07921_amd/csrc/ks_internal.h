@@ -154,6 +154,8 @@ hipError_t launch_gram(const Geo &g, const double2 *psi, int nk, int ns,
 hipError_t launch_dot_partial(const Geo &g, const double2 *a,
                               const double2 *b, int ns, int nchunks,
                               double2 *part, hipStream_t st);
+hipError_t launch_vcombine(long N, int h, const double *const src[4],
+                           const double w[4], double *out, hipStream_t st);
 hipError_t launch_exchange_partial(const Geo &g, const double *rho,
                                    double *part, hipStream_t st);
 

@@ -310,6 +310,40 @@ hipError_t launch_kbapply(bool mixed, const GArgs &a, int ns, hipStream_t st)
     return hipGetLastError();
 }
 
+// out[g] = sum_j w[j] src[j][g], j = 0 .. h-1 in order (potential
+// extrapolation of the CFM4 propagator).
+struct VComb {
+    const double *src[4];
+    double w[4];
+};
+
+__global__ __launch_bounds__(256) void k_vcombine(long N, int h, VComb c,
+                                                  double *out)
+{
+    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= N)
+        return;
+    double s = 0.0;
+    for (int j = 0; j < h; ++j)
+        s += c.w[j] * c.src[j][g];
+    out[g] = s;
+}
+
+hipError_t launch_vcombine(long N, int h, const double *const src[4],
+                           const double w[4], double *out, hipStream_t st)
+{
+    if (h < 1 || h > 4)
+        return hipErrorInvalidValue;
+    VComb c;
+    for (int j = 0; j < 4; ++j) {
+        c.src[j] = j < h ? src[j] : nullptr;
+        c.w[j] = j < h ? w[j] : 0.0;
+    }
+    hipLaunchKernelGGL(k_vcombine, dim3((unsigned)((N + 255) / 256)),
+                       dim3(256), 0, st, N, h, c, out);
+    return hipGetLastError();
+}
+
 int density_blocks(long N)
 {
     return (int)((N + kDensThreads - 1) / kDensThreads);

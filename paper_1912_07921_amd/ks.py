@@ -79,6 +79,9 @@ EXPORTS = {
     "ks_propagate_etrs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_int, C.c_double, C.c_double,
                                     C.c_void_p, C.c_void_p]),
+    "ks_propagate_cfm4": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_int, C.c_double, C.c_double,
+                                    C.c_void_p, C.c_void_p]),
     "ks_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ks_dipole": (C.c_int, [C.c_void_p, C.c_void_p,
                             C.POINTER(C.c_double)]),
@@ -219,6 +222,11 @@ def ks_apply_h(h, psi, hpsi, k, s0, ns, t):
 
 def ks_propagate_etrs(h, psi, vion, nsteps, dt, t0, dipole, norms):
     return _check(lib().ks_propagate_etrs(h, _ptr(psi), _ptr(vion), nsteps,
+                                          dt, t0, _ptr(dipole), _ptr(norms)))
+
+
+def ks_propagate_cfm4(h, psi, vion, nsteps, dt, t0, dipole, norms):
+    return _check(lib().ks_propagate_cfm4(h, _ptr(psi), _ptr(vion), nsteps,
                                           dt, t0, _ptr(dipole), _ptr(norms)))
 
 
@@ -395,6 +403,19 @@ class Grid:
                               dtype=self.torch.float64, device=self.device)
              if norms else None)
         ks_propagate_etrs(self.h, psi, vion, int(nsteps), float(dt),
+                          float(t0), d, n)
+        return d, n
+
+    def propagate_cfm4(self, psi, vion, nsteps, dt, t0=0.0, dipole=True,
+                       norms=True):
+        self._psi(psi)
+        _dev(vion, self.torch.float64, self.N, "vion")
+        d = (self.torch.zeros((nsteps + 1, 3), dtype=self.torch.float64,
+                              device=self.device) if dipole else None)
+        n = (self.torch.zeros((nsteps + 1, self.nk * self.ns),
+                              dtype=self.torch.float64, device=self.device)
+             if norms else None)
+        ks_propagate_cfm4(self.h, psi, vion, int(nsteps), float(dt),
                           float(t0), d, n)
         return d, n
 

@@ -164,16 +164,18 @@ def test_gram_larger_than_one_tile(torch_cuda, oracle_mod):
 # ETRS propagation
 # ---------------------------------------------------------------------------
 def propagate_parity(torch, oracle_mod, spec, v, psi, nsteps, dt, t0=0.0,
-                     prec=0, kick=0.0, tol=1e-10, dip_tol=None):
+                     prec=0, kick=0.0, tol=1e-10, dip_tol=None,
+                     method="etrs"):
     o = oracle_mod.Oracle(spec)
     if kick:
         psi = o.kick(psi, kick)
-    want, wd, wn = o.propagate_etrs(psi, v, nsteps, dt, t0)
+    want, wd, wn = getattr(o, "propagate_" + method)(psi, v, nsteps, dt, t0)
     g = grid(spec, prec)
     dpsi = dev(torch, psi)
     periodic = any(spec.periodic)
-    d, n = g.propagate_etrs(dpsi, dev(torch, v), nsteps, dt, t0,
-                            dipole=not periodic, norms=True)
+    d, n = getattr(g, "propagate_" + method)(dpsi, dev(torch, v), nsteps, dt,
+                                             t0, dipole=not periodic,
+                                             norms=True)
     got = dpsi.cpu().numpy()
     e_psi = rel_err(got.reshape(-1, o.N), want.reshape(-1, o.N))
     e_norm = np.abs(n.cpu().numpy() - wn).max()
@@ -303,3 +305,49 @@ def test_propagate_independent_of_launch_shape(torch_cuda, oracle_mod):
         outs.append(dpsi.cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
     assert np.array_equal(outs[0], outs[2])
+
+
+# ---------------------------------------------------------------------------
+# CFM4 propagation
+# ---------------------------------------------------------------------------
+def test_cfm4_c1_full_length(torch_cuda, oracle_mod):
+    w = W.c1()
+    propagate_parity(torch_cuda, oracle_mod, w.spec, w.vion, w.psi0,
+                     w.nsteps, w.dt, method="cfm4")
+
+
+def test_cfm4_tiny_every_term(torch_cuda, oracle_mod):
+    """Exchange, projectors and a laser: 7 steps cover the start-up
+    extrapolation orders (1, 2, 3 points) and the steady cubic one."""
+    spec, v, psi = W.tiny(n=(17, 15, 14), nk=1, nstates=3, natoms=2, lmax=2,
+                          rc=1.2, sigma=0.4, xc=1,
+                          laser=(0.3, 0.8, 3.0, 0.2, 0.1, 0.9))
+    h3 = np.prod(spec.h)
+    psi = psi / np.sqrt(np.sum(np.abs(psi) ** 2, axis=2, keepdims=True) * h3)
+    propagate_parity(torch_cuda, oracle_mod, spec, 0.3 * v, psi, 7, 0.01,
+                     t0=0.2, kick=0.05, method="cfm4")
+
+
+def test_cfm4_periodic_kpoints(torch_cuda, oracle_mod):
+    spec, v, psi = W.tiny(n=(16, 14, 15), h=(0.35, 0.35, 0.35),
+                          periodic=(1, 1, 1), nk=2, nstates=2, natoms=2,
+                          lmax=1, rc=1.1, sigma=0.4, xc=1,
+                          laser=(0.3, 0.8, 3.0, 0.0, 0.0, 1.0))
+    h3 = np.prod(spec.h)
+    psi = psi / np.sqrt(np.sum(np.abs(psi) ** 2, axis=2, keepdims=True) * h3)
+    propagate_parity(torch_cuda, oracle_mod, spec, 0.3 * v, psi, 5, 0.01,
+                     method="cfm4")
+
+
+def test_cfm4_c2_full_size_few_steps(torch_cuda, oracle_mod):
+    w = W.c2(nsteps=5)
+    propagate_parity(torch_cuda, oracle_mod, w.spec, w.vion, w.psi0,
+                     w.nsteps, w.dt, kick=w.kick, method="cfm4")
+
+
+def test_cfm4_mixed_c2_dipole(torch_cuda, oracle_mod):
+    w = W.c2(nsteps=8)
+    res = propagate_parity(torch_cuda, oracle_mod, w.spec, w.vion, w.psi0,
+                           w.nsteps, w.dt, kick=w.kick, prec=1,
+                           dip_tol=1e-6, method="cfm4")
+    assert res["psi"] < 1e-4, res
