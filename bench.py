@@ -114,7 +114,8 @@ def make_workload(name):
     return {"c1": W.c1, "c2": W.c2, "c3": W.c3, "c5": W.c5}[name]()
 
 
-def run_gpu(w, precision, steps, warmup, torch, tune=True, shape=None):
+def run_gpu(w, precision, steps, warmup, torch, tune=True, shape=None,
+            method="etrs"):
     """(seconds for `steps` steps, dipole trace, profile, grid, launch
     shape).  The launch shape is `shape` (tile rows, z-chunk) if given, else
     the autotuner's choice (tune) or the default."""
@@ -129,17 +130,17 @@ def run_gpu(w, precision, steps, warmup, torch, tune=True, shape=None):
     elif tune:
         g.autotune(psi, reps=3)
     periodic = any(w.spec.periodic)
+    prop = getattr(g, "propagate_" + method)
     if warmup:
-        g.propagate_etrs(psi, vion, warmup, w.dt, dipole=not periodic,
-                         norms=True)
+        prop(psi, vion, warmup, w.dt, dipole=not periodic, norms=True)
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     g.profile_begin(64 * steps + 64)
     e0.record(st)
-    d, n = g.propagate_etrs(psi, vion, steps, w.dt, t0=warmup * w.dt,
-                            dipole=not periodic, norms=True)
+    d, n = prop(psi, vion, steps, w.dt, t0=warmup * w.dt,
+                dipole=not periodic, norms=True)
     e1.record(st)
     prof = g.profile_end()
     torch.cuda.synchronize()
@@ -253,6 +254,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 2 GiB device copy (counter calibration)")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-cfm4", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shape (no autotuner)")
     ap.add_argument("--shape", default="",
@@ -290,6 +292,7 @@ def main():
     log(f"FP64: {args.warmup} warmup + {args.steps} timed steps")
     fixed = tuple(int(v) for v in args.shape.split(",")) if args.shape \
         else None
+    dipc64 = None
     sec, dip64, nrm64, prof, _, shape = run_gpu(w, 0, args.steps,
                                                 args.warmup, torch,
                                                 not args.no_tune, fixed)
@@ -359,6 +362,26 @@ def main():
         if dip64 is not None:
             mixed["dipole_err_vs_fp64"] = float(abs(dipm - dip64).max())
         out["mixed"] = mixed
+
+    if not args.no_cfm4:
+        # the order-four propagator of the paper: 8 H.psi per step as ETRS
+        cf = {}
+        for prec, key in ((0, "fp64"), (1, "mixed")):
+            log(f"CFM4 {key}: {args.warmup} warmup + {args.steps} steps")
+            csec, cdip, _, cprof, _, cshape = run_gpu(
+                w, prec, args.steps, args.warmup, torch, not args.no_tune,
+                fixed if prec == 0 else None, method="cfm4")
+            ch_ms, ch_n = cprof["hpsi"]
+            cf[key] = dict(value=units * args.steps / csec,
+                           ms_per_step=1e3 * csec / args.steps,
+                           hpsi_avg_us=round(1e3 * ch_ms / max(ch_n, 1), 2),
+                           launch_shape=cshape)
+            if prec == 1 and cdip is not None and dipc64 is not None:
+                cf[key]["dipole_err_vs_fp64"] = float(
+                    abs(cdip - dipc64).max())
+            if prec == 0:
+                dipc64 = cdip
+        out["cfm4"] = cf
 
     if not args.no_serving:
         out["serving"] = run_serving(torch, args.serving_requests,
