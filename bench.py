@@ -258,8 +258,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shape (no autotuner)")
     ap.add_argument("--shape", default="",
-                    help="FP64 launch shape 'tile_rows,zchunk' instead of "
-                         "the autotuner's (profiling runs)")
+                    help="FP64 launch shape 'tile_rows,zchunk,rows_per_thread'"
+                         " instead of the autotuner's (profiling runs)")
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=128)
     ap.add_argument("--serving-steps", type=int, default=50,

@@ -184,18 +184,21 @@ int ks_energy(ks_grid *g, const void *d_psi, const double *d_vion, double t,
               double *out_host);
 
 /* Launch shape of the H.psi kernel: a workgroup owns tile_rows full x-rows
- * of one state and marches through zchunk z-planes; with nx * tile_rows
- * above 512 each thread marches two rows.  0 keeps the library's choice for
- * that parameter.  KS_E_ARG / KS_E_UNSUPPORTED if the shape does not fit
- * (at most 512 threads of nx * ceil(tile_rows / rows per thread), 160 KiB of
- * LDS, 16 halo loads per thread).  The workspace size does not depend on the
- * shape.  States, dipoles and densities do not depend on the shape; the norm
- * diagnostics sum per-tile partials, so their last bits do. */
-int ks_set_launch(ks_grid *g, int tile_rows, int zchunk);
+ * of one state and marches through zchunk z-planes; each thread marches
+ * rows_per_thread (1 or 2) rows of the tile, ceil(tile_rows /
+ * rows_per_thread) apart.  0 keeps the library's choice for that
+ * parameter.  KS_E_ARG / KS_E_UNSUPPORTED if the shape does not fit (at
+ * most 512 threads of nx * ceil(tile_rows / rows_per_thread), 160 KiB of
+ * LDS, 16 halo loads per thread (8 with two rows)).  The workspace size does
+ * not depend on the shape.  States, dipoles and densities do not depend on
+ * the shape; the norm diagnostics sum per-tile partials, so their last bits
+ * do. */
+int ks_set_launch(ks_grid *g, int tile_rows, int zchunk, int rows_per_thread);
 
 /* out[0] = tile_rows, out[1] = zchunk, out[2] = workgroups per H.psi launch
- * over all states, out[3] = threads per workgroup. */
-int ks_get_launch(const ks_grid *g, int out[4]);
+ * over all states, out[3] = threads per workgroup, out[4] = rows per
+ * thread. */
+int ks_get_launch(const ks_grid *g, int out[5]);
 
 /* Kernel timing with HIP events on the grid's stream.  After
  * ks_profile_begin(g, capacity), every later launch of the H.psi kernel
@@ -208,19 +211,19 @@ int ks_get_launch(const ks_grid *g, int out[4]);
 int ks_profile_begin(ks_grid *g, int capacity);
 int ks_profile_end(ks_grid *g, double out_ms[4], long out_count[4]);
 
-/* Autotuner: time the H.psi pass (the Taylor-term pass that dominates a
- * step: FP64 psi -> t1, or complex64 t -> t1 in the mixed form) on the
- * caller's states `d_psi` ([nk][nstates][N] complex128, read only) over
- * candidate launch shapes (tile rows x z-chunk: the default, the largest
- * tile (two rows per thread), the tallest of one row per thread, an even
- * split of ny, halves and quarters; z-chunks of nz, nz/2, ... down to 8
- * planes), `reps` timed launches
- * each, and keep the fastest.  Results of every call are the same for every
- * shape; only speed changes.  Synchronises the grid's stream.  Writes the
- * chosen (tile rows, z-chunk) to out_shape and its time per pass in
- * microseconds to *out_us (either may be NULL).  Overwrites the workspace's
- * Taylor buffers; needs a workspace. */
-int ks_autotune(ks_grid *g, const void *d_psi, int reps, int out_shape[2],
+/* Autotuner: time the four H.psi passes of one Taylor exponential (the
+ * three term passes and the final sum, the mix a step runs; projector
+ * terms included as they are) on the caller's states `d_psi`
+ * ([nk][nstates][N] complex128, read only) over
+ * candidate launch shapes (for one and for two rows per thread: the tallest
+ * tile of 512 threads, the even split of ny into as many tiles, 3/4, 1/2
+ * and 1/4 of it; z-chunks of nz, nz/2, ... down to 8 planes), `reps` timed
+ * launches each, and keep the fastest.  Results of every call are the same
+ * for every shape; only speed changes.  Synchronises the grid's stream.
+ * Writes the chosen (tile rows, z-chunk, rows per thread) to out_shape and
+ * its mean time per pass in microseconds to *out_us (either may be NULL).
+ * Overwrites the workspace's Taylor buffers; needs a workspace. */
+int ks_autotune(ks_grid *g, const void *d_psi, int reps, int out_shape[3],
                 double *out_us);
 
 /* ---- batched form ----

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <array>
 #include <vector>
 
 using namespace ks;
@@ -68,7 +69,7 @@ struct ks_grid {
     std::vector<int> h_npts, h_nproj;
 
     // launch shape
-    int TY = 1, zchunk = 1, ntile_y = 1, nzc = 1;
+    int TY = 1, zchunk = 1, ntile_y = 1, nzc = 1, rpt = 1;
 
     // workspace
     char *ws = nullptr;
@@ -328,12 +329,12 @@ size_t lds_for(const ks_grid *g, int TY, int zchunk)
 // Launch shape: rows per tile TY (up to 512 threads, one or two rows per
 // thread) and planes per z-chunk (the full z extent unless that leaves fewer
 // than ~4 workgroups per CU).  Either may be forced (> 0) by the caller.
-bool tile_ok(const ks_grid *g, int TY)
+bool tile_ok(const ks_grid *g, int TY, int rpt)
 {
     const Geo &G = g->geo;
-    if (TY < 1 || TY > G.ny || G.nx * TY > 2 * kRowThreads)
+    if (TY < 1 || TY > G.ny || rpt < 1 || rpt > 2)
         return false;
-    const int nthr = hpsi_threads(G.nx, TY);
+    const int nthr = hpsi_threads(G.nx, TY, rpt);
     if (nthr > kRowThreads)
         return false;
     // the kernel holds at most 16 halo loads per thread and plane (8 when
@@ -341,27 +342,25 @@ bool tile_ok(const ks_grid *g, int TY)
     const int dyn = 2 * kHalf * G.nx +
                     (G.per[0] ? 2 * kHalf * (TY + 2 * kHalf) : 0);
     const int hm = (dyn + nthr - 1) / nthr;
-    return hm <= (hpsi_rpt(G.nx, TY) == 2 ? 8 : 16);
+    return hm <= (rpt == 2 ? 8 : 16);
 }
 
-int set_tiles(ks_grid *g, int TY, int zchunk)
+int set_tiles(ks_grid *g, int TY, int zchunk, int rpt)
 {
     const Geo &G = g->geo;
+    if (rpt <= 0)
+        rpt = (TY > 0 && G.nx * TY <= kRowThreads) ? 1 : (g->mixed ? 1 : 2);
     if (TY <= 0) {
         // the tallest tile that fits the threads and the default LDS share:
-        // the 8 halo rows are then the smallest fraction of what it loads.
-        // Two rows per thread pay off in FP64; the mixed form keeps one
-        // (its shorter registers already give enough loads in flight).
-        const int rows_per_thread = g->mixed ? 1 : 2;
-        TY = std::max(1, std::min(G.ny,
-                                  rows_per_thread * kRowThreads / G.nx));
-        while (TY > 1 && (!tile_ok(g, TY) ||
+        // the 8 halo rows are then the smallest fraction of what it loads
+        TY = std::max(1, std::min(G.ny, rpt * kRowThreads / G.nx));
+        while (TY > 1 && (!tile_ok(g, TY, rpt) ||
                           lds_for(g, TY, std::min(G.nz, 16)) > kLdsDefault))
             --TY;
     }
-    if (!tile_ok(g, TY))
-        return fail(KS_E_ARG, "tile height %d invalid for nx=%d ny=%d", TY,
-                    G.nx, G.ny);
+    if (!tile_ok(g, TY, rpt))
+        return fail(KS_E_ARG, "tile height %d with %d rows per thread "
+                    "invalid for nx=%d ny=%d", TY, rpt, G.nx, G.ny);
     const int ntile_y = (G.ny + TY - 1) / TY;
     if (zchunk <= 0) {
         // about two workgroups per CU over the launch, chunks of at least
@@ -382,6 +381,7 @@ int set_tiles(ks_grid *g, int TY, int zchunk)
     if ((long)ntile_y * nzc * g->stot >= (1L << 31))
         return fail(KS_E_UNSUPPORTED, "too many workgroups");
     g->TY = TY;
+    g->rpt = rpt;
     g->ntile_y = ntile_y;
     g->zchunk = zchunk;
     g->nzc = nzc;
@@ -476,6 +476,7 @@ HArgs base_hargs(ks_grid *g)
             a.W = g->ws + g->lay.W;
     }
     a.TY = g->TY;
+    a.rpt = g->rpt;
     a.zchunk = g->zchunk;
     a.ntile_y = g->ntile_y;
     a.nzc = g->nzc;
@@ -666,7 +667,7 @@ int ks_grid_create(const ks_grid_desc *d, ks_grid **out)
         ks_grid_destroy(g);
         return rc;
     }
-    if ((rc = set_tiles(g, 0, 0))) {
+    if ((rc = set_tiles(g, 0, 0, 0))) {
         ks_grid_destroy(g);
         return rc;
     }
@@ -938,27 +939,25 @@ int ks_energy(ks_grid *g, const void *d_psi, const double *d_vion, double t,
     return KS_OK;
 }
 
-int ks_set_launch(ks_grid *g, int tile_rows, int zchunk)
+int ks_set_launch(ks_grid *g, int tile_rows, int zchunk, int rows_per_thread)
 {
     if (!g)
         return fail(KS_E_ARG, "grid is NULL");
-    const int oldTY = g->TY, oldz = g->zchunk;
-    int rc = set_tiles(g, tile_rows, zchunk);
+    const int oldTY = g->TY, oldz = g->zchunk, oldr = g->rpt;
+    int rc = set_tiles(g, tile_rows, zchunk, rows_per_thread);
     if (rc) {
-        set_tiles(g, oldTY, oldz);
+        set_tiles(g, oldTY, oldz, oldr);
         return rc;
     }
-    const size_t need = g->lay.total;
     layout(g);
     if (g->ws && g->lay.total > g->ws_bytes) {
         g->ws = nullptr;   // the caller must lend a larger workspace
         return fail(KS_E_OOM, "workspace too small for this launch shape");
     }
-    (void)need;
     return KS_OK;
 }
 
-int ks_autotune(ks_grid *g, const void *d_psi, int reps, int out_shape[2],
+int ks_autotune(ks_grid *g, const void *d_psi, int reps, int out_shape[3],
                 double *out_us)
 {
     if (!g || !d_psi || reps < 1)
@@ -969,18 +968,19 @@ int ks_autotune(ks_grid *g, const void *d_psi, int reps, int out_shape[2],
     const Geo &G = g->geo;
     const int S = g->stot;
     const bool mx = g->mixed;
-    // candidate tile heights: the largest that fits 512 threads, the one
-    // that splits ny evenly into as many tiles, and halves / quarters
-    const int m = std::max(1, std::min(G.ny, 2 * kRowThreads / G.nx));
-    std::vector<int> tys = {m,         m - 1,         m / 2,
-                            m / 4,     (m * 3) / 4,
-                            std::max(1, std::min(G.ny, kRowThreads / G.nx))};
-    {
+    // candidate (tile rows, rows per thread): for one and two rows per
+    // thread the tallest tile of 512 threads, the one that splits ny evenly
+    // into as many tiles, and 3/4, 1/2 and 1/4 of it
+    std::vector<std::pair<int, int>> shapes;
+    for (int rpt = 1; rpt <= 2; ++rpt) {
+        const int m = std::max(1, std::min(G.ny, rpt * kRowThreads / G.nx));
         const int nt = (G.ny + m - 1) / m;
-        tys.push_back((G.ny + nt - 1) / nt);
+        for (int ty : {m, m - 1, (m * 3) / 4, m / 2, m / 4,
+                       (G.ny + nt - 1) / nt})
+            if (ty >= rpt)
+                shapes.push_back({ty, rpt});
     }
-    // candidate z-chunks: the whole axis, halves down to 8 planes, and the
-    // default heuristic's choice
+    // candidate z-chunks: the whole axis, halves down to 8 planes
     std::vector<int> zcs;
     for (int z = G.nz; z >= 8; z = (z + 1) / 2) {
         zcs.push_back(z);
@@ -989,7 +989,7 @@ int ks_autotune(ks_grid *g, const void *d_psi, int reps, int out_shape[2],
     }
     if (zcs.empty())
         zcs.push_back(G.nz);
-    const int oldTY = g->TY, oldz = g->zchunk;
+    const int oldTY = g->TY, oldz = g->zchunk, oldr = g->rpt;
     // valid W for the timed passes: projector coefficients of psi
     GArgs ga = base_gargs(g);
     ga.D = g->ws + g->lay.D;
@@ -1001,63 +1001,76 @@ int ks_autotune(ks_grid *g, const void *d_psi, int reps, int out_shape[2],
     hipEvent_t e0, e1;
     KS_HIP(hipEventCreate(&e0));
     KS_HIP(hipEventCreate(&e1));
-    int bestTY = oldTY, bestz = oldz;
+    int bestTY = oldTY, bestz = oldz, bestr = oldr;
     double best = 1e300;
-    std::vector<std::pair<int, int>> tried;
-    auto run = [&](int ty, int zc) -> int {
+    std::vector<std::array<int, 3>> tried;
+    auto run = [&](int ty, int zc, int rpt) -> int {
         for (auto &p : tried)
-            if (p.first == ty && p.second == zc)
+            if (p[0] == ty && p[1] == zc && p[2] == rpt)
                 return KS_OK;
-        tried.push_back({ty, zc});
-        if (set_tiles(g, ty, zc) != KS_OK)
+        tried.push_back({ty, zc, rpt});
+        if (set_tiles(g, ty, zc, rpt) != KS_OK)
             return KS_OK;            // shape not allowed here: skip it
         g_err.clear();
+        // one Taylor-4 exponential's four passes (three terms and the
+        // final sum into psi_half), the mix of passes a step runs
         HArgs a = base_hargs(g);
         a.v = g->d_v;
         a.cre = 0.0;
-        a.cim = -0.01;
-        // FP64: psi -> t1.  Mixed: psi -> t2 once (FP64 input), then the
-        // dominant complex64 pass t2 -> t1 is timed.
-        const void *in = d_psi;
-        bool f64 = true;
-        if (mx) {
-            a.in = d_psi;
-            a.out = g->ws + g->lay.t2;
-            KS_HIP(launch_hpsi(kTerm, true, true, a, S, g->stream));
-            in = g->ws + g->lay.t2;
-            f64 = false;
-        }
-        a.in = in;
-        a.out = g->ws + g->lay.t1;
-        KS_HIP(launch_hpsi(kTerm, mx, f64, a, S, g->stream));   // warm
+        auto expo = [&]() -> int {
+            void *tb[3] = {g->ws + g->lay.t1, g->ws + g->lay.t2,
+                           g->ws + g->lay.t3};
+            const void *cur = d_psi;
+            for (int j = 1; j <= 4; ++j) {
+                a.in = cur;
+                a.cim = -0.01 / j;
+                if (j < 4) {
+                    a.out = tb[j - 1];
+                    KS_HIP(launch_hpsi(kTerm, mx, j == 1 || !mx, a, S,
+                                       g->stream));
+                    cur = tb[j - 1];
+                } else {
+                    a.out = g->ws + g->lay.half;
+                    a.base = static_cast<const double2 *>(d_psi);
+                    a.t1 = tb[0];
+                    a.t2 = tb[1];
+                    KS_HIP(launch_hpsi(kFinal, mx, false, a, S, g->stream));
+                }
+            }
+            return KS_OK;
+        };
+        int e = expo();                                          // warm
+        if (e)
+            return e;
         KS_HIP(hipEventRecord(e0, g->stream));
         for (int r = 0; r < reps; ++r)
-            KS_HIP(launch_hpsi(kTerm, mx, f64, a, S, g->stream));
+            if ((e = expo()))
+                return e;
         KS_HIP(hipEventRecord(e1, g->stream));
         KS_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
         KS_HIP(hipEventElapsedTime(&ms, e0, e1));
-        const double us = 1e3 * ms / reps;
+        const double us = 1e3 * ms / (4.0 * reps);
         if (us < best) {
             best = us;
             bestTY = g->TY;
             bestz = g->zchunk;
+            bestr = g->rpt;
         }
         return KS_OK;
     };
-    rc = KS_OK;
-    // the default shape first, then every candidate pair
-    rc = run(oldTY, oldz);
-    for (int ty : tys) {
-        if (rc || ty < 1 || ty > m)
-            continue;
+    // the default shape first, then every candidate
+    rc = run(oldTY, oldz, oldr);
+    for (auto &sh : shapes)
         for (int zc : zcs)
             if (!rc)
-                rc = run(ty, zc);
-    }
+                rc = run(sh.first, zc, sh.second);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    set_tiles(g, rc ? oldTY : bestTY, rc ? oldz : bestz);
+    if (rc)
+        set_tiles(g, oldTY, oldz, oldr);
+    else
+        set_tiles(g, bestTY, bestz, bestr);
     layout(g);
     if (rc)
         return rc;
@@ -1065,20 +1078,22 @@ int ks_autotune(ks_grid *g, const void *d_psi, int reps, int out_shape[2],
     if (out_shape) {
         out_shape[0] = g->TY;
         out_shape[1] = g->zchunk;
+        out_shape[2] = g->rpt;
     }
     if (out_us)
         *out_us = best;
     return KS_OK;
 }
 
-int ks_get_launch(const ks_grid *g, int out[4])
+int ks_get_launch(const ks_grid *g, int out[5])
 {
     if (!g || !out)
         return fail(KS_E_ARG, "NULL argument");
     out[0] = g->TY;
     out[1] = g->zchunk;
     out[2] = g->ntile_y * g->nzc * g->stot;
-    out[3] = hpsi_threads(g->geo.nx, g->TY);
+    out[3] = hpsi_threads(g->geo.nx, g->TY, g->rpt);
+    out[4] = g->rpt;
     return KS_OK;
 }
 
@@ -1556,7 +1571,7 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
         if (g->laser[0] != 0.0)
             b->grad = true;
         b->hm = std::max(b->hm, hpsi_halo_per_thread(g->geo, g->TY, 512));
-        b->rpt = std::max(b->rpt, hpsi_rpt(g->geo.nx, g->TY));
+        b->rpt = std::max(b->rpt, g->rpt);
         b->lds = std::max(b->lds, lds_for(g, g->TY, g->zchunk));
     }
     if (b->rpt == 2 && b->hm > 8) {

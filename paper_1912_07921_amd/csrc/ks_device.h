@@ -299,9 +299,9 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w)
     const int perx = a.geo.per[0], pery = a.geo.per[1], perz = a.geo.per[2];
 
     const int TY = a.TY;
-    // rows per thread of this tile shape (the launch's RPT is the most any
-    // item of it needs)
-    const int rpt = (RPT > 1 && nx * TY > kRowThreads) ? 2 : 1;
+    // rows per thread of this item's shape (the launch's RPT is the most
+    // any item of it uses)
+    const int rpt = RPT > 1 ? a.rpt : 1;
     const int TYh = (TY + rpt - 1) / rpt;
     const int y0 = tile_y * TY;
     const int rows = min(TY, ny - y0);

@@ -32,14 +32,8 @@ __global__ __launch_bounds__(512) KS_HPSI_ATTR void k_hpsi(HArgs a)
 // launchers
 // ---------------------------------------------------------------------------
 #if KS_HPSI_PART == 0
-int hpsi_rpt(int nx, int TY)
+int hpsi_threads(int nx, int TY, int rpt)
 {
-    return nx * TY > kRowThreads ? 2 : 1;
-}
-
-int hpsi_threads(int nx, int TY)
-{
-    const int rpt = hpsi_rpt(nx, TY);
     const int want = std::max(nx * ((TY + rpt - 1) / rpt), 64);
     return ((want + 63) / 64) * 64;
 }
@@ -66,12 +60,12 @@ size_t hpsi_lds_bytes(int nx, int TY, int zchunk, bool mixed)
 template <class R, class InT, class TT, int MODE, bool GRAD>
 static hipError_t go_hpsi2(const HArgs &a, int ns, hipStream_t st)
 {
-    const int nthr = hpsi_threads(a.geo.nx, a.TY);
+    const int nthr = hpsi_threads(a.geo.nx, a.TY, a.rpt);
     const size_t lds = hpsi_lds_bytes(a.geo.nx, a.TY, a.zchunk,
                                       sizeof(R) == 4);
     dim3 grid((unsigned)(a.ntile_y * a.nzc * ns));
     const int hm = hpsi_halo_per_thread(a.geo, a.TY, nthr);
-    if (hpsi_rpt(a.geo.nx, a.TY) == 2) {
+    if (a.rpt == 2) {
         if (hm <= 2)
             hipLaunchKernelGGL((k_hpsi<R, InT, TT, MODE, GRAD, 2, 2>), grid,
                                dim3(nthr), lds, st, a);

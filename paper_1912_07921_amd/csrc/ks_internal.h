@@ -83,6 +83,7 @@ struct HArgs {
     const void *W = nullptr;       // [ns][nhull] V_NL in on the hull
     int nhull = 0;
     int TY = 1, zchunk = 1, ntile_y = 1, nzc = 1;
+    int rpt = 1;                   // rows marched per thread (1 or 2)
 };
 
 // LDS one workgroup may use (gfx950: 160 KiB per workgroup), and the most
@@ -90,8 +91,7 @@ struct HArgs {
 constexpr size_t kLdsBudget = 163840;
 constexpr size_t kLdsDefault = 98304;
 
-// Threads of one row set of the H.psi kernel: a tile of TY rows with
-// nx * TY above this is marched two rows per thread.
+// Most threads of one H.psi workgroup.
 constexpr int kRowThreads = 512;
 
 struct GArgs {
@@ -122,8 +122,7 @@ struct DArgs {
 };
 
 // Launch shape of the H.psi kernel.
-int hpsi_rpt(int nx, int TY);
-int hpsi_threads(int nx, int TY);
+int hpsi_threads(int nx, int TY, int rpt);
 int hpsi_halo_per_thread(const Geo &g, int TY, int nthr);
 size_t hpsi_lds_bytes(int nx, int TY, int zchunk, bool mixed);
 

@@ -90,7 +90,7 @@ EXPORTS = {
     "ks_gram": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ks_energy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                             C.POINTER(C.c_double)]),
-    "ks_set_launch": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    "ks_set_launch": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
     "ks_get_launch": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
     "ks_profile_begin": (C.c_int, [C.c_void_p, C.c_int]),
     "ks_profile_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
@@ -258,15 +258,16 @@ def ks_energy(h, psi, vion, t):
     return out.value
 
 
-def ks_set_launch(h, tile_rows, zchunk):
-    return _check(lib().ks_set_launch(h, int(tile_rows), int(zchunk)))
+def ks_set_launch(h, tile_rows, zchunk, rows_per_thread=0):
+    return _check(lib().ks_set_launch(h, int(tile_rows), int(zchunk),
+                                      int(rows_per_thread)))
 
 
 def ks_get_launch(h):
-    out = (C.c_int * 4)()
+    out = (C.c_int * 5)()
     _check(lib().ks_get_launch(h, out))
     return dict(tile_rows=out[0], zchunk=out[1], workgroups=out[2],
-                threads=out[3])
+                threads=out[3], rows_per_thread=out[4])
 
 
 def ks_profile_begin(h, capacity):
@@ -284,11 +285,12 @@ def ks_profile_end(h):
 
 
 def ks_autotune(h, psi, reps=3):
-    """Returns (tile_rows, zchunk, microseconds per H.psi pass)."""
-    shape = (C.c_int * 2)()
+    """Returns (tile_rows, zchunk, rows_per_thread, microseconds per H.psi
+    pass)."""
+    shape = (C.c_int * 3)()
     us = C.c_double()
     _check(lib().ks_autotune(h, _ptr(psi), int(reps), shape, C.byref(us)))
-    return shape[0], shape[1], us.value
+    return shape[0], shape[1], shape[2], us.value
 
 
 def ks_batch_create(jobs, stream):
@@ -451,9 +453,9 @@ class Grid:
         ks_gram(self.h, psi, out)
         return out
 
-    def set_launch(self, tile_rows=0, zchunk=0):
+    def set_launch(self, tile_rows=0, zchunk=0, rows_per_thread=0):
         try:
-            ks_set_launch(self.h, tile_rows, zchunk)
+            ks_set_launch(self.h, tile_rows, zchunk, rows_per_thread)
         except KSError as e:
             if e.code == -2:       # workspace too small: lend a larger one
                 self._alloc_ws()
@@ -465,7 +467,7 @@ class Grid:
 
     def autotune(self, psi, reps=3):
         """Pick the fastest launch shape on these states; returns
-        (tile_rows, zchunk, us per pass)."""
+        (tile_rows, zchunk, rows_per_thread, us per pass)."""
         self._psi(psi)
         return ks_autotune(self.h, psi, reps)
 

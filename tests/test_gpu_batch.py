@@ -211,10 +211,11 @@ def test_autotune_changes_speed_only(torch_cuda, prec):
     d_ref, n_ref = ref.propagate_etrs(p_ref, dev(torch, v), 3, 0.01)
     g = ks.Grid(spec, precision=prec)
     p = dev(torch, psi)
-    ty, zc, us = g.autotune(p, reps=2)
+    ty, zc, rpt, us = g.autotune(p, reps=2)
     sh = g.get_launch()
-    assert (sh["tile_rows"], sh["zchunk"]) == (ty, zc)
-    assert 1 <= ty <= 27 and 1 <= zc <= 33 and us > 0
+    assert (sh["tile_rows"], sh["zchunk"], sh["rows_per_thread"]) == \
+        (ty, zc, rpt)
+    assert 1 <= ty <= 27 and 1 <= zc <= 33 and rpt in (1, 2) and us > 0
     g.update_vlocal(dev(torch, v))
     assert np.array_equal(g.apply_h(p[0]).cpu().numpy(), h_ref)
     d, n = g.propagate_etrs(p, dev(torch, v), 3, 0.01)

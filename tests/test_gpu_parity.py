@@ -285,12 +285,15 @@ def test_apply_h_independent_of_launch_shape(torch_cuda, oracle_mod):
     ref = g.apply_h(dpsi).cpu().numpy()
     want = oracle_mod.Oracle(spec).apply_h(v, psi[0])
     assert rel_err(ref, want) < 1e-12
-    # 12 rows: one row per thread; 20 and 24 rows: two rows per thread
-    for ty, zc in [(1, 0), (2, 5), (3, 33), (7, 1), (12, 16), (12, 0),
-                   (20, 0), (24, 7)]:
-        g.set_launch(ty, zc)
+    # (tile rows, z-chunk, rows per thread)
+    for ty, zc, rpt in [(1, 0, 1), (2, 5, 1), (3, 33, 1), (7, 1, 1),
+                        (12, 16, 1), (12, 0, 1), (20, 0, 2), (24, 7, 2),
+                        (8, 3, 2), (5, 0, 2), (2, 9, 2)]:
+        g.set_launch(ty, zc, rpt)
+        sh = g.get_launch()
+        assert (sh["tile_rows"], sh["rows_per_thread"]) == (ty, rpt)
         got = g.apply_h(dpsi).cpu().numpy()
-        assert np.array_equal(got, ref), (ty, zc)
+        assert np.array_equal(got, ref), (ty, zc, rpt)
 
 
 def test_propagate_independent_of_launch_shape(torch_cuda, oracle_mod):
