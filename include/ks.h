@@ -201,14 +201,16 @@ int ks_set_launch(ks_grid *g, int tile_rows, int zchunk, int rows_per_thread);
 int ks_get_launch(const ks_grid *g, int out[5]);
 
 /* Kernel timing with HIP events on the grid's stream.  After
- * ks_profile_begin(g, capacity), every later launch of the H.psi kernel
- * (class 0), of the projector gather (class 1), of the density / reduction
- * kernels (class 2) and of the projector apply (class 3) is bracketed by a
- * pair of events, up to `capacity` pairs.  ks_profile_end() waits for the
- * stream, stops recording and returns per class the summed kernel time (ms)
- * and the number of launches timed, in out_ms[4] and out_count[4] (host
- * arrays). */
-int ks_profile_begin(ks_grid *g, int capacity);
+ * ks_profile_begin(g, capacity, class_mask), every later launch of the
+ * H.psi kernel (class 0), of the projector gather (class 1), of the density
+ * / reduction kernels (class 2) and of the projector apply (class 3) whose
+ * bit is set in class_mask (1 << class) is bracketed by a pair of events,
+ * up to `capacity` pairs.  ks_profile_end() waits for the stream, stops
+ * recording and returns per class the summed kernel time (ms) and the
+ * number of launches timed, in out_ms[4] and out_count[4] (host arrays).
+ * Events between launches cost time of their own: time throughput with
+ * profiling off, or with only the class of interest on. */
+int ks_profile_begin(ks_grid *g, int capacity, int class_mask);
 int ks_profile_end(ks_grid *g, double out_ms[4], long out_count[4]);
 
 /* Autotuner: time the four H.psi passes of one Taylor exponential (the

@@ -88,6 +88,7 @@ struct ks_grid {
     std::vector<int> ev_class;
     int ev_used = 0;
     bool profiling = false;
+    int prof_mask = 0xf;
 };
 
 namespace {
@@ -436,7 +437,8 @@ struct Timed {
     int slot = -1;
     Timed(ks_grid *gg, int c) : g(gg)
     {
-        if (g->profiling && g->ev_used < (int)g->ev_class.size()) {
+        if (g->profiling && ((g->prof_mask >> c) & 1) &&
+            g->ev_used < (int)g->ev_class.size()) {
             slot = g->ev_used++;
             g->ev_class[slot] = c;
             (void)hipEventRecord(g->ev[2 * slot], g->stream);
@@ -1097,10 +1099,11 @@ int ks_get_launch(const ks_grid *g, int out[5])
     return KS_OK;
 }
 
-int ks_profile_begin(ks_grid *g, int capacity)
+int ks_profile_begin(ks_grid *g, int capacity, int class_mask)
 {
-    if (!g || capacity < 1)
-        return fail(KS_E_ARG, "grid is NULL or capacity < 1");
+    if (!g || capacity < 1 || (class_mask & ~0xf) || !class_mask)
+        return fail(KS_E_ARG, "grid is NULL, capacity < 1 or bad mask");
+    g->prof_mask = class_mask;
     while ((int)g->ev_class.size() < capacity) {
         hipEvent_t a, b;
         KS_HIP(hipEventCreate(&a));
@@ -1399,7 +1402,7 @@ struct ks_batch {
     std::vector<JobDev> hjobs;
     hipStream_t stream = nullptr;
     bool mixed = false, grad = false;
-    int hm = 2, rpt = 1;
+    int hm = 2, rpt = 1, nthr = 64;
     size_t lds = 0;
     int grid_hpsi = 0, grid_proj = 0;
     std::vector<void *> owned;
@@ -1450,7 +1453,7 @@ int batch_enqueue_step(ks_batch *b)
                                            batch_args(b, kItemApply, p),
                                            b->grid_proj, st));
             KS_HIP(launch_pass_batch(b->mixed, batch_args(b, kItemHpsi, p),
-                                     b->grad, b->hm, b->rpt, b->lds,
+                                     b->grad, b->hm, b->rpt, b->nthr, b->lds,
                                      b->grid_hpsi, st));
         }
         if (e == 0)
@@ -1570,10 +1573,14 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
         b->hjobs.push_back(J);
         if (g->laser[0] != 0.0)
             b->grad = true;
-        b->hm = std::max(b->hm, hpsi_halo_per_thread(g->geo, g->TY, 512));
         b->rpt = std::max(b->rpt, g->rpt);
+        b->nthr = std::max(b->nthr, hpsi_threads(g->geo.nx, g->TY, g->rpt));
         b->lds = std::max(b->lds, lds_for(g, g->TY, g->zchunk));
     }
+    // halo loads per thread for the workgroup size of the batch (the
+    // largest any job asks for)
+    for (ks_grid *g : b->grids)
+        b->hm = std::max(b->hm, hpsi_halo_per_thread(g->geo, g->TY, b->nthr));
     if (b->rpt == 2 && b->hm > 8) {
         ks_batch_destroy(b);
         return fail(KS_E_UNSUPPORTED, "batch halo too large for two-row "

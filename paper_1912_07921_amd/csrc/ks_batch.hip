@@ -20,46 +20,64 @@ namespace ks {
 // job table and the job's device step counter, so a captured step replays
 // unchanged.
 // ---------------------------------------------------------------------------
+// The job table, item offsets, A(t) tables and step counters do not change
+// while a batch kernel runs: read them through the constant address space
+// (scalar loads into SGPRs, shared by the whole wavefront).
+template <class T> using cptr_t = __attribute__((address_space(4))) const T *;
+template <class T> __device__ __forceinline__ cptr_t<T> cp(const T *p)
+{
+    return (cptr_t<T>)p;
+}
+
+// a whole struct read through the constant address space
+template <class T> __device__ __forceinline__ T cload(cptr_t<T> p)
+{
+    T v;
+    __builtin_memcpy(&v, (const T *)p, sizeof(T));
+    return v;
+}
+
 __device__ __forceinline__ int find_job(const int *off, int njobs, int item)
 {
     int j = 0;
-    while (j + 1 < njobs && item >= off[j + 1])
+    while (j + 1 < njobs && item >= cp(off)[j + 1])
         ++j;
     return j;
 }
 
 // input of Taylor pass p: exponential 0 starts from psi, 1 from psi_half
-__device__ __forceinline__ const void *pass_input(const JobDev &J, int p)
+__device__ __forceinline__ const void *pass_input(cptr_t<JobDev> J, int p)
 {
     const int e = (p - 1) / 4, j = (p - 1) % 4 + 1;
     if (j == 1)
-        return e == 0 ? (const void *)J.psi : (const void *)J.half;
-    return J.t[j - 2];
+        return e == 0 ? (const void *)J->psi : (const void *)J->half;
+    return J->t[j - 2];
 }
 
-__device__ __forceinline__ HArgs pass_hargs(const JobDev &J, int p)
+__device__ __forceinline__ HArgs pass_hargs(cptr_t<JobDev> J, int p)
 {
-    HArgs a = J.h;
+    HArgs a = cload<HArgs>(&J->h);
     const int e = (p - 1) / 4, j = (p - 1) % 4 + 1;
-    const double4 Av = J.Atab[2 * *J.step + e];   // A(t0 + (step + e) dt)
+    // A(t0 + (step + e) dt)
+    const double4 Av = cload<double4>(cp(J->Atab) + 2 * *cp(J->step) + e);
     a.A[0] = Av.x;
     a.A[1] = Av.y;
     a.A[2] = Av.z;
     a.a2half = Av.w;
     a.in = pass_input(J, p);
-    a.v = e == 0 ? J.vcur : (J.xc ? J.vpred : J.vion);
+    a.v = e == 0 ? J->vcur : (J->xc ? J->vpred : J->vion);
     a.cre = 0.0;
-    a.cim = -0.5 * J.dt / j;
+    a.cim = -0.5 * J->dt / j;
     if (j < 4) {
-        a.out = J.t[j - 1];
+        a.out = J->t[j - 1];
     } else {
-        a.out = e == 0 ? (void *)J.half : (void *)J.psi;
-        a.base = e == 0 ? J.psi : J.half;
-        a.t1 = J.t[0];
-        a.t2 = J.t[1];
-        a.npart = e == 0 ? (J.xc ? J.npart : nullptr)
-                         : (J.npart_end ? J.npart : nullptr);
-        a.normpart = e == 1 ? J.normpart_end : nullptr;
+        a.out = e == 0 ? (void *)J->half : (void *)J->psi;
+        a.base = e == 0 ? J->psi : J->half;
+        a.t1 = J->t[0];
+        a.t2 = J->t[1];
+        a.npart = e == 0 ? (J->xc ? J->npart : nullptr)
+                         : (J->npart_end ? J->npart : nullptr);
+        a.normpart = e == 1 ? J->normpart_end : nullptr;
     }
     return a;
 }
@@ -67,12 +85,12 @@ __device__ __forceinline__ HArgs pass_hargs(const JobDev &J, int p)
 template <class R, class InT, class TT, int MODE, bool GRAD, int HM, int RPT>
 __global__ __launch_bounds__(512) void k_hpsi_batch(BArgs b)
 {
-    const int total = b.off[b.njobs];
+    const int total = cp(b.off)[b.njobs];
     for (int L = blockIdx.x; L < total; L += gridDim.x) {
         const int item = xcd_remap(L, total);
         const int jb = find_job(b.off, b.njobs, item);
-        const HArgs a = pass_hargs(b.jobs[jb], b.pass);
-        hpsi_item<R, InT, TT, MODE, GRAD, HM, RPT>(a, item - b.off[jb]);
+        const HArgs a = pass_hargs(cp(b.jobs) + jb, b.pass);
+        hpsi_item<R, InT, TT, MODE, GRAD, HM, RPT>(a, item - cp(b.off)[jb]);
         __syncthreads();   // LDS is reused by the next item
     }
 }
@@ -80,13 +98,13 @@ __global__ __launch_bounds__(512) void k_hpsi_batch(BArgs b)
 template <class R, class InT>
 __global__ __launch_bounds__(256) void k_gather_batch(BArgs b)
 {
-    const int total = b.off[b.njobs];
+    const int total = cp(b.off)[b.njobs];
     for (int L = blockIdx.x; L < total; L += gridDim.x) {
         const int jb = find_job(b.off, b.njobs, L);
-        const JobDev &J = b.jobs[jb];
-        GArgs a = J.g;
+        const cptr_t<JobDev> J = cp(b.jobs) + jb;
+        GArgs a = cload<GArgs>(&J->g);
         a.in = pass_input(J, b.pass);
-        int r = L - b.off[jb];
+        int r = L - cp(b.off)[jb];
         const int ch = r % a.nchunk;
         r /= a.nchunk;
         const int ngrp = (a.ns + kGatherStates - 1) / kGatherStates;
@@ -98,11 +116,12 @@ __global__ __launch_bounds__(256) void k_gather_batch(BArgs b)
 template <class R>
 __global__ __launch_bounds__(256) void k_gather_finalize_batch(BArgs b)
 {
-    const int total = b.off[b.njobs];
+    const int total = cp(b.off)[b.njobs];
     for (int L = blockIdx.x; L < total; L += gridDim.x) {
         const int jb = find_job(b.off, b.njobs, L);
-        gather_finalize_item<R>(b.jobs[jb].g,
-                                (long)(L - b.off[jb]) * blockDim.x +
+        const GArgs g = cload<GArgs>(&(cp(b.jobs) + jb)->g);
+        gather_finalize_item<R>(g,
+                                (long)(L - cp(b.off)[jb]) * blockDim.x +
                                     threadIdx.x);
     }
 }
@@ -110,11 +129,11 @@ __global__ __launch_bounds__(256) void k_gather_finalize_batch(BArgs b)
 template <class R>
 __global__ __launch_bounds__(256) void k_kbapply_batch(BArgs b)
 {
-    const int total = b.off[b.njobs];
+    const int total = cp(b.off)[b.njobs];
     for (int L = blockIdx.x; L < total; L += gridDim.x) {
         const int jb = find_job(b.off, b.njobs, L);
-        const GArgs &a = b.jobs[jb].g;
-        const int r = L - b.off[jb];
+        const GArgs a = cload<GArgs>(&(cp(b.jobs) + jb)->g);
+        const int r = L - cp(b.off)[jb];
         kbapply_item<R>(a, r % a.pj.nhchunk, r / a.pj.nhchunk);
     }
 }
@@ -162,37 +181,37 @@ int batch_items(int kind, const JobDev &J)
 #endif
 
 template <class R, class InT, class TT, int MODE, bool GRAD>
-static hipError_t go_hpsi_batch(const BArgs &b, int hm, int rpt, size_t lds,
-                                int grid, hipStream_t st)
+static hipError_t go_hpsi_batch(const BArgs &b, int hm, int rpt, int nthr,
+                                size_t lds, int grid, hipStream_t st)
 {
     if (rpt == 2) {
         if (hm <= 2)
             hipLaunchKernelGGL((k_hpsi_batch<R, InT, TT, MODE, GRAD, 2, 2>),
-                               dim3(grid), dim3(512), lds, st, b);
+                               dim3(grid), dim3(nthr), lds, st, b);
         else if (hm <= 4)
             hipLaunchKernelGGL((k_hpsi_batch<R, InT, TT, MODE, GRAD, 4, 2>),
-                               dim3(grid), dim3(512), lds, st, b);
+                               dim3(grid), dim3(nthr), lds, st, b);
         else
             hipLaunchKernelGGL((k_hpsi_batch<R, InT, TT, MODE, GRAD, 8, 2>),
-                               dim3(grid), dim3(512), lds, st, b);
+                               dim3(grid), dim3(nthr), lds, st, b);
         return hipGetLastError();
     }
     switch (hm) {
     case 2:
         hipLaunchKernelGGL((k_hpsi_batch<R, InT, TT, MODE, GRAD, 2, 1>),
-                           dim3(grid), dim3(512), lds, st, b);
+                           dim3(grid), dim3(nthr), lds, st, b);
         break;
     case 4:
         hipLaunchKernelGGL((k_hpsi_batch<R, InT, TT, MODE, GRAD, 4, 1>),
-                           dim3(grid), dim3(512), lds, st, b);
+                           dim3(grid), dim3(nthr), lds, st, b);
         break;
     case 8:
         hipLaunchKernelGGL((k_hpsi_batch<R, InT, TT, MODE, GRAD, 8, 1>),
-                           dim3(grid), dim3(512), lds, st, b);
+                           dim3(grid), dim3(nthr), lds, st, b);
         break;
     default:
         hipLaunchKernelGGL((k_hpsi_batch<R, InT, TT, MODE, GRAD, 16, 1>),
-                           dim3(grid), dim3(512), lds, st, b);
+                           dim3(grid), dim3(nthr), lds, st, b);
         break;
     }
     return hipGetLastError();
@@ -200,50 +219,54 @@ static hipError_t go_hpsi_batch(const BArgs &b, int hm, int rpt, size_t lds,
 
 template <class R, class InT, class TT, int MODE>
 static hipError_t go_hpsi_batch_g(const BArgs &b, bool grad, int hm, int rpt,
-                                  size_t lds, int grid, hipStream_t st)
+                                  int nthr, size_t lds, int grid,
+                                  hipStream_t st)
 {
-    return grad ? go_hpsi_batch<R, InT, TT, MODE, true>(b, hm, rpt, lds,
-                                                        grid, st)
-                : go_hpsi_batch<R, InT, TT, MODE, false>(b, hm, rpt, lds,
-                                                         grid, st);
+    return grad ? go_hpsi_batch<R, InT, TT, MODE, true>(b, hm, rpt, nthr,
+                                                        lds, grid, st)
+                : go_hpsi_batch<R, InT, TT, MODE, false>(b, hm, rpt, nthr,
+                                                         lds, grid, st);
 }
 
 // Compiled twice like the single-grid H.psi file: part 0 holds the FP64
 // pass kernels and everything else, part 1 the mixed-precision pass kernels.
 hipError_t launch_pass_batch_mixed(const BArgs &b, bool grad, int hm, int rpt,
-                                   size_t lds, int grid, hipStream_t st);
+                                   int nthr, size_t lds, int grid,
+                                   hipStream_t st);
 
 #if KS_HPSI_PART == 0
 hipError_t launch_pass_batch(bool mixed, const BArgs &b, bool grad, int hm,
-                             int rpt, size_t lds, int grid, hipStream_t st)
+                             int rpt, int nthr, size_t lds, int grid,
+                             hipStream_t st)
 {
     if (mixed)
-        return launch_pass_batch_mixed(b, grad, hm, rpt, lds, grid, st);
+        return launch_pass_batch_mixed(b, grad, hm, rpt, nthr, lds, grid, st);
     const int j = (b.pass - 1) % 4 + 1, e = (b.pass - 1) / 4;
     using D2 = double2;
     if (j < 4)
-        return go_hpsi_batch_g<double, D2, D2, kTerm>(b, grad, hm, rpt, lds,
-                                                      grid, st);
+        return go_hpsi_batch_g<double, D2, D2, kTerm>(b, grad, hm, rpt, nthr,
+                                                      lds, grid, st);
     return e == 0 ? go_hpsi_batch_g<double, D2, D2, kFinalPred>(
-                        b, grad, hm, rpt, lds, grid, st)
+                        b, grad, hm, rpt, nthr, lds, grid, st)
                   : go_hpsi_batch_g<double, D2, D2, kFinal>(
-                        b, grad, hm, rpt, lds, grid, st);
+                        b, grad, hm, rpt, nthr, lds, grid, st);
 }
 #else
 hipError_t launch_pass_batch_mixed(const BArgs &b, bool grad, int hm, int rpt,
-                                   size_t lds, int grid, hipStream_t st)
+                                   int nthr, size_t lds, int grid,
+                                   hipStream_t st)
 {
     const int j = (b.pass - 1) % 4 + 1, e = (b.pass - 1) / 4;
     if (j == 1)
         return go_hpsi_batch_g<float, double2, float2, kTerm>(
-            b, grad, hm, rpt, lds, grid, st);
+            b, grad, hm, rpt, nthr, lds, grid, st);
     if (j < 4)
         return go_hpsi_batch_g<float, float2, float2, kTerm>(
-            b, grad, hm, rpt, lds, grid, st);
+            b, grad, hm, rpt, nthr, lds, grid, st);
     return e == 0 ? go_hpsi_batch_g<float, float2, float2, kFinalPred>(
-                        b, grad, hm, rpt, lds, grid, st)
+                        b, grad, hm, rpt, nthr, lds, grid, st)
                   : go_hpsi_batch_g<float, float2, float2, kFinal>(
-                        b, grad, hm, rpt, lds, grid, st);
+                        b, grad, hm, rpt, nthr, lds, grid, st);
 }
 #endif
 

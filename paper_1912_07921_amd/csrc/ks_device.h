@@ -92,10 +92,55 @@ template <class V> __device__ __forceinline__ V cmulc(V a, V b)
     return r;
 }
 
+// Every buffer the kernels touch is global memory.  Accesses go through an
+// explicitly global pointer, so that pointers read from memory (the job
+// table of the batched form) compile to global, not flat, instructions.
+template <class T> using gptr_t = __attribute__((address_space(1))) T *;
+template <class T> __device__ __forceinline__ gptr_t<T> gp(T *p)
+{
+    return (gptr_t<T>)p;
+}
+
+// Loads and stores of the HIP vector classes through global pointers go by
+// the compiler's native vector types.
+typedef double gd2_t __attribute__((ext_vector_type(2)));
+typedef float gf2_t __attribute__((ext_vector_type(2)));
+typedef double gd4_t __attribute__((ext_vector_type(4)));
+typedef int gi4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double2 gld(const double2 *p)
+{
+    const gd2_t v = *gp(reinterpret_cast<const gd2_t *>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 gld(const float2 *p)
+{
+    const gf2_t v = *gp(reinterpret_cast<const gf2_t *>(p));
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double4 gld(const double4 *p)
+{
+    const gd4_t v = *gp(reinterpret_cast<const gd4_t *>(p));
+    return make_double4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ int4 gld(const int4 *p)
+{
+    const gi4_t v = *gp(reinterpret_cast<const gi4_t *>(p));
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gst(double2 *p, double2 v)
+{
+    *gp(reinterpret_cast<gd2_t *>(p)) = gd2_t{v.x, v.y};
+}
+__device__ __forceinline__ void gst(float2 *p, float2 v)
+{
+    *gp(reinterpret_cast<gf2_t *>(p)) = gf2_t{v.x, v.y};
+}
+
 template <class R, class T> __device__ __forceinline__ typename Cplx<R>::T
 ldc(const T *p, long i)
 {
-    T v = p[i];
+    T v = gld(p + i);
     typename Cplx<R>::T r;
     r.x = (R)v.x;
     r.y = (R)v.y;
@@ -119,44 +164,46 @@ __device__ __forceinline__ void st_stream(double2 *p, double x, double y)
 {
 #if KS_NT_STORE
     nd2_t v = {x, y};
-    __builtin_nontemporal_store(v, reinterpret_cast<nd2_t *>(p));
+    __builtin_nontemporal_store(v, gp(reinterpret_cast<nd2_t *>(p)));
 #else
-    *p = make_double2(x, y);
+    gst(p, make_double2(x, y));
 #endif
 }
 __device__ __forceinline__ void st_stream(float2 *p, float x, float y)
 {
 #if KS_NT_STORE
     nf2_t v = {x, y};
-    __builtin_nontemporal_store(v, reinterpret_cast<nf2_t *>(p));
+    __builtin_nontemporal_store(v, gp(reinterpret_cast<nf2_t *>(p)));
 #else
-    *p = make_float2(x, y);
+    gst(p, make_float2(x, y));
 #endif
 }
 __device__ __forceinline__ void st_stream(double *p, double x)
 {
 #if KS_NT_STORE
-    __builtin_nontemporal_store(x, p);
+    __builtin_nontemporal_store(x, gp(p));
 #else
-    *p = x;
+    *gp(p) = x;
 #endif
 }
 __device__ __forceinline__ double2 ld_stream(const double2 *p)
 {
 #if KS_NT_LOAD
-    const nd2_t v = __builtin_nontemporal_load(reinterpret_cast<const nd2_t *>(p));
+    const nd2_t v =
+        __builtin_nontemporal_load(gp(reinterpret_cast<const nd2_t *>(p)));
     return make_double2(v.x, v.y);
 #else
-    return *p;
+    return gld(p);
 #endif
 }
 __device__ __forceinline__ float2 ld_stream(const float2 *p)
 {
 #if KS_NT_LOAD
-    const nf2_t v = __builtin_nontemporal_load(reinterpret_cast<const nf2_t *>(p));
+    const nf2_t v =
+        __builtin_nontemporal_load(gp(reinterpret_cast<const nf2_t *>(p)));
     return make_float2(v.x, v.y);
 #else
-    return *p;
+    return gld(p);
 #endif
 }
 
@@ -205,7 +252,8 @@ __device__ __forceinline__ void block_sum(T (&v)[NV], T *sbuf)
 template <class V>
 __device__ __forceinline__ V phase_pow(const double2 *kph, int axis, int w)
 {
-    V ph = cmk<V>(kph[axis].x, kph[axis].y);
+    const double2 kv = gld(kph + axis);
+    V ph = cmk<V>(kv.x, kv.y);
     if (w < 0) {
         ph.y = -ph.y;
         w = -w;
@@ -354,8 +402,10 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w)
     if (proj)
         for (int t = tid; t < (z1 - z0) * TY; t += nthr) {
             const int zz = z0 + t / TY, r = t % TY;
-            sRow[t] = r < rows ? a.rowinfo[zz * ny + y0 + r]
-                               : make_int4(1, 0, 0, 0);
+            int4 ri = make_int4(1, 0, 0, 0);
+            if (r < rows)
+                ri = gld(a.rowinfo + zz * ny + y0 + r);
+            sRow[t] = ri;
         }
 
     // ---- halo of the padded plane: 8 rows of nx and 8 columns of rows+8.
@@ -441,12 +491,12 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w)
         if (proj && act[r]) {
             const int4 ri = sRow[(zq - z0) * TY + ylr[r]];
             if (x >= ri.x && x <= ri.y)
-                v = Wst[ri.z + x - ri.x];
+                v = gld(Wst + ri.z + x - ri.x);
         }
         return v;
     };
     auto v_val = [&](int r, int zq) -> double {
-        return act[r] ? a.v[(long)zq * P + po[r]] : 0.0;
+        return act[r] ? gp(a.v)[(long)zq * P + po[r]] : 0.0;
     };
 
     // ---- prologue ----
@@ -495,7 +545,7 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w)
             Az = (R)(a.A[2] / a.geo.h[2]);
     const V cs = cmk<V>(a.cre, a.cim);
     const double w_occ = (MODE == kFinal || MODE == kFinalPred)
-                             ? a.wocc[sg] : 0.0;
+                             ? gp(a.wocc)[sg] : 0.0;
     double nrm = 0.0;
     V *cur = buf0, *nxt = buf1;
     for (int z = z0; z < z1; ++z) {
@@ -623,7 +673,7 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w)
         double vals[1] = {nrm};
         block_sum<double, 1>(vals, reinterpret_cast<double *>(smem_raw));
         if (tid == 0)
-            a.normpart[(size_t)sl * ntiles + tile] = vals[0];
+            gp(a.normpart)[(size_t)sl * ntiles + tile] = vals[0];
     }
 }
 
@@ -681,11 +731,11 @@ __device__ __forceinline__ void gather_item(const GArgs &a, const int at,
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int s0 = grp * kGatherStates + wave * kGatherSPW;
-    const int np = a.pj.nproj[at];
-    const int npt = a.pj.npts[at];
-    const long io = a.pj.ioff[at];
-    const double4 ap = a.pj.apos[at];
-    const double2 ar = a.pj.arad[at];
+    const int np = gp(a.pj.nproj)[at];
+    const int npt = gp(a.pj.npts)[at];
+    const long io = gp(a.pj.ioff)[at];
+    const double4 ap = gld(a.pj.apos + at);
+    const double2 ar = gld(a.pj.arad + at);
     const int nx = a.geo.nx, ny = a.geo.ny, nz = a.geo.nz;
     const double Lx = nx * a.geo.h[0], Ly = ny * a.geo.h[1],
                  Lz = nz * a.geo.h[2];
@@ -698,9 +748,9 @@ __device__ __forceinline__ void gather_item(const GArgs &a, const int at,
     for (int u = 0; u < U; ++u) {
         const int pt = p0 + lane + 64 * u;
         const bool ok = pt < p1;
-        gi[u] = ok ? a.pj.sidx[io + pt] : -1;
-        pk[u] = ok ? a.pj.sxyz[io + pt] : 0;
-        code[u] = ok ? a.pj.sshift[io + pt] : 0;
+        gi[u] = ok ? gp(a.pj.sidx)[io + pt] : -1;
+        pk[u] = ok ? gp(a.pj.sxyz)[io + pt] : 0;
+        code[u] = ok ? gp(a.pj.sshift)[io + pt] : 0;
     }
     V val[U][kGatherSPW];
 #pragma unroll
@@ -779,7 +829,7 @@ __device__ __forceinline__ void gather_item(const GArgs &a, const int at,
             R *part = reinterpret_cast<R *>(a.Dpart) +
                       2 * ((((size_t)sl * a.pj.natoms + at) * a.nchunk + ch) *
                            kMaxProj);
-            part[jj] = sum;        // (j, re/im) interleaved as in V
+            gp(part)[jj] = sum;    // (j, re/im) interleaved as in V
         }
     }
 }
@@ -796,18 +846,18 @@ __device__ __forceinline__ void gather_finalize_item(const GArgs &a,
     const int j = (int)(i % kMaxProj);
     const long sa = i / kMaxProj;           // s * natoms + atom
     const int at = (int)(sa % a.pj.natoms);
-    const int nch = (a.pj.npts[at] + kGatherChunk - 1) / kGatherChunk;
+    const int nch = (gp(a.pj.npts)[at] + kGatherChunk - 1) / kGatherChunk;
     const V *part = reinterpret_cast<const V *>(a.Dpart) +
                     (size_t)sa * a.nchunk * kMaxProj + j;
     R re = 0, im = 0;
     for (int c = 0; c < nch; ++c) {
-        V v = part[(size_t)c * kMaxProj];
+        const V v = gld(part + (size_t)c * kMaxProj);
         re += v.x;
         im += v.y;
     }
-    const R e = (j < a.pj.nproj[at]) ? (R)a.pj.EjN2[at * kMaxProj + j]
+    const R e = (j < gp(a.pj.nproj)[at]) ? (R)gp(a.pj.EjN2)[at * kMaxProj + j]
                                      : (R)0;
-    reinterpret_cast<V *>(a.D)[i] = cmk<V>(e * re, e * im);
+    gst(reinterpret_cast<V *>(a.D) + i, cmk<V>(e * re, e * im));
 }
 
 // V_NL in on the hull: W[s][h] = sum over atoms a whose sphere holds hull
@@ -846,7 +896,7 @@ __device__ __forceinline__ void kbapply_item(const GArgs &a, const int chunk,
     const int perx = a.geo.per[0], pery = a.geo.per[1], perz = a.geo.per[2];
     const double Lx = nx * a.geo.h[0], Ly = ny * a.geo.h[1],
                  Lz = nz * a.geo.h[2];
-    const int pk = valid ? a.pj.hxyz[h] : 0;
+    const int pk = valid ? gp(a.pj.hxyz)[h] : 0;
     const double xc = axis_coord(nx, a.geo.h[0], perx, pk & 0x3ff);
     const double yc = axis_coord(ny, a.geo.h[1], pery, (pk >> 10) & 0x3ff);
     const double zc = axis_coord(nz, a.geo.h[2], perz, pk >> 20);
@@ -854,26 +904,27 @@ __device__ __forceinline__ void kbapply_item(const GArgs &a, const int chunk,
 #pragma unroll
     for (int q = 0; q < kApplySPW; ++q)
         acc[q] = czero<V>();
-    const int c0 = a.pj.hc_off[chunk], c1 = a.pj.hc_off[chunk + 1];
+    const int c0 = gp(a.pj.hc_off)[chunk], c1 = gp(a.pj.hc_off)[chunk + 1];
     for (int b0 = c0; b0 < c1; b0 += kApplyAtoms) {
         const int nb = min(kApplyAtoms, c1 - b0);
         __syncthreads();              // the previous batch has been read
         if (tid < nb) {
-            const int at = a.pj.hc_atoms[b0 + tid];
-            sh.apos[tid] = a.pj.apos[at];
-            sh.arad[tid] = a.pj.arad[at];
-            sh.np[tid] = a.pj.nproj[at];
+            const int at = gp(a.pj.hc_atoms)[b0 + tid];
+            sh.apos[tid] = gld(a.pj.apos + at);
+            sh.arad[tid] = gld(a.pj.arad + at);
+            sh.np[tid] = gp(a.pj.nproj)[at];
         }
         for (int t = tid; t < nb * kApplyStates * kMaxProj; t += blockDim.x) {
             const int i = t / (kApplyStates * kMaxProj);
             const int r = t - i * (kApplyStates * kMaxProj);
             const int q = r / kMaxProj, j = r - q * kMaxProj;
-            const int at = a.pj.hc_atoms[b0 + i];
+            const int at = gp(a.pj.hc_atoms)[b0 + i];
             const int sl = sb + q;
-            sh.D[i][q][j] = sl < a.ns ? reinterpret_cast<const V *>(a.D)[
-                                            ((size_t)sl * a.pj.natoms + at) *
-                                                kMaxProj + j]
-                                      : czero<V>();
+            V d = czero<V>();
+            if (sl < a.ns)
+                d = gld(reinterpret_cast<const V *>(a.D) +
+                        ((size_t)sl * a.pj.natoms + at) * kMaxProj + j);
+            sh.D[i][q][j] = d;
         }
         __syncthreads();
         for (int i = 0; i < nb; ++i) {
@@ -922,8 +973,8 @@ __device__ __forceinline__ void kbapply_item(const GArgs &a, const int chunk,
         for (int q = 0; q < kApplySPW; ++q) {
             const int sl = s0 + q;
             if (sl < a.ns)
-                reinterpret_cast<V *>(a.W)[(size_t)sl * a.pj.nhull + h] =
-                    acc[q];
+                gst(reinterpret_cast<V *>(a.W) + (size_t)sl * a.pj.nhull + h,
+                    acc[q]);
         }
 }
 

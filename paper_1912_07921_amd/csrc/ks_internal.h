@@ -194,7 +194,8 @@ struct BArgs {
 
 int batch_items(int kind, const JobDev &J);
 hipError_t launch_pass_batch(bool mixed, const BArgs &b, bool grad, int hm,
-                             int rpt, size_t lds, int grid, hipStream_t st);
+                             int rpt, int nthr, size_t lds, int grid,
+                             hipStream_t st);
 hipError_t launch_projectors_batch(bool mixed, const BArgs &bg,
                                    const BArgs &bf, const BArgs &ba,
                                    int grid, hipStream_t st);

@@ -92,7 +92,7 @@ EXPORTS = {
                             C.POINTER(C.c_double)]),
     "ks_set_launch": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
     "ks_get_launch": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
-    "ks_profile_begin": (C.c_int, [C.c_void_p, C.c_int]),
+    "ks_profile_begin": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "ks_profile_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
                                  C.POINTER(C.c_long)]),
     "ks_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int,
@@ -270,8 +270,14 @@ def ks_get_launch(h):
                 threads=out[3], rows_per_thread=out[4])
 
 
-def ks_profile_begin(h, capacity):
-    return _check(lib().ks_profile_begin(h, int(capacity)))
+PROFILE_CLASSES = ("hpsi", "gather", "reduce", "kbapply")
+
+
+def ks_profile_begin(h, capacity, classes=PROFILE_CLASSES):
+    mask = 0
+    for c in classes:
+        mask |= 1 << PROFILE_CLASSES.index(c)
+    return _check(lib().ks_profile_begin(h, int(capacity), mask))
 
 
 def ks_profile_end(h):
@@ -471,8 +477,8 @@ class Grid:
         self._psi(psi)
         return ks_autotune(self.h, psi, reps)
 
-    def profile_begin(self, capacity=100000):
-        ks_profile_begin(self.h, capacity)
+    def profile_begin(self, capacity=100000, classes=PROFILE_CLASSES):
+        ks_profile_begin(self.h, capacity, classes)
 
     def profile_end(self):
         return ks_profile_end(self.h)

@@ -95,6 +95,37 @@ def test_apply_h_degenerate_grids(torch_cuda, oracle_mod, n, periodic):
     apply_parity(torch_cuda, oracle_mod, spec, v, psi)
 
 
+@pytest.mark.parametrize("periodic", [(0, 0, 0), (1, 1, 0)])
+def test_apply_h_widest_rows(torch_cuda, oracle_mod, periodic):
+    """The widest x-row the kernel takes (nx = 192, so one row fills three
+    wavefronts and a tile is two rows), with projectors and Bloch wraps."""
+    spec, v, psi = W.tiny(n=(192, 7, 9), h=(0.15, 0.4, 0.4),
+                          periodic=periodic, nk=1, nstates=2, natoms=2,
+                          lmax=2, rc=1.1, sigma=0.35,
+                          laser=(0.3, 0.8, 4.0, 0.6, 0.0, 0.8))
+    apply_parity(torch_cuda, oracle_mod, spec, v, psi, A_t=1.1)
+
+
+def test_apply_h_no_states_and_sub_ranges(torch_cuda, oracle_mod):
+    """ns = 0 is a no-op; a state sub-range [s0, s0+ns) of a k-point gives
+    the rows of the full application."""
+    torch = torch_cuda
+    from paper_1912_07921_amd import ks
+    spec, v, psi = W.tiny(n=(12, 11, 10), nk=2, nstates=4, natoms=2,
+                          periodic=(1, 1, 1))
+    g = grid(spec)
+    g.update_vlocal(dev(torch, v))
+    full = g.apply_h(dev(torch, psi[1]), k=1).cpu().numpy().reshape(4, -1)
+    a = torch.zeros(1, dtype=torch.complex128, device="cuda")
+    b = torch.zeros(1, dtype=torch.complex128, device="cuda")
+    ks.ks_apply_h(g.h, a, b, 1, 2, 0, 0.0)            # nothing to do
+    assert float(b.abs().sum()) == 0.0
+    sub = dev(torch, psi[1][1:3])
+    got = torch.empty_like(sub)
+    ks.ks_apply_h(g.h, sub, got, 1, 1, 2, 0.0)
+    assert np.array_equal(got.cpu().numpy().reshape(2, -1), full[1:3])
+
+
 def test_apply_h_c1(torch_cuda, oracle_mod):
     w = W.c1()
     apply_parity(torch_cuda, oracle_mod, w.spec, w.vion, w.psi0)
