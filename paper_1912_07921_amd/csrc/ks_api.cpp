@@ -1407,6 +1407,7 @@ struct ks_batch {
     int grid_hpsi = 0, grid_proj = 0;
     std::vector<void *> owned;
     JobDev *d_jobs = nullptr;
+    HArgs *d_hargs = nullptr;
     int *d_off[4] = {nullptr, nullptr, nullptr, nullptr};
     int off_total[4] = {0, 0, 0, 0};
     int **d_steps = nullptr;
@@ -1437,6 +1438,7 @@ BArgs batch_args(const ks_batch *b, int kind, int pass)
     a.off = b->d_off[kind];
     a.off_total = b->off_total[kind];
     a.pass = pass;
+    a.hargs = b->d_hargs;
     return a;
 }
 
@@ -1637,7 +1639,46 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
             return fail(KS_E_HIP, "upload of item offsets failed");
         }
     }
-    if (hipMemcpy(b->d_jobs, b->hjobs.data(), njobs * sizeof(JobDev),
+    // the H.psi arguments of every job's eight Taylor passes: exponential
+    // e = (p-1)/4 starts from psi (e = 0) or psi_half (e = 1); term j writes
+    // t_j, the fourth pass the sum (psi_half, then psi); the potential is
+    // v(t) in the first exponential and v(t+dt) (predicted when exchange is
+    // on) in the second
+    std::vector<HArgs> hargs(8 * (size_t)njobs);
+    for (int i = 0; i < njobs; ++i) {
+        const JobDev &J = b->hjobs[i];
+        for (int p = 1; p <= 8; ++p) {
+            const int e = (p - 1) / 4, j = (p - 1) % 4 + 1;
+            HArgs a = J.h;
+            a.A[0] = a.A[1] = a.A[2] = 0.0;
+            a.a2half = 0.0;
+            a.in = j == 1 ? (e == 0 ? (const void *)J.psi
+                                    : (const void *)J.half)
+                          : J.t[j - 2];
+            a.v = e == 0 ? J.vcur : (J.xc ? J.vpred : J.vion);
+            a.cre = 0.0;
+            a.cim = -0.5 * J.dt / j;
+            if (j < 4) {
+                a.out = J.t[j - 1];
+            } else {
+                a.out = e == 0 ? (void *)J.half : (void *)J.psi;
+                a.base = e == 0 ? J.psi : J.half;
+                a.t1 = J.t[0];
+                a.t2 = J.t[1];
+                a.npart = e == 0 ? (J.xc ? J.npart : nullptr)
+                                 : (J.npart_end ? J.npart : nullptr);
+                a.normpart = e == 1 ? J.normpart_end : nullptr;
+            }
+            hargs[8 * (size_t)i + p - 1] = a;
+        }
+    }
+    if ((rc = batch_alloc(b, &b->d_hargs, hargs.size()))) {
+        ks_batch_destroy(b);
+        return rc;
+    }
+    if (hipMemcpy(b->d_hargs, hargs.data(), hargs.size() * sizeof(HArgs),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_jobs, b->hjobs.data(), njobs * sizeof(JobDev),
                   hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->d_steps, steps.data(), njobs * sizeof(int *),
                   hipMemcpyHostToDevice) != hipSuccess) {

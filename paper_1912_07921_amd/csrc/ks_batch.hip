@@ -54,34 +54,6 @@ __device__ __forceinline__ const void *pass_input(cptr_t<JobDev> J, int p)
     return J->t[j - 2];
 }
 
-__device__ __forceinline__ HArgs pass_hargs(cptr_t<JobDev> J, int p)
-{
-    HArgs a = cload<HArgs>(&J->h);
-    const int e = (p - 1) / 4, j = (p - 1) % 4 + 1;
-    // A(t0 + (step + e) dt)
-    const double4 Av = cload<double4>(cp(J->Atab) + 2 * *cp(J->step) + e);
-    a.A[0] = Av.x;
-    a.A[1] = Av.y;
-    a.A[2] = Av.z;
-    a.a2half = Av.w;
-    a.in = pass_input(J, p);
-    a.v = e == 0 ? J->vcur : (J->xc ? J->vpred : J->vion);
-    a.cre = 0.0;
-    a.cim = -0.5 * J->dt / j;
-    if (j < 4) {
-        a.out = J->t[j - 1];
-    } else {
-        a.out = e == 0 ? (void *)J->half : (void *)J->psi;
-        a.base = e == 0 ? J->psi : J->half;
-        a.t1 = J->t[0];
-        a.t2 = J->t[1];
-        a.npart = e == 0 ? (J->xc ? J->npart : nullptr)
-                         : (J->npart_end ? J->npart : nullptr);
-        a.normpart = e == 1 ? J->normpart_end : nullptr;
-    }
-    return a;
-}
-
 template <class R, class InT, class TT, int MODE, bool GRAD, int HM, int RPT>
 __global__ __launch_bounds__(512) void k_hpsi_batch(BArgs b)
 {
@@ -89,8 +61,15 @@ __global__ __launch_bounds__(512) void k_hpsi_batch(BArgs b)
     for (int L = blockIdx.x; L < total; L += gridDim.x) {
         const int item = xcd_remap(L, total);
         const int jb = find_job(b.off, b.njobs, item);
-        const HArgs a = pass_hargs(cp(b.jobs) + jb, b.pass);
-        hpsi_item<R, InT, TT, MODE, GRAD, HM, RPT>(a, item - cp(b.off)[jb]);
+        const cptr_t<JobDev> J = cp(b.jobs) + jb;
+        const int e = (b.pass - 1) / 4;
+        // A(t0 + (step + e) dt)
+        const double4 Av = cload<double4>(cp(J->Atab) + 2 * *cp(J->step) + e);
+        // the pass's arguments stay in the constant address space (read by
+        // scalar loads where used, like kernel arguments)
+        const HArgs &a = *(const HArgs *)(cp(b.hargs) + 8 * jb + b.pass - 1);
+        hpsi_item<R, InT, TT, MODE, GRAD, HM, RPT>(a, item - cp(b.off)[jb],
+                                                   Av);
         __syncthreads();   // LDS is reused by the next item
     }
 }

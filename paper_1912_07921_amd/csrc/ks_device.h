@@ -322,13 +322,15 @@ __device__ __forceinline__ int xcd_remap(int L, int nblk)
 extern __shared__ double2 smem_d2[];
 
 // One work item of the H.psi pass described by `a`: work item w is
-// (launch state, z-chunk, y-tile).  The whole workgroup takes part.  Thread
+// (launch state, z-chunk, y-tile).  The whole workgroup takes part.  Avec
+// holds the vector potential (x, y, z) and |A|^2 / 2 of the pass.  Thread
 // t owns column x = t % nx of rows yl + r * TYh (r < RPT, yl = t / nx,
 // TYh = ceil(TY / RPT)): every row set is a contiguous run of the plane, so
 // loads stay coalesced while a tile of TY rows needs only TY / RPT thread
 // rows.
 template <class R, class InT, class TT, int MODE, bool GRAD, int HM, int RPT>
-__device__ __forceinline__ void hpsi_item(const HArgs &a, const int w)
+__device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
+                                          const double4 Avec)
 {
     using V = typename Cplx<R>::T;
     unsigned char *smem_raw = reinterpret_cast<unsigned char *>(smem_d2);
@@ -541,8 +543,8 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w)
     const R ih2y = (R)(1.0 / (a.geo.h[1] * a.geo.h[1]));
     const R ih2z = (R)(1.0 / (a.geo.h[2] * a.geo.h[2]));
     const R c0sum = LC[0] * (ih2x + ih2y + ih2z);
-    const R Ax = (R)(a.A[0] / a.geo.h[0]), Ay = (R)(a.A[1] / a.geo.h[1]),
-            Az = (R)(a.A[2] / a.geo.h[2]);
+    const R Ax = (R)(Avec.x / a.geo.h[0]), Ay = (R)(Avec.y / a.geo.h[1]),
+            Az = (R)(Avec.z / a.geo.h[2]);
     const V cs = cmk<V>(a.cre, a.cim);
     const double w_occ = (MODE == kFinal || MODE == kFinalPred)
                              ? gp(a.wocc)[sg] : 0.0;
@@ -592,7 +594,7 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w)
             V lap = cadd(cadd(cscale(sx, ih2x), cscale(sy, ih2y)),
                          cscale(sz, ih2z));
             lap = cadd(lap, cscale(c, c0sum));
-            const R vv = (R)(vc[r] + a.a2half);
+            const R vv = (R)(vc[r] + Avec.w);
             V hp = cadd(cscale(lap, (R)-0.5), cscale(c, vv));
             if constexpr (GRAD) {
                 // -i A.grad

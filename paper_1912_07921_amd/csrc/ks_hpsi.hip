@@ -23,9 +23,9 @@ namespace ks {
 template <class R, class InT, class TT, int MODE, bool GRAD, int HM, int RPT>
 __global__ __launch_bounds__(512) KS_HPSI_ATTR void k_hpsi(HArgs a)
 {
-    hpsi_item<R, InT, TT, MODE, GRAD, HM, RPT>(a,
-                                               xcd_remap(blockIdx.x,
-                                                         gridDim.x));
+    hpsi_item<R, InT, TT, MODE, GRAD, HM, RPT>(
+        a, xcd_remap(blockIdx.x, gridDim.x),
+        make_double4(a.A[0], a.A[1], a.A[2], a.a2half));
 }
 
 // ---------------------------------------------------------------------------

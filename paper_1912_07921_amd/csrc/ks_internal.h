@@ -186,6 +186,9 @@ enum ItemKind : int { kItemHpsi = 0, kItemGather = 1, kItemGatherFin = 2,
 
 struct BArgs {
     const JobDev *jobs = nullptr;
+    // [njobs][8] H.psi arguments of each job's Taylor passes (vector
+    // potential left to the kernel, from the job's A(t) table)
+    const HArgs *hargs = nullptr;
     int njobs = 0;
     const int *off = nullptr;      // [njobs+1] item offsets (device)
     int off_total = 0;             // items over all jobs (host copy)
