@@ -350,6 +350,12 @@ def main():
         },
         "roofline": roofline,
         "kernels": kernel_times,
+        # the paper reports no H.psi rate or bandwidth, only relative
+        # whole-run GPU speed-ups on other hardware (context, not a target)
+        "paper_context": ("Octopus GPU port on NVIDIA V100: a full GPU node "
+                          "(2x V100 PCIe) 4.8x faster per TD step than a "
+                          "full CPU node (2x Xeon 6148); 1.95/3.70/5.97x on "
+                          "2/4/8 NVLink V100s with states distributed"),
     }
 
     if not args.no_mixed:
