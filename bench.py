@@ -8,9 +8,11 @@ HBM.  Throughput is H.psi grid-point-states per second:
 8 * N * (nk * nstates) * steps / time.
 
 Prints one JSON line with the FP64 rate, the roofline of the dominant kernel
-(the H.psi stencil, timed live with HIP events on its stream), the CPU
-oracle timed on the host on a bounded sample, and the FP32-mixed form on the
-same workload.
+(the H.psi stencil, timed live with HIP events on its stream, beside a plain
+device copy timed in the same run), the CPU oracle timed on the host on a
+bounded sample, the FP32-mixed form and the CFM4 propagator on the same
+workload, and the serving mix (continuous batching of propagation requests)
+in both precisions.
 """
 from __future__ import annotations
 

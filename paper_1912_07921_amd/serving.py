@@ -87,7 +87,6 @@ class Server:
                 8 * (req.nsteps + 1) * (3 + S) + 4096)
 
     def _admit(self, req, grid, now):
-        torch = self.torch
         grid.ensure_workspace()
         psi = req.psi.to(self.device, non_blocking=True).contiguous()
         vion = req.vion.to(self.device, non_blocking=True).contiguous()
@@ -100,7 +99,6 @@ class Server:
         req.t_admit = now
         a = _Active(req, grid, job)
         a.fp = self._footprint(req, grid)
-        del torch
         return a
 
     def _retire(self, a, now):
