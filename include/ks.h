@@ -195,6 +195,15 @@ int ks_energy(ks_grid *g, const void *d_psi, const double *d_vion, double t,
  * do. */
 int ks_set_launch(ks_grid *g, int tile_rows, int zchunk, int rows_per_thread);
 
+/* Propagation overlap: with halves = 2 and projectors present, each Taylor
+ * exponential runs the first half of the states on the grid's stream and
+ * the second half on a second stream of the grid, forked from and joined
+ * back into it, so that one half's small projector kernels can run beside
+ * the other half's stencil.  1 (the default) runs all states in one chain.
+ * Results are the same either way; kernel profiling always runs one chain.
+ * KS_E_ARG for other values. */
+int ks_set_overlap(ks_grid *g, int halves);
+
 /* out[0] = tile_rows, out[1] = zchunk, out[2] = workgroups per H.psi launch
  * over all states, out[3] = threads per workgroup, out[4] = rows per
  * thread. */

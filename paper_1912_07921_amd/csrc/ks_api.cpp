@@ -89,6 +89,12 @@ struct ks_grid {
     int ev_used = 0;
     bool profiling = false;
     int prof_mask = 0xf;
+    // second stream: the states are propagated in two halves whose pass
+    // chains overlap (one half's projector kernels beside the other half's
+    // stencil)
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    int halves = 1;
 };
 
 namespace {
@@ -529,23 +535,44 @@ double half_a2(const double A[3])
     return 0.5 * (A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
 }
 
-int taylor_exponential(ks_grid *g, const double2 *in, double2 *out,
-                       const double *v, const double A[3], double a2half,
-                       double tau, int final_mode, double *npart,
-                       double *normpart)
+// The four passes of one Taylor exponential for states [s0, s0 + ns) on
+// stream st: every buffer is offset to the first of those states.
+int exp_chain(ks_grid *g, hipStream_t st, int s0, int ns, const double2 *in,
+              double2 *out, const double *v, const double A[3],
+              double a2half, double tau, int final_mode, double *npart,
+              double *normpart)
 {
-    const int S = g->stot;
     const bool mx = g->mixed;
-    void *tb[3] = {g->ws + g->lay.t1, g->ws + g->lay.t2, g->ws + g->lay.t3};
-    void *D = g->ws + g->lay.D;
+    const size_t N = g->geo.N;
+    const size_t tsz = mx ? 8 : 16;     // Taylor terms and projector data
+    const size_t na = std::max(1, g->natoms);
+    auto off = [](void *p, size_t bytes) {
+        return static_cast<void *>(static_cast<char *>(p) + bytes);
+    };
+    void *tb[3];
+    for (int k = 0; k < 3; ++k)
+        tb[k] = off(g->ws + (k == 0 ? g->lay.t1 : k == 1 ? g->lay.t2
+                                                        : g->lay.t3),
+                    (size_t)s0 * N * tsz);
+    in += (size_t)s0 * N;
+    out += (size_t)s0 * N;
     HArgs a = base_hargs(g);
+    a.sg0 = s0;
     a.v = v;
     a.A[0] = A[0];
     a.A[1] = A[1];
     a.A[2] = A[2];
     a.a2half = a2half;
+    if (a.W)
+        a.W = off(const_cast<void *>(a.W), (size_t)s0 * g->nhull * tsz);
     GArgs ga = base_gargs(g);
-    ga.D = D;
+    ga.sg0 = s0;
+    ga.D = off(g->ws + g->lay.D, (size_t)s0 * na * kMaxProj * tsz);
+    if (ga.W)
+        ga.W = off(ga.W, (size_t)s0 * g->nhull * tsz);
+    if (ga.Dpart)
+        ga.Dpart = off(ga.Dpart,
+                       (size_t)s0 * na * g->nchunk * kMaxProj * tsz);
     const void *cur = in;
     for (int j = 1; j <= 4; ++j) {
         const bool f64 = (j == 1) || !mx;
@@ -553,10 +580,10 @@ int taylor_exponential(ks_grid *g, const double2 *in, double2 *out,
         if (g->natoms > 0) {
             {
                 Timed tm(g, 1);
-                KS_HIP(launch_gather(mx, f64, ga, S, g->stream));
+                KS_HIP(launch_gather(mx, f64, ga, ns, st));
             }
             Timed tm(g, 3);
-            KS_HIP(launch_kbapply(mx, ga, S, g->stream));
+            KS_HIP(launch_kbapply(mx, ga, ns, st));
         }
         a.in = cur;
         a.cre = 0.0;
@@ -565,7 +592,7 @@ int taylor_exponential(ks_grid *g, const double2 *in, double2 *out,
             a.out = tb[j - 1];
             {
                 Timed tm(g, 0);
-                KS_HIP(launch_hpsi(kTerm, mx, f64, a, S, g->stream));
+                KS_HIP(launch_hpsi(kTerm, mx, f64, a, ns, st));
             }
             cur = tb[j - 1];
         } else {
@@ -573,12 +600,43 @@ int taylor_exponential(ks_grid *g, const double2 *in, double2 *out,
             a.base = in;
             a.t1 = tb[0];
             a.t2 = tb[1];
-            a.npart = npart;
-            a.normpart = normpart;
+            a.npart = npart ? npart + (size_t)s0 * N : nullptr;
+            a.normpart = normpart
+                             ? normpart + (size_t)s0 * g->ntile_y * g->nzc
+                             : nullptr;
             Timed tm(g, 0);
-            KS_HIP(launch_hpsi(final_mode, mx, false, a, S, g->stream));
+            KS_HIP(launch_hpsi(final_mode, mx, false, a, ns, st));
         }
     }
+    return KS_OK;
+}
+
+// One Taylor-4 exponential of H (potential v, vector potential A) for all
+// states.  With two halves (and projectors, whose small kernels are what
+// the overlap hides) the second half runs on the side stream, forked from
+// and joined back into the grid's stream; kernel profiling runs whole.
+int taylor_exponential(ks_grid *g, const double2 *in, double2 *out,
+                       const double *v, const double A[3], double a2half,
+                       double tau, int final_mode, double *npart,
+                       double *normpart)
+{
+    const int S = g->stot;
+    if (g->halves < 2 || S < 2 || g->natoms == 0 || g->profiling)
+        return exp_chain(g, g->stream, 0, S, in, out, v, A, a2half, tau,
+                         final_mode, npart, normpart);
+    const int sa = S / 2;
+    KS_HIP(hipEventRecord(g->fork_ev, g->stream));
+    KS_HIP(hipStreamWaitEvent(g->side, g->fork_ev, 0));
+    int rc = exp_chain(g, g->stream, 0, sa, in, out, v, A, a2half, tau,
+                       final_mode, npart, normpart);
+    if (rc)
+        return rc;
+    rc = exp_chain(g, g->side, sa, S - sa, in, out, v, A, a2half, tau,
+                   final_mode, npart, normpart);
+    if (rc)
+        return rc;
+    KS_HIP(hipEventRecord(g->join_ev, g->side));
+    KS_HIP(hipStreamWaitEvent(g->stream, g->join_ev, 0));
     return KS_OK;
 }
 
@@ -641,6 +699,15 @@ int ks_grid_create(const ks_grid_desc *d, ks_grid **out)
     std::memcpy(g->laser, d->laser, sizeof g->laser);
     g->mixed = d->precision == KS_MIXED;
     g->stream = static_cast<hipStream_t>(d->stream);
+    if (hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking) !=
+            hipSuccess ||
+        hipEventCreateWithFlags(&g->fork_ev, hipEventDisableTiming) !=
+            hipSuccess ||
+        hipEventCreateWithFlags(&g->join_ev, hipEventDisableTiming) !=
+            hipSuccess) {
+        ks_grid_destroy(g);
+        return fail(KS_E_HIP, "stream or event creation failed");
+    }
     g->kpts.assign(3 * d->nk, 0.0);
     if (d->kpts)
         g->kpts.assign(d->kpts, d->kpts + 3 * d->nk);
@@ -683,11 +750,27 @@ int ks_grid_destroy(ks_grid *g)
     if (!g)
         return KS_OK;
     (void)hipStreamSynchronize(g->stream);
+    if (g->side) {
+        (void)hipStreamSynchronize(g->side);
+        (void)hipStreamDestroy(g->side);
+    }
+    if (g->fork_ev)
+        (void)hipEventDestroy(g->fork_ev);
+    if (g->join_ev)
+        (void)hipEventDestroy(g->join_ev);
     for (hipEvent_t e : g->ev)
         (void)hipEventDestroy(e);
     for (void *p : g->owned)
         (void)hipFree(p);
     delete g;
+    return KS_OK;
+}
+
+int ks_set_overlap(ks_grid *g, int halves)
+{
+    if (!g || halves < 1 || halves > 2)
+        return fail(KS_E_ARG, "grid is NULL or halves not 1 or 2");
+    g->halves = halves;
     return KS_OK;
 }
 

@@ -92,6 +92,7 @@ EXPORTS = {
                             C.POINTER(C.c_double)]),
     "ks_set_launch": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
     "ks_get_launch": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
+    "ks_set_overlap": (C.c_int, [C.c_void_p, C.c_int]),
     "ks_profile_begin": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "ks_profile_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
                                  C.POINTER(C.c_long)]),
@@ -261,6 +262,10 @@ def ks_energy(h, psi, vion, t):
 def ks_set_launch(h, tile_rows, zchunk, rows_per_thread=0):
     return _check(lib().ks_set_launch(h, int(tile_rows), int(zchunk),
                                       int(rows_per_thread)))
+
+
+def ks_set_overlap(h, halves):
+    return _check(lib().ks_set_overlap(h, int(halves)))
 
 
 def ks_get_launch(h):
@@ -470,6 +475,11 @@ class Grid:
 
     def get_launch(self):
         return ks_get_launch(self.h)
+
+    def set_overlap(self, halves=2):
+        """Propagate the states in two overlapped halves (2) or one chain
+        (1)."""
+        ks_set_overlap(self.h, halves)
 
     def autotune(self, psi, reps=3):
         """Pick the fastest launch shape on these states; returns

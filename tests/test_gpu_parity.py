@@ -385,3 +385,21 @@ def test_cfm4_mixed_c2_dipole(torch_cuda, oracle_mod):
                            w.nsteps, w.dt, kick=w.kick, prec=1,
                            dip_tol=1e-6, method="cfm4")
     assert res["psi"] < 1e-4, res
+
+
+def test_overlapped_halves_give_the_same_propagation(torch_cuda):
+    """States propagated in two halves on two streams (projector kernels of
+    one half beside the stencil of the other) end bitwise where one chain
+    ends, dipole and norms included."""
+    torch = torch_cuda
+    w = W.c2(nsteps=3)
+    outs = []
+    for halves in (1, 2):
+        g = grid(w.spec)
+        g.set_overlap(halves)
+        p = dev(torch, w.psi0)
+        d, n = g.propagate_etrs(p, dev(torch, w.vion), 3, w.dt)
+        d4, n4 = g.propagate_cfm4(p, dev(torch, w.vion), 2, w.dt)
+        outs.append([x.cpu().numpy() for x in (p, d, n, d4, n4)])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
