@@ -54,12 +54,12 @@
  *   R6  ETRS step: with u_k = H_t^k psi(t),
  *         psi_half = sum (-i dt/2)^k u_k / k!,
  *         psi_pred = sum (-i dt  )^k u_k / k!   (same powers),
- *         v(t+dt)  = v_ion + v_x[n(psi_pred)],
+ *         v(t+dt)  = v_ion + v_x[n(psi_pred)] (+ v_H, R11),
  *         psi(t+dt) = T4(dt/2, H_{t+dt}) psi_half;
  *       then v is rebuilt from n(psi(t+dt)) for the next step.
  *   R7  LDA exchange only (Dirac/Slater): v_x = -(3 n / pi)^(1/3),
- *       E_x = -(3/4)(3/pi)^(1/3) h^3 sum n^(4/3).  No Hartree, no
- *       correlation.
+ *       E_x = -(3/4)(3/pi)^(1/3) h^3 sum n^(4/3).  No correlation; no
+ *       Hartree unless R11 is switched on.
  *   R8  Density n = sum_k w_k sum_s f_s |psi_ks|^2; dipole d = h^3 sum r n.
  *   R9  Kick: psi <- exp(i kappa z) psi.
  *   R10 CFM4 (the order-four commutator-free Magnus propagator): H(t1),
@@ -68,6 +68,16 @@
  *       through four points; through the points available in the first
  *       three steps of a run, so the run starts at lower order).  Each
  *       exponential is Taylor-4 of a H(t1) + b H(t2) with step dt.
+ *   R11 Hartree potential (optional; the paper names it as part of the
+ *       density-dependent potential but prescribes no solver): v_H solves
+ *       Lap v_H = -4 pi n.  Finite grid (no periodic axis): free space,
+ *       v_H(r_i) = h^3 sum_j n_j G(r_i - r_j), G(r) = 1/|r| for r != 0 and
+ *       G(0) = the mean of 1/|r| over the grid cell centred at the origin.
+ *       Periodic grid (all axes periodic): v_H(G) = 4 pi n(G) / |G|^2 over
+ *       the grid's discrete Fourier frequencies G_a = 2 pi m_a / L_a,
+ *       m_a in (-n_a/2, n_a/2], with v_H(G = 0) = 0 (a compensating uniform
+ *       background).  Mixed periodicity is not defined.  With R11 on,
+ *       v = v_ion + v_H[n] (+ v_x[n]) and E gains E_H = 1/2 h^3 sum n v_H.
  *
  * Layout: psi is complex double, [nk][nstates][nz][ny][nx], x fastest.
  */
@@ -101,6 +111,7 @@ typedef struct {
     const double *E;     /* natoms*3, E[a*3 + l] in Hartree */
     int xc;              /* 0: none, 1: LDA exchange */
     double laser[6];     /* A0, omega, T, pol_x, pol_y, pol_z */
+    int hartree;         /* 0: none, 1: + Hartree potential (R11) */
 } orc_desc;
 
 typedef struct {
@@ -249,6 +260,11 @@ orc_system *orc_create(const orc_desc *d)
     if (d->n[0] < 1 || d->n[1] < 1 || d->n[2] < 1 || d->nk < 1 ||
         d->nstates < 0 || d->natoms < 0)
         return NULL;
+    {
+        const int np = d->periodic[0] + d->periodic[1] + d->periodic[2];
+        if (d->hartree && np != 0 && np != 3)
+            return NULL;   /* R11 is defined for these two cases only */
+    }
     orc_system *S = calloc(1, sizeof(orc_system));
     S->d = *d;
     S->N = (long)d->n[0] * d->n[1] * d->n[2];
@@ -424,7 +440,141 @@ void orc_density(const orc_system *S, const cplx *psi, double *rho)
     }
 }
 
-/* v = v_ion + v_x[n] (R7); rho may be NULL (no exchange term). */
+/*
+ * Integral of 1/|r| over the box [0,a] x [0,b] x [0,c] (one corner at the
+ * origin), in closed form: with R = |(a, b, c)|,
+ *   bc ln((a+R)/|(b,c)|) + ca ln((b+R)/|(c,a)|) + ab ln((c+R)/|(a,b)|)
+ *   - a^2/2 atan(bc/(aR)) - b^2/2 atan(ca/(bR)) - c^2/2 atan(ab/(cR)).
+ */
+static double corner_integral(double a, double b, double c)
+{
+    double R = sqrt(a * a + b * b + c * c);
+    return b * c * log((a + R) / sqrt(b * b + c * c)) +
+           c * a * log((b + R) / sqrt(c * c + a * a)) +
+           a * b * log((c + R) / sqrt(a * a + b * b)) -
+           0.5 * a * a * atan(b * c / (a * R)) -
+           0.5 * b * b * atan(c * a / (b * R)) -
+           0.5 * c * c * atan(a * b / (c * R));
+}
+
+/* G(0) of R11: the mean of 1/|r| over the cell of sides h centred at 0. */
+double orc_coulomb_cell_mean(const double h[3])
+{
+    return 8.0 * corner_integral(0.5 * h[0], 0.5 * h[1], 0.5 * h[2]) /
+           (h[0] * h[1] * h[2]);
+}
+
+/*
+ * One-dimensional discrete Fourier transform along `axis` of the complex
+ * array f (layout [nz][ny][nx]), in place: f(m) <- sum_j f(j) e^{sgn 2 pi i
+ * j m / n}.  Written out term by term (O(n) per output).
+ */
+static void dft_axis(const int n[3], cplx *f, int axis, int sgn)
+{
+    const int na = n[axis];
+    const long stride = axis == 0 ? 1 : axis == 1 ? n[0] : (long)n[0] * n[1];
+    const long nlines = (long)n[0] * n[1] * n[2] / na;
+#pragma omp parallel
+    {
+        cplx *in = malloc(sizeof(cplx) * na);
+        cplx *tw = malloc(sizeof(cplx) * na);
+        for (int j = 0; j < na; ++j)
+            tw[j] = cexp(sgn * 2.0 * M_PI * I * j / na);
+#pragma omp for
+        for (long line = 0; line < nlines; ++line) {
+            /* first element of the line: the index with coordinate 0 on
+             * `axis` and the other two taken from `line` */
+            long base;
+            if (axis == 0)
+                base = line * na;
+            else if (axis == 1)
+                base = (line / n[0]) * n[0] * n[1] + line % n[0];
+            else
+                base = line;
+            for (int j = 0; j < na; ++j)
+                in[j] = f[base + j * stride];
+            for (int m = 0; m < na; ++m) {
+                cplx acc = 0.0;
+                for (int j = 0; j < na; ++j)
+                    acc += in[j] * tw[(long)j * m % na];
+                f[base + m * stride] = acc;
+            }
+        }
+        free(in);
+        free(tw);
+    }
+}
+
+/*
+ * Hartree potential v_H[n] of R11 into vh.  Returns 0, or -1 when the grid
+ * has mixed periodicity.
+ */
+int orc_hartree(const orc_system *S, const double *rho, double *vh)
+{
+    const int *n = S->d.n;
+    const double *h = S->d.h;
+    const long N = S->N;
+    const int np = S->d.periodic[0] + S->d.periodic[1] + S->d.periodic[2];
+    if (np == 0) {
+        const double g0 = orc_coulomb_cell_mean(h);
+        const double h3 = dvol(S);
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < N; ++i) {
+            const int xi = (int)(i % n[0]), yi = (int)((i / n[0]) % n[1]);
+            const int zi = (int)(i / ((long)n[0] * n[1]));
+            double acc = 0.0;
+            for (long j = 0; j < N; ++j) {
+                const int xj = (int)(j % n[0]), yj = (int)((j / n[0]) % n[1]);
+                const int zj = (int)(j / ((long)n[0] * n[1]));
+                const double dx = (xi - xj) * h[0], dy = (yi - yj) * h[1];
+                const double dz = (zi - zj) * h[2];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                acc += rho[j] * (r2 > 0.0 ? 1.0 / sqrt(r2) : g0);
+            }
+            vh[i] = h3 * acc;
+        }
+        return 0;
+    }
+    if (np != 3)
+        return -1;
+    cplx *f = malloc(sizeof(cplx) * N);
+    for (long i = 0; i < N; ++i)
+        f[i] = rho[i];
+    for (int a = 0; a < 3; ++a)
+        dft_axis(n, f, a, -1);
+    for (long i = 0; i < N; ++i) {
+        const int m[3] = {(int)(i % n[0]), (int)((i / n[0]) % n[1]),
+                          (int)(i / ((long)n[0] * n[1]))};
+        double G2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const int ma = 2 * m[a] > n[a] ? m[a] - n[a] : m[a];
+            const double Ga = 2.0 * M_PI * ma / (n[a] * h[a]);
+            G2 += Ga * Ga;
+        }
+        f[i] = G2 > 0.0 ? f[i] * (4.0 * M_PI / G2) : 0.0;
+    }
+    for (int a = 0; a < 3; ++a)
+        dft_axis(n, f, a, +1);
+    for (long i = 0; i < N; ++i)
+        vh[i] = creal(f[i]) / N;
+    free(f);
+    return 0;
+}
+
+/* E_H = 1/2 h^3 sum n v_H (R11). */
+double orc_hartree_energy(const orc_system *S, const double *rho)
+{
+    double *vh = malloc(sizeof(double) * S->N);
+    orc_hartree(S, rho, vh);
+    double s = 0.0;
+    for (long g = 0; g < S->N; ++g)
+        s += rho[g] * vh[g];
+    free(vh);
+    return 0.5 * dvol(S) * s;
+}
+
+/* v = v_ion + v_x[n] (R7) + v_H[n] (R11); rho may be NULL (neither
+ * density term). */
 void orc_vlocal(const orc_system *S, const double *vion, const double *rho,
                 double *v)
 {
@@ -433,6 +583,13 @@ void orc_vlocal(const orc_system *S, const double *vion, const double *rho,
         if (S->d.xc == 1 && rho)
             vx = -cbrt(3.0 * rho[g] / M_PI);
         v[g] = vion[g] + vx;
+    }
+    if (S->d.hartree && rho) {
+        double *vh = malloc(sizeof(double) * S->N);
+        orc_hartree(S, rho, vh);
+        for (long g = 0; g < S->N; ++g)
+            v[g] += vh[g];
+        free(vh);
     }
 }
 
@@ -509,7 +666,7 @@ void orc_gram(const orc_system *S, const cplx *psi, cplx *G)
 
 /*
  * Total energy of R7: sum_k w_k sum_s f_s <psi|T + v_ion + V_NL + gauge|psi>
- * + E_x[n].  Work space: ns*N complex.
+ * + E_x[n] + E_H[n].  Work space: ns*N complex.
  */
 double orc_energy(const orc_system *S, const cplx *psi, const double *vion,
                   double t)
@@ -531,10 +688,13 @@ double orc_energy(const orc_system *S, const cplx *psi, const double *vion,
         }
     }
     free(hp);
-    if (S->d.xc == 1) {
+    if (S->d.xc == 1 || S->d.hartree) {
         double *rho = malloc(sizeof(double) * N);
         orc_density(S, psi, rho);
-        e += orc_exchange_energy(S, rho);
+        if (S->d.xc == 1)
+            e += orc_exchange_energy(S, rho);
+        if (S->d.hartree)
+            e += orc_hartree_energy(S, rho);
         free(rho);
     }
     return e;
@@ -587,7 +747,7 @@ int orc_propagate_etrs(const orc_system *S, cplx *psi, const double *vion,
     cplx *pred = malloc(sizeof(cplx) * M * nk);
 
     orc_density(S, psi, rho);
-    orc_vlocal(S, vion, S->d.xc ? rho : NULL, v);
+    orc_vlocal(S, vion, (S->d.xc || S->d.hartree) ? rho : NULL, v);
     if (dipole)
         orc_dipole(S, rho, dipole);
     if (norms)
@@ -627,13 +787,13 @@ int orc_propagate_etrs(const orc_system *S, cplx *psi, const double *vion,
         }
         /* Hamiltonian at t+dt from the predicted density */
         orc_density(S, pred, rho);
-        orc_vlocal(S, vion, S->d.xc ? rho : NULL, vnext);
+        orc_vlocal(S, vion, (S->d.xc || S->d.hartree) ? rho : NULL, vnext);
         for (int k = 0; k < nk; ++k)
             orc_taylor4(S, vnext, k, An, dt / 2, ns, half + (size_t)k * M,
                         psi + (size_t)k * M);
         /* potential for the next step from the new density */
         orc_density(S, psi, rho);
-        orc_vlocal(S, vion, S->d.xc ? rho : NULL, v);
+        orc_vlocal(S, vion, (S->d.xc || S->d.hartree) ? rho : NULL, v);
         if (dipole)
             orc_dipole(S, rho, dipole + 3 * (step + 1));
         if (norms)
@@ -699,7 +859,7 @@ int orc_propagate_cfm4(const orc_system *S, cplx *psi, const double *vion,
     int nhist = 0;
 
     orc_density(S, psi, rho);
-    orc_vlocal(S, vion, S->d.xc ? rho : NULL, hist);
+    orc_vlocal(S, vion, (S->d.xc || S->d.hartree) ? rho : NULL, hist);
     nhist = 1;
     if (dipole)
         orc_dipole(S, rho, dipole);
@@ -747,7 +907,7 @@ int orc_propagate_cfm4(const orc_system *S, cplx *psi, const double *vion,
         if (nhist < 4)
             ++nhist;
         orc_density(S, psi, rho);
-        orc_vlocal(S, vion, S->d.xc ? rho : NULL, hist);
+        orc_vlocal(S, vion, (S->d.xc || S->d.hartree) ? rho : NULL, hist);
         if (dipole)
             orc_dipole(S, rho, dipole + 3 * (step + 1));
         if (norms)

@@ -47,6 +47,7 @@ class _Desc(C.Structure):
         ("E", C.POINTER(C.c_double)),
         ("xc", C.c_int),
         ("laser", C.c_double * 6),
+        ("hartree", C.c_int),
     ]
 
 
@@ -88,6 +89,12 @@ def _load():
         lib.orc_propagate_cfm4.restype = C.c_int
         lib.orc_propagate_cfm4.argtypes = [vp, vp, vp, C.c_int, C.c_double,
                                            C.c_double, vp, vp]
+        lib.orc_hartree.restype = C.c_int
+        lib.orc_hartree.argtypes = [vp, vp, vp]
+        lib.orc_hartree_energy.restype = C.c_double
+        lib.orc_hartree_energy.argtypes = [vp, vp]
+        lib.orc_coulomb_cell_mean.restype = C.c_double
+        lib.orc_coulomb_cell_mean.argtypes = [vp]
         lib.orc_num_threads.restype = C.c_int
         _lib = lib
     return _lib
@@ -109,7 +116,7 @@ class Oracle:
 
     ``spec`` needs: n, h, periodic (3 each), kpts (nk x 3), kw (nk),
     nstates, occ (nstates), pos (natoms x 3), lmax, rc, sigma (natoms),
-    E (natoms x 3), xc (0/1), laser (6).
+    E (natoms x 3), xc (0/1), laser (6); optionally hartree (0/1).
     """
 
     def __init__(self, spec):
@@ -143,6 +150,7 @@ class Oracle:
         d.E = E.ctypes.data_as(C.POINTER(C.c_double))
         d.xc = int(spec.xc)
         d.laser[:] = [float(v) for v in spec.laser]
+        d.hartree = int(getattr(spec, "hartree", 0))
         self.natoms = d.natoms
         self._d = d
         h = lib.orc_create(C.byref(d))
@@ -225,6 +233,20 @@ class Oracle:
         rho = _f64(rho)
         return self._lib.orc_exchange_energy(self._h, _ptr(rho))
 
+    def hartree(self, rho):
+        """v_H[rho] (reading R11 of ks_oracle.c)."""
+        rho = _f64(rho)
+        if rho.size != self.N:
+            raise ValueError(f"expected {self.N} density values")
+        vh = np.empty(self.N)
+        if self._lib.orc_hartree(self._h, _ptr(rho), _ptr(vh)) != 0:
+            raise ValueError("Hartree potential of a mixed-periodicity grid")
+        return vh
+
+    def hartree_energy(self, rho):
+        rho = _f64(rho)
+        return self._lib.orc_hartree_energy(self._h, _ptr(rho))
+
     def dipole(self, rho):
         rho = _f64(rho)
         d = np.zeros(3)
@@ -283,6 +305,13 @@ class Oracle:
         if rc != 0:
             raise RuntimeError("oracle propagation failed")
         return psi, dip, nrm
+
+
+def coulomb_cell_mean(h) -> float:
+    """Mean of 1/|r| over the grid cell of sides h centred at the origin
+    (the G(0) of reading R11)."""
+    hh = _f64(h)
+    return float(_load().orc_coulomb_cell_mean(_ptr(hh)))
 
 
 def num_threads() -> int:

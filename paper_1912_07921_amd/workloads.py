@@ -56,6 +56,7 @@ class SystemSpec:
     E: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
     xc: int = 0
     laser: tuple = (0.0, 0.0, 0.0, 0.0, 0.0, 1.0)
+    hartree: int = 0
 
     def __post_init__(self):
         self.n = tuple(int(v) for v in self.n)
