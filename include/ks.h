@@ -34,8 +34,16 @@
  *    -1/280}; zero outside a non-periodic axis, Bloch phase
  *    psi(i + n) = exp(i k_a L_a) psi(i) along a periodic axis (k-points,
  *    section "Periodic systems").
- *  - v = v_ion + v_x[n]; v_x = -(3 n / pi)^(1/3) (LDA exchange, section
- *    "Local domains", E_xc^LDA; Dirac/Slater form).
+ *  - v = v_ion + v_x[n] (+ v_H[n]); v_x = -(3 n / pi)^(1/3) (LDA exchange,
+ *    section "Local domains", E_xc^LDA; Dirac/Slater form).  v_H, the
+ *    Hartree potential, is optional (desc.hartree): the paper counts it
+ *    among the density-dependent terms that the CFM4 propagator
+ *    extrapolates (section "New propagators") but fixes no solver.  Here
+ *    v_H solves Lap v_H = -4 pi n: on a finite grid (no periodic axis) as
+ *    v_H(r_i) = h^3 sum_j n_j G(r_i - r_j) with G = 1/|r| and G(0) the mean
+ *    of 1/|r| over one grid cell; on a periodic grid (all axes periodic) as
+ *    v_H(G) = 4 pi n(G) / |G|^2 over the grid's Fourier frequencies, with
+ *    v_H(G = 0) = 0.
  *  - V_NL: Kleinman-Bylander projectors on atom spheres |r - R_a| < rc_a
  *    (non-local pseudopotentials, section "Magneto-optics"):
  *    p_lm(r) = P_lm(r) exp(-r^2 / (2 sigma^2)) (1 - r^2/rc^2)^2 with real
@@ -95,6 +103,10 @@ typedef struct {
     int precision;       /* ks_precision */
     void *stream;        /* hipStream_t the calls are ordered on (NULL:
                             the default stream) */
+    int hartree;         /* 0: no Hartree term; 1: v += v_H[n]; needs all
+                            axes finite (n_a <= 256) or all periodic (each
+                            n_a a product of 2, 3 and 5, <= 512); else
+                            KS_E_UNSUPPORTED */
 } ks_grid_desc;
 
 /* Create a grid object: copies the description, builds the projector
@@ -116,10 +128,19 @@ size_t ks_workspace_bytes(const ks_grid *g);
  * ks_workspace_bytes() bytes, 256-byte aligned; KS_E_OOM if too small. */
 int ks_set_workspace(ks_grid *g, void *d_ws, size_t bytes);
 
-/* v = v_ion + v_x[rho] into the object's local potential (N doubles);
- * d_rho NULL (or xc == 0): v = v_ion.  (One-body potential of
- * eq. Hamiltonian_dipole; LDA of section "Local domains".) */
+/* v = v_ion + v_x[rho] + v_H[rho] into the object's local potential (N
+ * doubles), each density term only when the grid has it; d_rho NULL:
+ * v = v_ion.  (One-body potential of eq. Hamiltonian_dipole; LDA of
+ * section "Local domains".)  With the Hartree term and d_rho given, needs a
+ * workspace. */
 int ks_update_vlocal(ks_grid *g, const double *d_vion, const double *d_rho);
+
+/* d_vh = v_H[d_rho] (N doubles each, device, not overlapping): the Hartree
+ * potential of the density as defined above, by FFT convolution (zero
+ * padded to at least 2 n - 1 per axis on a finite grid).  KS_E_STATE if the
+ * grid was
+ * created without the Hartree term or has no workspace. */
+int ks_hartree(ks_grid *g, const double *d_rho, double *d_vh);
 
 /* d_hpsi = H(t) d_psi for ns states (each n points, complex128) of k-point
  * k, using the object's current local potential and A(t).  s0 is the index
@@ -133,7 +154,8 @@ int ks_apply_h(ks_grid *g, const void *d_psi, void *d_hpsi, int k, int s0,
  * of dt from t0.  Each step: H_t^j psi, j = 1..4 (Taylor-4, H frozen);
  * psi_half = sum (-i dt/2)^j H^j psi / j!; predictor
  * sum (-i dt)^j H^j psi / j! (same powers) gives n_pred and
- * v(t+dt) = v_ion + v_x[n_pred]; psi(t+dt) = T4(dt/2, H_{t+dt}) psi_half;
+ * v(t+dt) = v_ion + v_x[n_pred] (+ v_H[n_pred]);
+ * psi(t+dt) = T4(dt/2, H_{t+dt}) psi_half;
  * v is rebuilt from n(psi(t+dt)).  v(t0) is built from n(psi(t0)) first.
  * d_dipole: device (nsteps+1)*3 doubles, d(t_i) = h^3 sum r n (zero-boundary
  * grids only; NULL to skip).  d_norms: device (nsteps+1)*nk*nstates doubles,
@@ -178,7 +200,8 @@ int ks_norms(ks_grid *g, const void *d_psi, double *d_norms);
 int ks_gram(ks_grid *g, const void *d_psi, void *d_gram);
 
 /* Total energy sum_k w_k sum_s f_s <psi|T + v_ion + V_NL + gauge(t)|psi>
- * + E_x[n], E_x = -(3/4)(3/pi)^(1/3) h^3 sum n^(4/3) when xc == 1.
+ * + E_x[n], E_x = -(3/4)(3/pi)^(1/3) h^3 sum n^(4/3) when xc == 1,
+ * + E_H[n] = 1/2 h^3 sum n v_H[n] when hartree == 1.
  * Synchronises the stream.  Needs a workspace. */
 int ks_energy(ks_grid *g, const void *d_psi, const double *d_vion, double t,
               double *out_host);

@@ -505,6 +505,40 @@ static void dft_axis(const int n[3], cplx *f, int axis, int sgn)
     }
 }
 
+/* v_H at grid point i of a finite grid (R11): h^3 sum_j n_j G(r_i - r_j). */
+static double free_space_point(const orc_system *S, const double *rho,
+                               long i, double g0)
+{
+    const int *n = S->d.n;
+    const double *h = S->d.h;
+    const int xi = (int)(i % n[0]), yi = (int)((i / n[0]) % n[1]);
+    const int zi = (int)(i / ((long)n[0] * n[1]));
+    double acc = 0.0;
+    for (long j = 0; j < S->N; ++j) {
+        const int xj = (int)(j % n[0]), yj = (int)((j / n[0]) % n[1]);
+        const int zj = (int)(j / ((long)n[0] * n[1]));
+        const double dx = (xi - xj) * h[0], dy = (yi - yj) * h[1];
+        const double dz = (zi - zj) * h[2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        acc += rho[j] * (r2 > 0.0 ? 1.0 / sqrt(r2) : g0);
+    }
+    return dvol(S) * acc;
+}
+
+/* v_H of a finite grid at the listed grid points only (count of them);
+ * returns -1 on a grid with a periodic axis. */
+int orc_hartree_at(const orc_system *S, const double *rho, const long *idx,
+                   int count, double *out)
+{
+    if (S->d.periodic[0] || S->d.periodic[1] || S->d.periodic[2])
+        return -1;
+    const double g0 = orc_coulomb_cell_mean(S->d.h);
+#pragma omp parallel for schedule(dynamic)
+    for (int c = 0; c < count; ++c)
+        out[c] = free_space_point(S, rho, idx[c], g0);
+    return 0;
+}
+
 /*
  * Hartree potential v_H[n] of R11 into vh.  Returns 0, or -1 when the grid
  * has mixed periodicity.
@@ -517,22 +551,9 @@ int orc_hartree(const orc_system *S, const double *rho, double *vh)
     const int np = S->d.periodic[0] + S->d.periodic[1] + S->d.periodic[2];
     if (np == 0) {
         const double g0 = orc_coulomb_cell_mean(h);
-        const double h3 = dvol(S);
 #pragma omp parallel for schedule(static)
-        for (long i = 0; i < N; ++i) {
-            const int xi = (int)(i % n[0]), yi = (int)((i / n[0]) % n[1]);
-            const int zi = (int)(i / ((long)n[0] * n[1]));
-            double acc = 0.0;
-            for (long j = 0; j < N; ++j) {
-                const int xj = (int)(j % n[0]), yj = (int)((j / n[0]) % n[1]);
-                const int zj = (int)(j / ((long)n[0] * n[1]));
-                const double dx = (xi - xj) * h[0], dy = (yi - yj) * h[1];
-                const double dz = (zi - zj) * h[2];
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                acc += rho[j] * (r2 > 0.0 ? 1.0 / sqrt(r2) : g0);
-            }
-            vh[i] = h3 * acc;
-        }
+        for (long i = 0; i < N; ++i)
+            vh[i] = free_space_point(S, rho, i, g0);
         return 0;
     }
     if (np != 3)

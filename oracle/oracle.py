@@ -91,6 +91,8 @@ def _load():
                                            C.c_double, vp, vp]
         lib.orc_hartree.restype = C.c_int
         lib.orc_hartree.argtypes = [vp, vp, vp]
+        lib.orc_hartree_at.restype = C.c_int
+        lib.orc_hartree_at.argtypes = [vp, vp, vp, C.c_int, vp]
         lib.orc_hartree_energy.restype = C.c_double
         lib.orc_hartree_energy.argtypes = [vp, vp]
         lib.orc_coulomb_cell_mean.restype = C.c_double
@@ -242,6 +244,16 @@ class Oracle:
         if self._lib.orc_hartree(self._h, _ptr(rho), _ptr(vh)) != 0:
             raise ValueError("Hartree potential of a mixed-periodicity grid")
         return vh
+
+    def hartree_at(self, rho, idx):
+        """v_H[rho] at the listed grid points of a finite grid."""
+        rho = _f64(rho)
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        out = np.empty(len(idx))
+        if self._lib.orc_hartree_at(self._h, _ptr(rho), _ptr(idx), len(idx),
+                                    _ptr(out)) != 0:
+            raise ValueError("sampled Hartree potential of a periodic grid")
+        return out
 
     def hartree_energy(self, rho):
         rho = _f64(rho)

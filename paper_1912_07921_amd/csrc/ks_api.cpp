@@ -3,6 +3,7 @@
 // over the gfx950 kernels of ks_kernels.hip.
 #include "../../include/ks.h"
 #include "ks_internal.h"
+#include "ks_poisson.h"
 
 #include <hip/hip_runtime.h>
 
@@ -49,6 +50,9 @@ struct ks_grid {
     std::vector<double> kpts, kw, occ, wocc;
     std::vector<double2> kph;   // [nk][3] exp(i k_a L_a)
     int xc = 0;
+    int hartree = 0;
+    bool nonlin = false;        // the potential depends on the density
+    PoissonPlan pp;             // Hartree solver (hartree == 1)
     double laser[6] = {0, 0, 0, 0, 0, 0};
     bool mixed = false;
     hipStream_t stream = nullptr;
@@ -76,7 +80,8 @@ struct ks_grid {
     size_t ws_bytes = 0;
     struct {
         size_t t1, t2, t3, half, npart, normpart, D, W, Dpart, rho, vpred,
-            dpart, gpart, dotpart, xpart, step, vhist, veff, total;
+            dpart, gpart, dotpart, xpart, step, vhist, veff, pwork, vh,
+            total;
     } lay{};
     int ntiles_max = 64;
     int nchunk = 1;
@@ -428,6 +433,8 @@ void layout(ks_grid *g)
     g->lay.step = take(sizeof(int));
     g->lay.vhist = take(4 * N * 8);
     g->lay.veff = take(N * 8);
+    g->lay.pwork = take(g->hartree ? g->pp.work_elems * 16 : 0);
+    g->lay.vh = take(g->hartree ? N * 8 : 0);
     g->lay.total = off;
 }
 
@@ -435,6 +442,27 @@ template <class T> T *wsp(ks_grid *g, size_t off)
 {
     return reinterpret_cast<T *>(g->ws + off);
 }
+
+// The density kernel (with a.vout: v_out = v_ion + v_x[n]) followed, on a
+// grid with the Hartree term, by v_out += v_H[n].
+int density_potential(ks_grid *g, DArgs a, hipStream_t st)
+{
+    const bool hart = g->hartree && a.vout && a.nsrc > 0;
+    if (hart && !a.rho)
+        a.rho = wsp<double>(g, g->lay.rho);
+    KS_HIP(launch_density(a, st));
+    if (hart)
+        KS_HIP(launch_hartree(g->pp, g->geo, a.rho, a.vout, true,
+                              wsp<double2>(g, g->lay.pwork), st));
+    return KS_OK;
+}
+
+#define KS_TRY(call)                                                         \
+    do {                                                                     \
+        const int rc_ = (call);                                              \
+        if (rc_)                                                             \
+            return rc_;                                                      \
+    } while (0)
 
 // Event pair around one launch of class c (0 H.psi, 1 projector gather,
 // 2 reductions, 3 projector apply).
@@ -678,6 +706,13 @@ int ks_grid_create(const ks_grid_desc *d, ks_grid **out)
         return fail(KS_E_ARG, "atom arrays missing");
     if (d->xc != 0 && d->xc != 1)
         return fail(KS_E_ARG, "xc must be 0 or 1");
+    if (d->hartree != 0 && d->hartree != 1)
+        return fail(KS_E_ARG, "hartree must be 0 or 1");
+    const int nper = (d->periodic[0] ? 1 : 0) + (d->periodic[1] ? 1 : 0) +
+                     (d->periodic[2] ? 1 : 0);
+    if (d->hartree && nper != 0 && nper != 3)
+        return fail(KS_E_UNSUPPORTED,
+                    "Hartree term needs all axes finite or all periodic");
     if (d->precision != KS_FP64 && d->precision != KS_MIXED)
         return fail(KS_E_ARG, "precision must be KS_FP64 or KS_MIXED");
     if (d->laser[0] != 0.0 && !(d->laser[2] > 0.0))
@@ -696,6 +731,8 @@ int ks_grid_create(const ks_grid_desc *d, ks_grid **out)
     g->ns = d->nstates;
     g->stot = d->nk * d->nstates;
     g->xc = d->xc;
+    g->hartree = d->hartree;
+    g->nonlin = d->xc || d->hartree;
     std::memcpy(g->laser, d->laser, sizeof g->laser);
     g->mixed = d->precision == KS_MIXED;
     g->stream = static_cast<hipStream_t>(d->stream);
@@ -740,6 +777,23 @@ int ks_grid_create(const ks_grid_desc *d, ks_grid **out)
         ks_grid_destroy(g);
         return rc;
     }
+    if (g->hartree) {
+        int M[3];
+        if (!poisson_lengths(g->geo, nper == 3, M)) {
+            ks_grid_destroy(g);
+            return fail(KS_E_UNSUPPORTED,
+                        "Hartree transform lengths %d x %d x %d: each must "
+                        "be a product of 2, 3 and 5 up to %d", M[0], M[1],
+                        M[2], kFftMaxLen);
+        }
+        const hipError_t e =
+            poisson_plan_create(g->geo, nper == 3, &g->pp, g->stream);
+        if (e != hipSuccess) {
+            ks_grid_destroy(g);
+            return fail(e == hipErrorOutOfMemory ? KS_E_OOM : KS_E_HIP,
+                        "Hartree plan: %s", hipGetErrorString(e));
+        }
+    }
     layout(g);
     *out = g;
     return KS_OK;
@@ -762,6 +816,7 @@ int ks_grid_destroy(ks_grid *g)
         (void)hipEventDestroy(e);
     for (void *p : g->owned)
         (void)hipFree(p);
+    poisson_plan_destroy(&g->pp);
     delete g;
     return KS_OK;
 }
@@ -813,7 +868,15 @@ int ks_update_vlocal(ks_grid *g, const double *d_vion, const double *d_rho)
     a.xc = (d_rho && g->xc) ? 1 : 0;
     a.nsrc = d_rho ? 1 : 0;
     a.npart = d_rho ? d_rho : d_vion;  // not read when nsrc == 0
+    if (d_rho && g->hartree) {
+        const int rc = need_ws(g);
+        if (rc)
+            return rc;
+    }
     KS_HIP(launch_density(a, g->stream));
+    if (d_rho && g->hartree)
+        KS_HIP(launch_hartree(g->pp, g->geo, d_rho, g->d_v, true,
+                              wsp<double2>(g, g->lay.pwork), g->stream));
     g->vloc_set = true;
     return KS_OK;
 }
@@ -861,6 +924,23 @@ int ks_apply_h(ks_grid *g, const void *d_psi, void *d_hpsi, int k, int s0,
     return KS_OK;
 }
 
+int ks_hartree(ks_grid *g, const double *d_rho, double *d_vh)
+{
+    if (!g || !d_rho || !d_vh)
+        return fail(KS_E_ARG, "NULL argument");
+    if (!g->hartree)
+        return fail(KS_E_STATE, "grid created without the Hartree term");
+    if (d_rho == d_vh)
+        return fail(KS_E_ARG, "d_rho and d_vh must not overlap");
+    int rc = need_ws(g);
+    if (rc)
+        return rc;
+    Timed tm(g, 2);
+    KS_HIP(launch_hartree(g->pp, g->geo, d_rho, d_vh, false,
+                          wsp<double2>(g, g->lay.pwork), g->stream));
+    return KS_OK;
+}
+
 int ks_density(ks_grid *g, const void *d_psi, double *d_rho)
 {
     if (!g || !d_psi || !d_rho)
@@ -871,7 +951,7 @@ int ks_density(ks_grid *g, const void *d_psi, double *d_rho)
     a.psi = static_cast<const double2 *>(d_psi);
     a.wocc = g->d_wocc;
     a.rho = d_rho;
-    KS_HIP(launch_density(a, g->stream));
+    KS_TRY(density_potential(g, a, g->stream));
     return KS_OK;
 }
 
@@ -890,7 +970,7 @@ int ks_dipole(ks_grid *g, const double *d_rho, double out_host[3])
     a.nsrc = 1;
     a.npart = d_rho;
     a.dpart = wsp<double>(g, g->lay.dpart);
-    KS_HIP(launch_density(a, g->stream));
+    KS_TRY(density_potential(g, a, g->stream));
     double *dout = wsp<double>(g, g->lay.xpart);
     const double h3 = g->geo.h[0] * g->geo.h[1] * g->geo.h[2];
     KS_HIP(launch_dipole_finalize(a.dpart, density_blocks(g->geo.N), h3, dout,
@@ -984,10 +1064,10 @@ int ks_energy(ks_grid *g, const void *d_psi, const double *d_vion, double t,
     std::vector<double2> hdp((size_t)g->stot * g->norm_chunks);
     KS_HIP(hipMemcpyAsync(hdp.data(), dp, hdp.size() * sizeof(double2),
                           hipMemcpyDeviceToHost, g->stream));
-    double ex = 0.0;
+    double ex = 0.0, eh = 0.0;
     const int nb = density_blocks(N);
-    std::vector<double> hx;
-    if (g->xc) {
+    std::vector<double> hx, hh;
+    if (g->nonlin) {
         DArgs a;
         a.geo = g->geo;
         a.nsrc = g->stot;
@@ -995,13 +1075,24 @@ int ks_energy(ks_grid *g, const void *d_psi, const double *d_vion, double t,
         a.wocc = g->d_wocc;
         a.rho = wsp<double>(g, g->lay.rho);
         KS_HIP(launch_density(a, g->stream));
-        KS_HIP(launch_exchange_partial(g->geo, a.rho,
-                                       wsp<double>(g, g->lay.xpart),
-                                       g->stream));
-        hx.resize(nb);
-        KS_HIP(hipMemcpyAsync(hx.data(), wsp<double>(g, g->lay.xpart),
-                              nb * sizeof(double), hipMemcpyDeviceToHost,
-                              g->stream));
+        double *part = wsp<double>(g, g->lay.xpart);
+        if (g->xc) {
+            KS_HIP(launch_exchange_partial(g->geo, a.rho, part, g->stream));
+            hx.resize(nb);
+            KS_HIP(hipMemcpyAsync(hx.data(), part, nb * sizeof(double),
+                                  hipMemcpyDeviceToHost, g->stream));
+        }
+        if (g->hartree) {
+            // E_H = 1/2 h^3 sum n v_H; the partials buffer is reused after
+            // the (stream-ordered) copy of the exchange partials
+            double *vh = wsp<double>(g, g->lay.vh);
+            KS_HIP(launch_hartree(g->pp, g->geo, a.rho, vh, false,
+                                  wsp<double2>(g, g->lay.pwork), g->stream));
+            KS_HIP(launch_real_dot_partial(a.rho, vh, N, part, g->stream));
+            hh.resize(nb);
+            KS_HIP(hipMemcpyAsync(hh.data(), part, nb * sizeof(double),
+                                  hipMemcpyDeviceToHost, g->stream));
+        }
     }
     KS_HIP(hipStreamSynchronize(g->stream));
     const double h3 = g->geo.h[0] * g->geo.h[1] * g->geo.h[2];
@@ -1018,7 +1109,13 @@ int ks_energy(ks_grid *g, const void *d_psi, const double *d_vion, double t,
             sx += hx[b];
         ex = -0.75 * std::cbrt(3.0 / M_PI) * h3 * sx;
     }
-    *out_host = e + ex;
+    if (g->hartree) {
+        double sh = 0.0;
+        for (int b = 0; b < nb; ++b)
+            sh += hh[b];
+        eh = 0.5 * h3 * sh;
+    }
+    *out_host = e + ex + eh;
     if (!std::isfinite(*out_host))
         return fail(KS_E_NONFINITE, "energy is not finite");
     return KS_OK;
@@ -1259,7 +1356,7 @@ int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
         a.vout = g->d_v;
         a.xc = g->xc;
         a.dpart = d_dipole ? dpart : nullptr;
-        KS_HIP(launch_density(a, g->stream));
+        KS_TRY(density_potential(g, a, g->stream));
         if (d_dipole)
             KS_HIP(launch_dipole_finalize(dpart, ndb, h3, d_dipole,
                                           g->stream));
@@ -1271,21 +1368,22 @@ int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
         }
         g->vloc_set = true;
     }
-    const bool want_n_end = g->xc || d_dipole;
+    const bool want_n_end = g->nonlin || d_dipole;
     for (int step = 0; step < nsteps; ++step) {
         const double t = t0 + step * dt;
         double At[3], An[3];
         laser_A(g, t, At);
         laser_A(g, t + dt, An);
-        // exponential 1: H_t, tau = dt/2; predictor density when xc is on
+        // exponential 1: H_t, tau = dt/2; predictor density when the
+        // potential depends on the density
         rc = taylor_exponential(g, psi, half, g->d_v, At, half_a2(At),
                                 0.5 * dt,
-                                g->xc ? kFinalPred : kFinal,
-                                g->xc ? npart : nullptr, nullptr);
+                                g->nonlin ? kFinalPred : kFinal,
+                                g->nonlin ? npart : nullptr, nullptr);
         if (rc)
             return rc;
         const double *vnext = d_vion;
-        if (g->xc) {
+        if (g->nonlin) {
             DArgs a;
             a.geo = g->geo;
             a.nsrc = S;
@@ -1293,9 +1391,9 @@ int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
             a.rho = rho;
             a.vion = d_vion;
             a.vout = vpred;
-            a.xc = 1;
+            a.xc = g->xc;
             Timed tm(g, 2);
-            KS_HIP(launch_density(a, g->stream));
+            KS_TRY(density_potential(g, a, g->stream));
             vnext = vpred;
         }
         // exponential 2: H_{t+dt}, tau = dt/2, from psi_half into psi
@@ -1316,7 +1414,7 @@ int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
             a.xc = g->xc;
             a.dpart = d_dipole ? dpart : nullptr;
             Timed tm(g, 2);
-            KS_HIP(launch_density(a, g->stream));
+            KS_TRY(density_potential(g, a, g->stream));
             if (d_dipole)
                 KS_HIP(launch_dipole_finalize(dpart, ndb, h3,
                                               d_dipole + 3 * (step + 1),
@@ -1380,7 +1478,7 @@ int ks_propagate_cfm4(ks_grid *g, void *d_psi, const double *d_vion,
         a.vout = vh[ring[0]];
         a.xc = g->xc;
         a.dpart = d_dipole ? dpart : nullptr;
-        KS_HIP(launch_density(a, g->stream));
+        KS_TRY(density_potential(g, a, g->stream));
         if (d_dipole)
             KS_HIP(launch_dipole_finalize(dpart, ndb, h3, d_dipole,
                                           g->stream));
@@ -1449,7 +1547,7 @@ int ks_propagate_cfm4(ks_grid *g, void *d_psi, const double *d_vion,
             a.xc = g->xc;
             a.dpart = d_dipole ? dpart : nullptr;
             Timed tm(g, 2);
-            KS_HIP(launch_density(a, g->stream));
+            KS_TRY(density_potential(g, a, g->stream));
             if (d_dipole)
                 KS_HIP(launch_dipole_finalize(dpart, ndb, h3,
                                               d_dipole + 3 * (step + 1),
@@ -1544,7 +1642,7 @@ int batch_enqueue_step(ks_batch *b)
         if (e == 0)
             for (size_t i = 0; i < b->grids.size(); ++i) {
                 ks_grid *g = b->grids[i];
-                if (!g->xc)
+                if (!g->nonlin)
                     continue;
                 DArgs a;
                 a.geo = g->geo;
@@ -1553,8 +1651,8 @@ int batch_enqueue_step(ks_batch *b)
                 a.rho = wsp<double>(g, g->lay.rho);
                 a.vion = b->jobs[i].d_vion;
                 a.vout = wsp<double>(g, g->lay.vpred);
-                a.xc = 1;
-                KS_HIP(launch_density(a, st));
+                a.xc = g->xc;
+                KS_TRY(density_potential(g, a, st));
             }
     }
     for (size_t i = 0; i < b->grids.size(); ++i) {
@@ -1572,7 +1670,7 @@ int batch_enqueue_step(ks_batch *b)
             a.vout = g->d_v;
             a.xc = g->xc;
             a.dpart = jb.d_dipole ? wsp<double>(g, g->lay.dpart) : nullptr;
-            KS_HIP(launch_density(a, st));
+            KS_TRY(density_potential(g, a, st));
             if (jb.d_dipole)
                 KS_HIP(launch_dipole_finalize(a.dpart,
                                               density_blocks(g->geo.N), h3,
@@ -1646,13 +1744,13 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
         J.t[1] = g->ws + g->lay.t2;
         J.t[2] = g->ws + g->lay.t3;
         J.npart = wsp<double>(g, g->lay.npart);
-        J.npart_end = (g->xc || jobs[i].d_dipole) ? 1 : 0;
+        J.npart_end = (g->nonlin || jobs[i].d_dipole) ? 1 : 0;
         J.normpart_end = jobs[i].d_norms ? wsp<double>(g, g->lay.normpart)
                                          : nullptr;
         J.vion = jobs[i].d_vion;
         J.vcur = g->d_v;
         J.vpred = wsp<double>(g, g->lay.vpred);
-        J.xc = g->xc;
+        J.nonlin = g->nonlin ? 1 : 0;
         J.dt = jobs[i].dt;
         J.step = wsp<int>(g, g->lay.step);
         b->hjobs.push_back(J);
@@ -1725,8 +1823,8 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
     // the H.psi arguments of every job's eight Taylor passes: exponential
     // e = (p-1)/4 starts from psi (e = 0) or psi_half (e = 1); term j writes
     // t_j, the fourth pass the sum (psi_half, then psi); the potential is
-    // v(t) in the first exponential and v(t+dt) (predicted when exchange is
-    // on) in the second
+    // v(t) in the first exponential and v(t+dt) (predicted when the
+    // potential depends on the density) in the second
     std::vector<HArgs> hargs(8 * (size_t)njobs);
     for (int i = 0; i < njobs; ++i) {
         const JobDev &J = b->hjobs[i];
@@ -1738,7 +1836,7 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
             a.in = j == 1 ? (e == 0 ? (const void *)J.psi
                                     : (const void *)J.half)
                           : J.t[j - 2];
-            a.v = e == 0 ? J.vcur : (J.xc ? J.vpred : J.vion);
+            a.v = e == 0 ? J.vcur : (J.nonlin ? J.vpred : J.vion);
             a.cre = 0.0;
             a.cim = -0.5 * J.dt / j;
             if (j < 4) {
@@ -1748,7 +1846,7 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
                 a.base = e == 0 ? J.psi : J.half;
                 a.t1 = J.t[0];
                 a.t2 = J.t[1];
-                a.npart = e == 0 ? (J.xc ? J.npart : nullptr)
+                a.npart = e == 0 ? (J.nonlin ? J.npart : nullptr)
                                  : (J.npart_end ? J.npart : nullptr);
                 a.normpart = e == 1 ? J.normpart_end : nullptr;
             }
@@ -1798,6 +1896,9 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
         a.xc = g->xc;
         a.dpart = jb.d_dipole ? wsp<double>(g, g->lay.dpart) : nullptr;
         hipError_t e = launch_density(a, b->stream);
+        if (e == hipSuccess && g->hartree)
+            e = launch_hartree(g->pp, g->geo, a.rho, a.vout, true,
+                               wsp<double2>(g, g->lay.pwork), b->stream);
         if (e == hipSuccess && jb.d_dipole)
             e = launch_dipole_finalize(a.dpart, density_blocks(g->geo.N), h3,
                                        jb.d_dipole, b->stream);

@@ -169,11 +169,12 @@ struct JobDev {
     double2 *half = nullptr;       // psi_half
     void *t[3] = {nullptr, nullptr, nullptr};
     double *npart = nullptr;
-    int npart_end = 0;             // final density needed (xc or dipole)
+    int npart_end = 0;             // final density needed (a density-
+                                   // dependent potential or the dipole)
     double *normpart_end = nullptr;
     const double *vion = nullptr;
     double *vcur = nullptr, *vpred = nullptr;
-    int xc = 0;
+    int nonlin = 0;                // the potential depends on the density
     double dt = 0.0;
     // [max_steps][2] (A, |A|^2 / 2) at the two ends of each step, tabulated
     // on the host exactly as the single-job propagator evaluates them

@@ -48,6 +48,7 @@ class ks_grid_desc(C.Structure):
         ("laser", C.c_double * 6),
         ("precision", C.c_int),
         ("stream", C.c_void_p),
+        ("hartree", C.c_int),
     ]
 
 
@@ -74,6 +75,7 @@ EXPORTS = {
     "ks_workspace_bytes": (C.c_size_t, [C.c_void_p]),
     "ks_set_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "ks_update_vlocal": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ks_hartree": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ks_apply_h": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                              C.c_int, C.c_int, C.c_double]),
     "ks_propagate_etrs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
@@ -192,6 +194,7 @@ def ks_grid_create(spec, precision=KS_FP64, stream=None):
     d.laser[:] = list(spec.laser)
     d.precision = int(precision)
     d.stream = _stream_handle(stream)
+    d.hartree = int(getattr(spec, "hartree", 0))
     h = C.c_void_p()
     _check(lib().ks_grid_create(C.byref(d), C.byref(h)))
     return h, keep
@@ -215,6 +218,10 @@ def ks_set_workspace(h, ws):
 
 def ks_update_vlocal(h, vion, rho=None):
     return _check(lib().ks_update_vlocal(h, _ptr(vion), _ptr(rho)))
+
+
+def ks_hartree(h, rho, vh):
+    return _check(lib().ks_hartree(h, _ptr(rho), _ptr(vh)))
 
 
 def ks_apply_h(h, psi, hpsi, k, s0, ns, t):
@@ -394,6 +401,15 @@ class Grid:
         if rho is not None:
             _dev(rho, self.torch.float64, self.N, "rho")
         ks_update_vlocal(self.h, vion, rho)
+
+    def hartree(self, rho, out=None):
+        """Hartree potential v_H[rho] (FP64, N values on the device)."""
+        _dev(rho, self.torch.float64, self.N, "rho")
+        if out is None:
+            out = self.torch.empty_like(rho)
+        _dev(out, self.torch.float64, self.N, "vh")
+        ks_hartree(self.h, rho, out)
+        return out
 
     def apply_h(self, psi, out=None, k=0, s0=0, t=0.0):
         _dev(psi, self.torch.complex128, None, "psi")

@@ -7,6 +7,8 @@ import re
 
 import pytest
 
+from paper_1912_07921_amd import workloads as W
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ks.h")
 
@@ -51,11 +53,31 @@ def test_library_refuses_nothing_at_load_and_reports_errors_without_gpu():
     assert L.ks_grid_destroy(None) == 0
 
 
+def test_grid_description_errors_need_no_gpu():
+    """Invalid descriptions are refused before any device call: an unknown
+    Hartree flag (argument error) and the Hartree term on a grid with mixed
+    periodicity (unsupported)."""
+    from types import SimpleNamespace
+    from paper_1912_07921_amd import ks
+    null_stream = SimpleNamespace(cuda_stream=0)
+    spec = W.SystemSpec(n=(8, 8, 8), h=(0.4,) * 3, nstates=1, hartree=2)
+    with pytest.raises(ks.KSError) as e:
+        ks.ks_grid_create(spec, 0, null_stream)
+    assert e.value.code == -1
+    spec = W.SystemSpec(n=(8, 8, 8), h=(0.4,) * 3, periodic=(1, 0, 1),
+                        nstates=1, hartree=1)
+    with pytest.raises(ks.KSError) as e:
+        ks.ks_grid_create(spec, 0, null_stream)
+    assert e.value.code == -4
+    assert b"Hartree" in ks.lib().ks_last_error()
+
+
 def test_oracle_builds_and_loads(oracle_mod):
     lib = oracle_mod._load()
     for name in ["orc_create", "orc_apply_h", "orc_propagate_etrs",
                  "orc_density", "orc_dipole", "orc_vlocal", "orc_kick",
-                 "orc_gram", "orc_energy"]:
+                 "orc_gram", "orc_energy", "orc_hartree", "orc_hartree_at",
+                 "orc_hartree_energy"]:
         assert hasattr(lib, name)
 
 
