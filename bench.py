@@ -10,13 +10,14 @@ HBM.  Throughput is H.psi grid-point-states per second:
 Prints one JSON line with the FP64 rate, the roofline of the dominant kernel
 (the H.psi stencil, timed live with HIP events on its stream, beside a plain
 device copy timed in the same run), the CPU oracle timed on the host on a
-bounded sample, the FP32-mixed form and the CFM4 propagator on the same
-workload, and the serving mix (continuous batching of propagation requests)
-in both precisions.
+bounded sample, the FP32-mixed form, the CFM4 propagator and the step with
+the Hartree term on the same workload, and the serving mix (continuous
+batching of propagation requests) in both precisions.
 """
 from __future__ import annotations
 
 import argparse
+import copy
 import hashlib
 import json
 import os
@@ -159,6 +160,81 @@ def run_gpu(w, precision, steps, warmup, torch, tune=True, shape=None,
     return sec, dip, n.cpu().numpy(), prof, g, g.get_launch()
 
 
+def fft_length(n, periodic):
+    """Transform length of the Hartree solver along an axis of n points:
+    n (periodic) or the smallest product of 2, 3, 5 >= 2 n - 1."""
+    if periodic:
+        return n
+    m = max(1, 2 * n - 1)
+    while True:
+        r = m
+        for p in (2, 3, 5):
+            while r % p == 0:
+                r //= p
+        if r == 1:
+            return m
+        m += 1
+
+
+def hartree_pipeline_bytes(spec):
+    """HBM bytes one Hartree solve moves through its five passes (x forward
+    from the density, y forward, z forward * K * inverse, y inverse, x
+    inverse into the potential): the work array holds nz planes of
+    My x Mx complex values, K an octant of real values."""
+    nx, ny, nz = spec.n
+    per = all(spec.periodic)
+    Mx, My, Mz = (fft_length(n, per) for n in spec.n)
+    c = 16
+    xf = nx * ny * nz * 8 + ny * nz * Mx * c
+    yf = Mx * nz * ny * c + Mx * nz * My * c
+    zc = 2 * Mx * My * nz * c + (Mx // 2 + 1) * (My // 2 + 1) * \
+        (Mz // 2 + 1) * 8
+    yi = Mx * nz * My * c + Mx * nz * ny * c
+    xi = ny * nz * Mx * c + nx * ny * nz * 8
+    return xf + yf + zc + yi + xi, (Mx, My, Mz)
+
+
+def run_hartree(w, torch, steps, warmup, tune, reps=50):
+    """The same workload with the Hartree term in the potential: ETRS step
+    rate (FP64 and mixed) and the solve alone (HIP events around `reps`
+    back-to-back solves of the workload's density on the grid's stream)."""
+    from paper_1912_07921_amd import ks
+    wh = copy.copy(w)
+    wh.spec = copy.copy(w.spec)
+    wh.spec.hartree = 1
+    N, S = w.spec.npoints, w.spec.nk * w.spec.nstates
+    res = {}
+    for prec, key in ((0, "fp64"), (1, "mixed")):
+        log(f"Hartree {key}: {warmup} warmup + {steps} timed steps")
+        sec, _, _, prof, _, shape = run_gpu(wh, prec, steps, warmup, torch,
+                                            tune)
+        res[key] = dict(value=8.0 * N * S * steps / sec,
+                        ms_per_step=1e3 * sec / steps, launch_shape=shape)
+    g = ks.Grid(wh.spec)
+    rho = g.density(torch.from_numpy(w.psi0).cuda())
+    vh = torch.empty_like(rho)
+    for _ in range(5):
+        g.hartree(rho, vh)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        g.hartree(rho, vh)
+    e1.record(st)
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / reps
+    nbytes, M = hartree_pipeline_bytes(wh.spec)
+    res["solve"] = dict(us=round(us, 2), transform_lengths=list(M),
+                        pipeline_bytes=nbytes,
+                        achieved_GBs=round(nbytes / (us * 1e-6) / 1e9, 1),
+                        frac_of_hbm_peak=round(nbytes / (us * 1e-6) / 1e9 /
+                                               HBM_PEAK_GBS, 4),
+                        solves_per_step=2)
+    return res
+
+
 def serving_requests(torch, nreq, steps, rate):
     """The serving mix: request inputs built on the GPU, then held in pinned
     host memory as the payload each request brings (copied to HBM on
@@ -265,6 +341,10 @@ def main():
                     help="only run a 2 GiB device copy (counter calibration)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cfm4", action="store_true")
+    ap.add_argument("--no-hartree", action="store_true")
+    ap.add_argument("--hartree-only", action="store_true",
+                    help="only the step with the Hartree term and the solve "
+                         "alone (profiling runs)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shape (no autotuner)")
     ap.add_argument("--shape", default="",
@@ -298,6 +378,11 @@ def main():
     w = make_workload(args.workload)
     N, S = w.spec.npoints, w.spec.nk * w.spec.nstates
     units = 8.0 * N * S
+    if args.hartree_only:
+        print(json.dumps(dict(workload=w.name, hartree=run_hartree(
+            w, torch, args.steps, args.warmup, not args.no_tune))),
+            flush=True)
+        return
 
     log(f"FP64: {args.warmup} warmup + {args.steps} timed steps")
     fixed = tuple(int(v) for v in args.shape.split(",")) if args.shape \
@@ -398,6 +483,13 @@ def main():
             if prec == 0:
                 dipc64 = cdip
         out["cfm4"] = cf
+
+    per = w.spec.periodic
+    if not args.no_hartree and (all(per) or not any(per)):
+        hr = run_hartree(w, torch, args.steps, args.warmup, not args.no_tune)
+        hr["fp64"]["step_cost_vs_no_hartree"] = round(
+            hr["fp64"]["ms_per_step"] / out["ms_per_step"], 4)
+        out["hartree"] = hr
 
     if not args.no_serving:
         out["serving"] = run_serving(torch, args.serving_requests,

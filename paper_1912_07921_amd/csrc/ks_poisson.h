@@ -14,8 +14,9 @@ namespace ks {
 constexpr int kFftMaxLen = 512;     // longest transform along one axis
 constexpr int kFftMaxStages = 12;
 
-// One axis of the transform: length M = product of the radices (4, 2, 3,
-// 5, in this order), twiddles tw[m] = exp(-2 pi i m / M) on the device.
+// One axis of the transform: length M = product of the radices (16, 8, 4,
+// 2, 3, 5, in this order), twiddles tw[m] = exp(-2 pi i m / M) on the
+// device.
 struct FftAxis {
     int M = 1;
     int nst = 0;

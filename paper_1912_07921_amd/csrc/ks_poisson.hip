@@ -17,10 +17,12 @@
 // y inverse (keeping y < ny), x inverse (keeping x < nx, real part into v).
 // Lines that would transform zeros are never touched.
 //
-// Each 1D transform is a mixed-radix Stockham FFT (radices 4, 2, 3, 5) of NL
-// whole lines held in LDS as [point][line] with a padded row (NL + 1
-// complex values: the 16-byte accesses of consecutive lines fall in
-// distinct banks), ping-ponging between two buffers, one barrier per stage.
+// Each 1D transform is a mixed-radix Stockham FFT (radices 16, 8, 4, 2, 3,
+// 5; the 8- and 16-point butterflies are computed in registers from 2- and
+// 4-point ones, so a length of 128 or 256 takes two stages) of NL whole
+// lines held in LDS as [point][line] with a padded row (NL + 1 complex
+// values: the 16-byte accesses of consecutive lines fall in distinct
+// banks), ping-ponging between two buffers, one barrier per stage.
 // Along y and z the NL lines are NL consecutive x positions, so every global
 // access moves NL * 16 contiguous bytes; along x the lines are whole rows.
 #include "ks_poisson.h"
@@ -69,8 +71,44 @@ __device__ __forceinline__ double2 conj_if(double2 w, bool c)
     return w;
 }
 
-// y = DFT_P(c) with the P-th roots taken from the twiddle table
-// (w_P^m = tw[m * M / P]; conjugated for the inverse transform).
+// 4-point DFT of (a0, a1, a2, a3) into y0..y3 (w_4 = -i forward, +i
+// inverse).
+__device__ __forceinline__ void dft4(double2 a0, double2 a1, double2 a2,
+                                     double2 a3, double2 &y0, double2 &y1,
+                                     double2 &y2, double2 &y3, bool inv)
+{
+    const double2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
+    const double2 s13 = cadd(a1, a3), d13 = csub(a1, a3);
+    const double2 r = inv ? cmk<double2>(-d13.y, d13.x)
+                          : cmk<double2>(d13.y, -d13.x);
+    y0 = cadd(s02, s13);
+    y2 = csub(s02, s13);
+    y1 = cadd(d02, r);
+    y3 = csub(d02, r);
+}
+
+// x * w_16^m (conjugated root for the inverse); m is a constant after
+// unrolling.  cos and sin of 2 pi m / 16 from cos(pi/8), sin(pi/8), 1/sqrt2.
+__device__ __forceinline__ double2 mul_w16(double2 x, int m, bool inv)
+{
+    constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173;
+    constexpr double r2 = 0.70710678118654752440;
+    constexpr double C[16] = {1, c1, r2, s1, 0, -s1, -r2, -c1,
+                              -1, -c1, -r2, -s1, 0, s1, r2, c1};
+    constexpr double S[16] = {0, s1, r2, c1, 1, c1, r2, s1,
+                              0, -s1, -r2, -c1, -1, -c1, -r2, -s1};
+    const int mm = m & 15;
+    if (mm == 0)
+        return x;
+    return cmul(x, cmk<double2>(C[mm], inv ? S[mm] : -S[mm]));
+}
+
+// y = DFT_P(c).  P = 8 and 16 are composed of 2- and 4-point DFTs with the
+// inner roots of unity (q = 4 q1 + q2, u = u1 + (P/4) u2):
+//   DFT_P(c)[u] = DFT_4 over q2 of ( w_P^{u1 q2} DFT_{P/4} over q1 of
+//                 c[4 q1 + q2] )[u1].
+// P = 3 and 5 take their roots from the twiddle table (w_P^m =
+// tw[m * M / P]; conjugated for the inverse transform).
 template <int P>
 __device__ __forceinline__ void small_dft(const double2 (&c)[P],
                                           double2 (&y)[P],
@@ -81,15 +119,32 @@ __device__ __forceinline__ void small_dft(const double2 (&c)[P],
         y[0] = cadd(c[0], c[1]);
         y[1] = csub(c[0], c[1]);
     } else if constexpr (P == 4) {
-        const double2 s02 = cadd(c[0], c[2]), d02 = csub(c[0], c[2]);
-        const double2 s13 = cadd(c[1], c[3]), d13 = csub(c[1], c[3]);
-        // -i d13 (forward) or +i d13 (inverse)
-        const double2 r = inv ? cmk<double2>(-d13.y, d13.x)
-                              : cmk<double2>(d13.y, -d13.x);
-        y[0] = cadd(s02, s13);
-        y[2] = csub(s02, s13);
-        y[1] = cadd(d02, r);
-        y[3] = csub(d02, r);
+        dft4(c[0], c[1], c[2], c[3], y[0], y[1], y[2], y[3], inv);
+    } else if constexpr (P == 8) {
+        double2 z[4][2];
+#pragma unroll
+        for (int q2 = 0; q2 < 4; ++q2) {
+            z[q2][0] = cadd(c[q2], c[4 + q2]);
+            z[q2][1] = mul_w16(csub(c[q2], c[4 + q2]), 2 * q2, inv);
+        }
+#pragma unroll
+        for (int u1 = 0; u1 < 2; ++u1)
+            dft4(z[0][u1], z[1][u1], z[2][u1], z[3][u1], y[u1], y[u1 + 2],
+                 y[u1 + 4], y[u1 + 6], inv);
+    } else if constexpr (P == 16) {
+        double2 z[4][4];
+#pragma unroll
+        for (int q2 = 0; q2 < 4; ++q2) {
+            dft4(c[q2], c[4 + q2], c[8 + q2], c[12 + q2], z[q2][0], z[q2][1],
+                 z[q2][2], z[q2][3], inv);
+#pragma unroll
+            for (int u1 = 1; u1 < 4; ++u1)
+                z[q2][u1] = mul_w16(z[q2][u1], u1 * q2, inv);
+        }
+#pragma unroll
+        for (int u1 = 0; u1 < 4; ++u1)
+            dft4(z[0][u1], z[1][u1], z[2][u1], z[3][u1], y[u1], y[u1 + 4],
+                 y[u1 + 8], y[u1 + 12], inv);
     } else {
         const int step = M / P;
 #pragma unroll
@@ -116,11 +171,17 @@ __device__ __forceinline__ void fft_stage(const double2 *__restrict__ A,
                                           bool inv)
 {
     constexpr int PS = NL + 1;
+    constexpr int bstep = kFftThreads / NL;   // butterflies per sweep
     const int tstep = M / (L * P);
     const int nb = L * r;
-    for (int e = threadIdx.x; e < NL * nb; e += kFftThreads) {
-        const int l = e % NL, b = e / NL;
-        const int j = b / r, k = b - j * r;
+    // each thread keeps one line and walks the butterflies b = j r + k of
+    // that line with stride bstep (one division per stage, no division in
+    // the loop)
+    const int l = threadIdx.x % NL;
+    int b = threadIdx.x / NL;
+    int j = b / r, k = b - j * r;
+    const int dj = bstep / r, dk = bstep - dj * r;
+    for (; b < nb; b += bstep) {
         double2 c[P], y[P];
 #pragma unroll
         for (int q = 0; q < P; ++q) {
@@ -131,6 +192,12 @@ __device__ __forceinline__ void fft_stage(const double2 *__restrict__ A,
 #pragma unroll
         for (int u = 0; u < P; ++u)
             B[((j + L * u) * r + k) * PS + l] = y[u];
+        j += dj;
+        k += dk;
+        if (k >= r) {
+            k -= r;
+            ++j;
+        }
     }
 }
 
@@ -138,17 +205,19 @@ __device__ __forceinline__ void fft_stage(const double2 *__restrict__ A,
 // the result.  Ends with a barrier.
 template <int NL>
 __device__ double2 *fft_lines(double2 *A, double2 *B, const FftAxis &ax,
-                              bool inv)
+                              const double2 *tw, bool inv)
 {
     int L = 1, r = ax.M;
     for (int s = 0; s < ax.nst; ++s) {
         const int p = ax.rad[s];
         r /= p;
         switch (p) {
-        case 4: fft_stage<4, NL>(A, B, ax.M, L, r, ax.tw, inv); break;
-        case 2: fft_stage<2, NL>(A, B, ax.M, L, r, ax.tw, inv); break;
-        case 3: fft_stage<3, NL>(A, B, ax.M, L, r, ax.tw, inv); break;
-        default: fft_stage<5, NL>(A, B, ax.M, L, r, ax.tw, inv); break;
+        case 16: fft_stage<16, NL>(A, B, ax.M, L, r, tw, inv); break;
+        case 8: fft_stage<8, NL>(A, B, ax.M, L, r, tw, inv); break;
+        case 4: fft_stage<4, NL>(A, B, ax.M, L, r, tw, inv); break;
+        case 2: fft_stage<2, NL>(A, B, ax.M, L, r, tw, inv); break;
+        case 3: fft_stage<3, NL>(A, B, ax.M, L, r, tw, inv); break;
+        default: fft_stage<5, NL>(A, B, ax.M, L, r, tw, inv); break;
         }
         __syncthreads();
         double2 *t = A;
@@ -174,86 +243,134 @@ __device__ __forceinline__ double green(const LinePass &p, int i, int a,
     return r2 > 0.0 ? 1.0 / sqrt(r2) : p.g0;
 }
 
+// Most (point, line) pairs one thread owns in a launch (NL M <= 256 x this).
+constexpr int kMaxPts = 12;
+
+// The (point i, line li) pairs of the NL lines that this thread owns, in
+// the order that makes global accesses contiguous: along i for whole rows,
+// along li (x positions) otherwise.  All of a thread's loads are issued
+// before any of them is used.
+struct Points {
+    int i[kMaxPts], li[kMaxPts];
+    bool ok[kMaxPts];
+};
+
 template <int NL>
-__global__ __launch_bounds__(kFftThreads) void k_fft_lines(LinePass p)
+__device__ __forceinline__ void own_points(int M, bool rows, Points &q)
 {
-    extern __shared__ double2 lds[];
-    constexpr int PS = NL + 1;
-    const int M = p.ax.M;
-    double2 *A = lds, *B = lds + (size_t)M * PS;
-    const int l0 = blockIdx.x * NL;
-    const bool rows = p.sp == 1;   // whole contiguous lines (x axis)
-    for (int e = threadIdx.x; e < NL * M; e += kFftThreads) {
-        int i, li;
-        if (rows) {
-            i = e % M;
-            li = e / M;
-        } else {
-            li = e % NL;
-            i = e / NL;
-        }
-        const int l = l0 + li;
-        double2 val = cmk<double2>(0.0, 0.0);
-        if (l < p.nlines && i < p.nin) {
-            const int a = l % p.la, b = l / p.la;
-            if (p.in_kind == kFromWork)
-                val = p.work[a * p.sa + b * p.sb + i * p.sp];
-            else if (p.in_kind == kFromDensity)
-                val.x = p.rho[(long)l * p.nrow + i];
-            else
-                val.x = green(p, i, a, b);
-        }
-        A[i * PS + li] = val;
-    }
-    __syncthreads();
-    double2 *R = fft_lines<NL>(A, B, p.ax, p.op == kInverse);
-    if (p.op == kConvolve) {
-        const int hx = p.Kx / 2 + 1, hy = p.Ky / 2 + 1;
-        for (int e = threadIdx.x; e < NL * M; e += kFftThreads) {
-            const int li = e % NL, i = e / NL;
-            const int l = l0 + li;
-            if (l < p.nlines) {
-                const int a = l % p.la, b = l / p.la;
-                const int kx = min(a, p.Kx - a), ky = min(b, p.Ky - b);
-                const int kz = min(i, M - i);
-                const double k = p.K[((long)kz * hy + ky) * hx + kx];
-                R[i * PS + li] = cscale(R[i * PS + li], k);
+    if (rows) {
+        int i = threadIdx.x % M, li = threadIdx.x / M;
+        const int di = kFftThreads % M, dli = kFftThreads / M;
+#pragma unroll
+        for (int n = 0; n < kMaxPts; ++n) {
+            q.i[n] = i;
+            q.li[n] = li;
+            q.ok[n] = li < NL;
+            i += di;
+            li += dli;
+            if (i >= M) {
+                i -= M;
+                ++li;
             }
         }
-        __syncthreads();
-        double2 *other = R == A ? B : A;
-        R = fft_lines<NL>(R, other, p.ax, true);
-    }
-    for (int e = threadIdx.x; e < NL * M; e += kFftThreads) {
-        int i, li;
-        if (rows) {
-            i = e % M;
-            li = e / M;
-        } else {
-            li = e % NL;
-            i = e / NL;
-        }
-        const int l = l0 + li;
-        if (l < p.nlines && i < p.nout) {
-            const double2 val = R[i * PS + li];
-            if (p.out_kind == kToWork) {
-                const int a = l % p.la, b = l / p.la;
-                p.work[a * p.sa + b * p.sb + i * p.sp] = val;
-            } else if (p.out_kind == kToPotential) {
-                p.v[(long)l * p.nrow + i] = val.x;
-            } else {
-                p.v[(long)l * p.nrow + i] += val.x;
-            }
+    } else {
+        const int li = threadIdx.x % NL, i0 = threadIdx.x / NL;
+#pragma unroll
+        for (int n = 0; n < kMaxPts; ++n) {
+            q.i[n] = i0 + n * (kFftThreads / NL);
+            q.li[n] = li;
+            q.ok[n] = q.i[n] < M;
         }
     }
 }
 
-// Lines per workgroup for a transform length: both LDS buffers within
-// 96 KiB.
+template <int NL>
+__global__ __launch_bounds__(kFftThreads) void k_fft_lines(LinePass p)
+{
+    extern __shared__ double2 lds[];
+    __shared__ long lbase[NL];     // work-array offset of each line
+    __shared__ int lcoord[NL][2];  // its (a, b); a < 0: past the last line
+    constexpr int PS = NL + 1;
+    const int M = p.ax.M;
+    double2 *A = lds, *B = lds + (size_t)M * PS;
+    double2 *tw = B + (size_t)M * PS;   // the twiddle table, M values
+    const int l0 = blockIdx.x * NL;
+    const bool rows = p.sp == 1;   // whole contiguous lines (x axis)
+    for (int m = threadIdx.x; m < M; m += kFftThreads)
+        tw[m] = p.ax.tw[m];
+    if (threadIdx.x < NL) {
+        const int l = l0 + threadIdx.x;
+        const int a = l % p.la, b = l / p.la;
+        lbase[threadIdx.x] = a * p.sa + b * p.sb;
+        lcoord[threadIdx.x][0] = l < p.nlines ? a : -1;
+        lcoord[threadIdx.x][1] = b;
+    }
+    __syncthreads();
+    Points q;
+    own_points<NL>(M, rows, q);
+    {
+        double2 val[kMaxPts];
+#pragma unroll
+        for (int n = 0; n < kMaxPts; ++n) {
+            val[n] = cmk<double2>(0.0, 0.0);
+            const int i = q.i[n], li = q.li[n];
+            if (q.ok[n] && i < p.nin && lcoord[li][0] >= 0) {
+                if (p.in_kind == kFromWork)
+                    val[n] = p.work[lbase[li] + i * p.sp];
+                else if (p.in_kind == kFromDensity)
+                    val[n].x = p.rho[(long)(l0 + li) * p.nrow + i];
+                else
+                    val[n].x = green(p, i, lcoord[li][0], lcoord[li][1]);
+            }
+        }
+#pragma unroll
+        for (int n = 0; n < kMaxPts; ++n)
+            if (q.ok[n])
+                A[q.i[n] * PS + q.li[n]] = val[n];
+    }
+    __syncthreads();
+    double2 *R = fft_lines<NL>(A, B, p.ax, tw, p.op == kInverse);
+    if (p.op == kConvolve) {
+        // lines of the z axis: the points are along li (x positions)
+        const int hx = p.Kx / 2 + 1, hy = p.Ky / 2 + 1;
+        const int li = threadIdx.x % NL;
+        const int a = lcoord[li][0], b = lcoord[li][1];
+        if (a >= 0) {
+            const int kx = min(a, p.Kx - a), ky = min(b, p.Ky - b);
+            const double *Kl = p.K + (long)ky * hx + kx;
+            const long kstride = (long)hy * hx;
+            for (int i = threadIdx.x / NL; i < M; i += kFftThreads / NL)
+                R[i * PS + li] = cscale(R[i * PS + li],
+                                        Kl[min(i, M - i) * kstride]);
+        }
+        __syncthreads();
+        double2 *other = R == A ? B : A;
+        R = fft_lines<NL>(R, other, p.ax, tw, true);
+    }
+#pragma unroll
+    for (int n = 0; n < kMaxPts; ++n) {
+        const int i = q.i[n], li = q.li[n];
+        if (q.ok[n] && i < p.nout && lcoord[li][0] >= 0) {
+            const double2 val = R[i * PS + li];
+            if (p.out_kind == kToWork)
+                p.work[lbase[li] + i * p.sp] = val;
+            else if (p.out_kind == kToPotential)
+                p.v[(long)(l0 + li) * p.nrow + i] = val.x;
+            else
+                p.v[(long)(l0 + li) * p.nrow + i] += val.x;
+        }
+    }
+}
+
+// Lines per workgroup: both LDS buffers and the twiddles within 96 KiB and
+// at most kMaxPts points per thread.  (Fewer lines per group leave most of
+// the 256 threads idle in the 16-point stages; measured slower.)
 int lines_per_group(int M)
 {
     int nl = 32;
-    while (nl > 2 && 2 * (size_t)M * (nl + 1) * sizeof(double2) > 98304)
+    while (nl > 2 && ((2 * (size_t)M * (nl + 1) + M) * sizeof(double2) >
+                          98304 ||
+                      nl * M > kFftThreads * kMaxPts))
         nl /= 2;
     return nl;
 }
@@ -263,7 +380,11 @@ hipError_t run_pass(const LinePass &p, hipStream_t st)
     if (p.nlines <= 0)
         return hipSuccess;
     const int nl = lines_per_group(p.ax.M);
-    const size_t lds = 2 * (size_t)p.ax.M * (nl + 1) * sizeof(double2);
+    if (nl * p.ax.M > kFftThreads * kMaxPts)
+        return hipErrorInvalidValue;   // more points than a thread holds
+    // two line buffers and the twiddle table
+    const size_t lds = (2 * (size_t)p.ax.M * (nl + 1) + p.ax.M) *
+                       sizeof(double2);
     const dim3 grid((p.nlines + nl - 1) / nl), block(kFftThreads);
     switch (nl) {
     case 32: hipLaunchKernelGGL(k_fft_lines<32>, grid, block, lds, st, p);
@@ -342,7 +463,7 @@ bool factorize(int M, FftAxis *ax)
     if (M < 1 || M > kFftMaxLen)
         return false;
     int m = M, nst = 0;
-    for (int p : {4, 2, 3, 5})
+    for (int p : {16, 8, 4, 2, 3, 5})
         while (m % p == 0) {
             if (nst == kFftMaxStages)
                 return false;
