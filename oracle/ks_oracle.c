@@ -78,6 +78,24 @@
  *       m_a in (-n_a/2, n_a/2], with v_H(G = 0) = 0 (a compensating uniform
  *       background).  Mixed periodicity is not defined.  With R11 on,
  *       v = v_ion + v_H[n] (+ v_x[n]) and E gains E_H = 1/2 h^3 sum n v_H.
+ *   R12 Macroscopic current (section "Electric and thermal conductivities",
+ *       eq. current_density): J = -(i/Omega) sum_k w_k sum_s f_s
+ *       <psi|[H, r]|psi>, Omega = the cell (box) volume n_a h_a.  On the
+ *       grid the commutator has the matrix elements H_ij (x_j - x_i), with
+ *       x_j - x_i the displacement of the coupled point: m h along the
+ *       axis for a stencil tap m (so wrapped taps of a periodic axis count
+ *       their true displacement), and the difference of the two points'
+ *       images inside the atom's sphere for the projector term.  The local
+ *       potential is diagonal and drops out.
+ *   R13 Spectra from traces sampled at t_n = n dt, n = 0 .. nt-1 (section
+ *       "van der Waals", the absorption run; section "Electric and thermal
+ *       conductivities", eq. FT), with the trapezoid rule (weights 1/2 at
+ *       both ends) and a damping window e^{-gamma t}:
+ *       polarizability alpha(w) = (1/kappa) dt sum w_n (d(t_n) - d(0))
+ *       e^{+i w t_n} e^{-gamma t_n} after a kick kappa, strength function
+ *       S(w) = (2 w / pi) Im alpha(w) (integrates to the electron count);
+ *       conductivity sigma(w) = (1/E0) dt sum w_n J(t_n) e^{-i w t_n}
+ *       e^{-gamma t_n}.
  *
  * Layout: psi is complex double, [nk][nstates][nz][ny][nx], x fastest.
  */
@@ -321,6 +339,156 @@ void orc_atom_table(const orc_system *S, int a, int *idx, double *p)
     const orc_atom *A = &S->atoms[a];
     memcpy(idx, A->idx, sizeof(int) * A->npts);
     memcpy(p, A->p, sizeof(double) * A->nproj * A->npts);
+}
+
+/* psi at integer position (x,y,z) under the boundary rule of R1. */
+static cplx fetch(const orc_system *S, const cplx *psi, int k, int x, int y,
+                  int z);
+void orc_laser_A(const orc_system *S, double t, double A[3]);
+
+/*
+ * [H, r_axis] psi for one state on k-point k (R12): out_i =
+ * sum_j H_ij (x_j - x_i) psi_j.
+ */
+static void comm_r_one(const orc_system *S, int k, const double A[3],
+                       int axis, const cplx *psi, cplx *out)
+{
+    const orc_desc *d = &S->d;
+    const double h = d->h[axis];
+    for (int z = 0; z < d->n[2]; ++z)
+        for (int y = 0; y < d->n[1]; ++y)
+            for (int x = 0; x < d->n[0]; ++x) {
+                long g = ((long)z * d->n[1] + y) * d->n[0] + x;
+                cplx acc = 0.0;
+                for (int m = 1; m <= 4; ++m) {
+                    int p[3] = {x, y, z}, q[3] = {x, y, z};
+                    p[axis] += m;
+                    q[axis] -= m;
+                    cplx fp = fetch(S, psi, k, p[0], p[1], p[2]);
+                    cplx fm = fetch(S, psi, k, q[0], q[1], q[2]);
+                    /* kinetic taps -1/2 c_m / h^2 at displacements +-m h */
+                    acc += (-0.5 * LAP_C[m] / (h * h)) * (m * h) * (fp - fm);
+                    /* gauge taps -i A d_m / h (+m) and +i A d_m / h (-m) */
+                    acc += (-I * A[axis] * GRAD_D[m] / h) * (m * h) * fp +
+                           (I * A[axis] * GRAD_D[m] / h) * (-m * h) * fm;
+                }
+                out[g] = acc;
+            }
+    /* projectors: sum_g V_ig (X_g - X_i) psi_g with X the coordinate of the
+     * point's image inside the sphere */
+    double h3 = dvol(S);
+    for (int a = 0; a < d->natoms; ++a) {
+        const orc_atom *At = &S->atoms[a];
+        for (int j = 0; j < At->nproj; ++j) {
+            const double *p = At->p + (size_t)j * At->npts;
+            cplx C = 0.0, D = 0.0;
+            for (int i = 0; i < At->npts; ++i) {
+                const int *sh = At->lshift + 3 * i;
+                double kT = 0.0;
+                for (int ax = 0; ax < 3; ++ax)
+                    kT += S->kpts[3 * k + ax] * sh[ax] * cell_len(S, ax);
+                const long gi = At->idx[i];
+                const int c[3] = {(int)(gi % d->n[0]),
+                                  (int)((gi / d->n[0]) % d->n[1]),
+                                  (int)(gi / ((long)d->n[0] * d->n[1]))};
+                const double X = coord(S, axis, c[axis]) +
+                                 sh[axis] * cell_len(S, axis);
+                C += p[i] * cexp(I * kT) * psi[gi];
+                D += p[i] * cexp(I * kT) * X * psi[gi];
+            }
+            C *= h3;
+            D *= h3;
+            for (int i = 0; i < At->npts; ++i) {
+                const int *sh = At->lshift + 3 * i;
+                double kT = 0.0;
+                for (int ax = 0; ax < 3; ++ax)
+                    kT += S->kpts[3 * k + ax] * sh[ax] * cell_len(S, ax);
+                const long gi = At->idx[i];
+                const int c[3] = {(int)(gi % d->n[0]),
+                                  (int)((gi / d->n[0]) % d->n[1]),
+                                  (int)(gi / ((long)d->n[0] * d->n[1]))};
+                const double X = coord(S, axis, c[axis]) +
+                                 sh[axis] * cell_len(S, axis);
+                out[gi] += p[i] * cexp(-I * kT) * At->E[j] * (D - X * C);
+            }
+        }
+    }
+}
+
+/* [H(t), r_axis] applied to ns states of k-point k (R12), for tests. */
+void orc_comm_r(const orc_system *S, int k, double t, int axis, int ns,
+                const cplx *in, cplx *out)
+{
+    double A[3];
+    orc_laser_A(S, t, A);
+#pragma omp parallel for
+    for (int s = 0; s < ns; ++s)
+        comm_r_one(S, k, A, axis, in + (size_t)s * S->N,
+                   out + (size_t)s * S->N);
+}
+
+/*
+ * Macroscopic current J(t) of all nk*ns states (R12): J_a = -(i/Omega)
+ * sum_k w_k sum_s f_s h^3 sum_g conj(psi) [H, r_a] psi.  Jc receives the
+ * complex values (the imaginary parts vanish up to rounding).
+ */
+void orc_current(const orc_system *S, const cplx *psi, double t, cplx Jc[3])
+{
+    const long N = S->N;
+    const int ns = S->d.nstates;
+    double A[3];
+    orc_laser_A(S, t, A);
+    const double omega = cell_len(S, 0) * cell_len(S, 1) * cell_len(S, 2);
+    cplx *tmp = malloc(sizeof(cplx) * N);
+    for (int ax = 0; ax < 3; ++ax) {
+        cplx acc = 0.0;
+        for (int k = 0; k < S->d.nk; ++k)
+            for (int s = 0; s < ns; ++s) {
+                const cplx *p = psi + ((size_t)k * ns + s) * N;
+                comm_r_one(S, k, A, ax, p, tmp);
+                cplx e = 0.0;
+                for (long g = 0; g < N; ++g)
+                    e += conj(p[g]) * tmp[g];
+                acc += S->kw[k] * S->occ[s] * dvol(S) * e;
+            }
+        Jc[ax] = -I * acc / omega;
+    }
+    free(tmp);
+}
+
+/* Strength function S(w) of a kicked run from the dipole component d
+ * (nt samples) along the kick (R13). */
+void orc_strength_function(const double *d, int nt, double dt, double kappa,
+                           double gamma, const double *w, int nw,
+                           double *out)
+{
+    for (int i = 0; i < nw; ++i) {
+        cplx alpha = 0.0;
+        for (int n = 0; n < nt; ++n) {
+            const double wt = (n == 0 || n == nt - 1) ? 0.5 : 1.0;
+            const double t = n * dt;
+            alpha += wt * (d[n] - d[0]) * cexp(I * w[i] * t) *
+                     exp(-gamma * t);
+        }
+        alpha *= dt / kappa;
+        out[i] = 2.0 * w[i] / M_PI * cimag(alpha);
+    }
+}
+
+/* Conductivity sigma(w) from a current component J (nt samples) after an
+ * impulsive field E0 (R13). */
+void orc_conductivity(const double *J, int nt, double dt, double E0,
+                      double gamma, const double *w, int nw, cplx *out)
+{
+    for (int i = 0; i < nw; ++i) {
+        cplx acc = 0.0;
+        for (int n = 0; n < nt; ++n) {
+            const double wt = (n == 0 || n == nt - 1) ? 0.5 : 1.0;
+            const double t = n * dt;
+            acc += wt * J[n] * cexp(-I * w[i] * t) * exp(-gamma * t);
+        }
+        out[i] = acc * dt / E0;
+    }
 }
 
 /* psi at integer position (x,y,z) under the boundary rule of R1. */

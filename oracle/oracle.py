@@ -97,6 +97,14 @@ def _load():
         lib.orc_hartree_energy.argtypes = [vp, vp]
         lib.orc_coulomb_cell_mean.restype = C.c_double
         lib.orc_coulomb_cell_mean.argtypes = [vp]
+        lib.orc_comm_r.argtypes = [vp, C.c_int, C.c_double, C.c_int, C.c_int,
+                                   vp, vp]
+        lib.orc_current.argtypes = [vp, vp, C.c_double, vp]
+        lib.orc_strength_function.argtypes = [vp, C.c_int, C.c_double,
+                                              C.c_double, C.c_double, vp,
+                                              C.c_int, vp]
+        lib.orc_conductivity.argtypes = [vp, C.c_int, C.c_double, C.c_double,
+                                         C.c_double, vp, C.c_int, vp]
         lib.orc_num_threads.restype = C.c_int
         _lib = lib
     return _lib
@@ -259,6 +267,22 @@ class Oracle:
         rho = _f64(rho)
         return self._lib.orc_hartree_energy(self._h, _ptr(rho))
 
+    def comm_r(self, psi, axis, k=0, t=0.0):
+        """[H(t), r_axis] psi for the states in psi at k-point k (R12)."""
+        psi = np.ascontiguousarray(psi, dtype=np.complex128).reshape(
+            -1, self.N)
+        out = np.empty_like(psi)
+        self._lib.orc_comm_r(self._h, int(k), float(t), int(axis),
+                             psi.shape[0], _ptr(psi), _ptr(out))
+        return out
+
+    def current(self, psi, t=0.0, complex_values=False):
+        """Macroscopic current J(t) (3 values; R12)."""
+        psi = self._c128(psi, self.nk * self.ns)
+        Jc = np.zeros(3, dtype=np.complex128)
+        self._lib.orc_current(self._h, _ptr(psi), float(t), _ptr(Jc))
+        return Jc if complex_values else Jc.real
+
     def dipole(self, rho):
         rho = _f64(rho)
         d = np.zeros(3)
@@ -324,6 +348,29 @@ def coulomb_cell_mean(h) -> float:
     (the G(0) of reading R11)."""
     hh = _f64(h)
     return float(_load().orc_coulomb_cell_mean(_ptr(hh)))
+
+
+def strength_function(d, dt, kappa, gamma, omega):
+    """S(w) of a kicked run from the dipole component along the kick (R13)."""
+    lib = _load()
+    d = _f64(d)
+    omega = _f64(omega)
+    out = np.empty(len(omega))
+    lib.orc_strength_function(_ptr(d), len(d), float(dt), float(kappa),
+                              float(gamma), _ptr(omega), len(omega),
+                              _ptr(out))
+    return out
+
+
+def conductivity(J, dt, E0, gamma, omega):
+    """sigma(w) from a current component after an impulsive field (R13)."""
+    lib = _load()
+    J = _f64(J)
+    omega = _f64(omega)
+    out = np.empty(len(omega), dtype=np.complex128)
+    lib.orc_conductivity(_ptr(J), len(J), float(dt), float(E0),
+                         float(gamma), _ptr(omega), len(omega), _ptr(out))
+    return out
 
 
 def num_threads() -> int:

@@ -826,3 +826,121 @@ def test_harmonic_potential_theorem_with_hartree(oracle_mod):
     d1 = np.abs(out[1][0]) ** 2
     d0 = np.abs(out[0][0]) ** 2
     assert np.abs(d1 - d0).max() > 0.05 * d0.max()
+
+
+# --------------------------------------------------------------------------
+# macroscopic current (section "Electric and thermal conductivities", eq.
+# current_density; reading R12 of the oracle) and spectra of traces (R13)
+# --------------------------------------------------------------------------
+def _laser_system(periodic=(0, 0, 0), n=(9, 8, 7), h=(0.4, 0.35, 0.3)):
+    return W.tiny(n=n, h=h, periodic=periodic, nk=1, nstates=2, natoms=2,
+                  lmax=2, rc=1.0, sigma=0.35,
+                  laser=(0.3, 0.8, 3.0, 0.2, 0.1, 0.9))
+
+
+def test_commutator_with_position_on_a_finite_grid(oracle_mod):
+    """Without a wrap the displacement form of [H, x] is the literal
+    commutator H(x psi) - x (H psi), every term on (stencil, gauge,
+    projectors, potential)."""
+    spec, v, psi = _laser_system()
+    o = oracle_mod.Oracle(spec)
+    x, y, z = _coords(spec)
+    Zg, Yg, Xg = np.meshgrid(z, y, x, indexing="ij")
+    t = 1.1
+    A = o.laser_A(t)
+    for ax, X in enumerate((Xg, Yg, Zg)):
+        X = X.reshape(-1)
+        got = o.comm_r(psi[0], ax, t=t)
+        want = (o.apply_h(v, psi[0] * X, A=A) -
+                X * o.apply_h(v, psi[0], A=A))
+        assert np.abs(got - want).max() < 1e-13 * np.abs(want).max()
+
+
+def test_commutator_is_the_k_derivative_under_bloch_conditions(oracle_mod):
+    """Periodic grid: with psi = e^{ik.r} u, i <psi|[H, r_a]|psi> is the
+    derivative d/dk_a of <psi_k|H(k)|psi_k> (H(k) through the Bloch wrap
+    phases and projector phases), by central differences in k."""
+    import copy
+    spec, v, psi = _laser_system(periodic=(1, 1, 1), n=(8, 7, 9))
+    k0 = spec.kpts[0].copy()
+    x, y, z = _coords(spec)
+    Zg, Yg, Xg = np.meshgrid(z, y, x, indexing="ij")
+    r = [g.reshape(-1) for g in (Xg, Yg, Zg)]
+    u = psi[0, 0]
+    t = 1.1
+    h3 = np.prod(spec.h)
+
+    def energy(k):
+        s2 = copy.copy(spec)
+        s2.kpts = k[None].copy()
+        o2 = oracle_mod.Oracle(s2)
+        pk = np.exp(1j * (k[0] * r[0] + k[1] * r[1] + k[2] * r[2])) * u
+        return np.vdot(pk, o2.apply_h(v, pk, A=o2.laser_A(t))[0]) * h3
+
+    o = oracle_mod.Oracle(spec)
+    p0 = np.exp(1j * (k0[0] * r[0] + k0[1] * r[1] + k0[2] * r[2])) * u
+    for ax in range(3):
+        e = np.zeros(3)
+        e[ax] = 1e-4
+        dE = (energy(k0 + e) - energy(k0 - e)) / 2e-4
+        val = 1j * np.vdot(p0, o.comm_r(p0, ax, t=t)[0]) * h3
+        assert abs(dE - val) < 1e-8 * abs(val), (ax, dE, val)
+
+
+def test_current_is_minus_the_dipole_rate_over_the_volume(oracle_mod):
+    """Ehrenfest: d/dt sum <r> = i <[H, r]>, so along a non-linear
+    trajectory (exchange, projectors, laser, kick) the central difference of
+    the dipole trace equals -Omega J, to second order in dt."""
+    spec, v, psi = W.tiny(n=(12, 11, 10), h=(0.4, 0.4, 0.4), nstates=2,
+                          natoms=2, lmax=1, rc=1.2, sigma=0.4, xc=1,
+                          laser=(0.3, 0.8, 3.0, 0.2, 0.1, 0.9))
+    h3 = np.prod(spec.h)
+    psi = psi / np.sqrt(np.sum(np.abs(psi) ** 2, axis=2, keepdims=True) * h3)
+    o = oracle_mod.Oracle(spec)
+    psi = o.kick(psi, 0.1)
+    omega = np.prod(np.array(spec.n) * np.array(spec.h))
+    errs = []
+    for dt in (0.004, 0.002):
+        p, t, dips, Js = psi.copy(), 0.2, [], []
+        for _ in range(4):
+            Jc = o.current(p, t, complex_values=True)
+            assert np.abs(Jc.imag).max() < 1e-12 * np.abs(Jc.real).max()
+            Js.append(Jc.real)
+            p, d, _ = o.propagate_etrs(p, 0.3 * v, 1, dt, t)
+            dips.append(d[0])
+            t += dt
+        dips.append(d[1])
+        dips, Js = np.array(dips), np.array(Js)
+        rate = (dips[2:] - dips[:-2]) / (2 * dt)
+        errs.append(np.abs(rate + omega * Js[1:]).max())
+        scale = np.abs(omega * Js).max()
+    assert errs[1] < 1e-4 * scale and errs[0] / errs[1] > 3.0, errs
+
+
+def test_strength_function_closed_form_and_sum_rule(oracle_mod):
+    """A kicked harmonic response d(t) = N kappa / w0 sin(w0 t) has
+    alpha(w) = N / (w0^2 - (w + i gamma)^2) under the damping window, and
+    the strength function integrates to the electron count N (f-sum
+    rule)."""
+    N, kappa, w0, gamma, dt = 2.0, 0.01, 0.5, 0.05, 0.01
+    t = dt * np.arange(int(600 / dt) + 1)
+    d = N * kappa / w0 * np.sin(w0 * t)
+    om = np.linspace(0.05, 2.0, 40)
+    S = oracle_mod.strength_function(d, dt, kappa, gamma, om)
+    want = 2 * om / np.pi * (N / (w0 ** 2 - (om + 1j * gamma) ** 2)).imag
+    assert np.abs(S - want).max() < 1e-8 * np.abs(want).max()
+    om2 = np.linspace(0.0, 20.0, 20001)
+    S2 = oracle_mod.strength_function(d, dt, kappa, gamma, om2)
+    assert abs(np.trapezoid(S2, om2) - N) < 0.01 * N
+    assert abs(om[np.argmax(S)] - w0) <= om[1] - om[0]
+
+
+def test_conductivity_of_a_drude_current(oracle_mod):
+    """J(t) = E0 e^{-Gamma t} after an impulsive field gives
+    sigma(w) = 1 / (Gamma + gamma + i w) (with the damping window), to the
+    trapezoid rule's O(dt^2)."""
+    dt, E0, Gam, gamma = 0.01, 0.1, 0.3, 0.05
+    t = dt * np.arange(int(600 / dt) + 1)
+    om = np.linspace(0.0, 2.0, 21)
+    sig = oracle_mod.conductivity(E0 * np.exp(-Gam * t), dt, E0, gamma, om)
+    assert np.abs(sig - 1 / (Gam + gamma + 1j * om)).max() < 1e-4
