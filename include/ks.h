@@ -179,6 +179,45 @@ int ks_propagate_cfm4(ks_grid *g, void *d_psi, const double *d_vion,
                       int nsteps, double dt, double t0, double *d_dipole,
                       double *d_norms);
 
+/* Macroscopic current J(t) (section "Electric and thermal
+ * conductivities", eq. current_density):
+ *   J = -(i / Omega) sum_k w_k sum_s f_s <psi_ks|[H(t), r]|psi_ks>,
+ * Omega = nx hx ny hy nz hz (the cell, or the box of a finite grid), for
+ * all nk*nstates states in d_psi (complex128, device) at time t (A(t) of
+ * the grid's laser).  On the grid [H, r] has the matrix elements
+ * H_ij (x_j - x_i) with x_j - x_i the displacement of the coupled point:
+ * m h for a stencil tap m (also across a periodic wrap), the difference of
+ * the two points' sphere images for the projectors; the local potential
+ * drops out.  On a finite grid this is the literal commutator; on a
+ * periodic one it is the k-derivative of the Bloch Hamiltonian.  out_host:
+ * 3 doubles (x, y, z).  Synchronises the stream.  Needs a workspace. */
+int ks_current(ks_grid *g, const void *d_psi, double t, double out_host[3]);
+
+/* Strength function of a kicked run (section "van der Waals", the
+ * absorption run): from nt samples d(t_n), t_n = n dt, of the dipole
+ * component along the kick (device, sample n at d_trace[n * stride]; for
+ * the (nsteps+1) x 3 dipole trace of ks_propagate_etrs use stride 3 and
+ * offset the pointer to the component),
+ *   alpha(w) = (1/kappa) dt sum_n w_n (d(t_n) - d(0)) e^{i w t_n}
+ *              e^{-gamma t_n}   (trapezoid weights w_n: 1/2 at both ends),
+ *   d_out[i] = S(w_i) = (2 w_i / pi) Im alpha(w_i)
+ * for the nw frequencies d_omega (device).  S integrates to the number of
+ * electrons; the absorption cross section is (2 pi^2 / c) S.  Stream-
+ * ordered on `stream` (a hipStream_t, NULL: default); needs no grid. */
+int ks_strength_function(const double *d_trace, int nt, int stride,
+                         double dt, double kappa, double gamma,
+                         const double *d_omega, int nw, double *d_out,
+                         void *stream);
+
+/* Conductivity after an impulsive field E0 (section "Electric and thermal
+ * conductivities", eq. FT): from nt samples J(t_n) of a current component
+ * (device, stride as above),
+ *   sigma(w_i) = (1/E0) dt sum_n w_n J(t_n) e^{-i w_i t_n} e^{-gamma t_n},
+ * into d_out (device, nw complex128).  Stream-ordered on `stream`. */
+int ks_conductivity(const double *d_trace, int nt, int stride, double dt,
+                    double E0, double gamma, const double *d_omega, int nw,
+                    void *d_out, void *stream);
+
 /* d_rho[g] = sum_k w_k sum_s f_s |psi_ks(g)|^2 over all nk*nstates states
  * (section "Local domains", n = sum of densities). */
 int ks_density(ks_grid *g, const void *d_psi, double *d_rho);

@@ -3,6 +3,7 @@
 // over the gfx950 kernels of ks_kernels.hip.
 #include "../../include/ks.h"
 #include "ks_internal.h"
+#include "ks_observe.h"
 #include "ks_poisson.h"
 
 #include <hip/hip_runtime.h>
@@ -80,8 +81,8 @@ struct ks_grid {
     size_t ws_bytes = 0;
     struct {
         size_t t1, t2, t3, half, npart, normpart, D, W, Dpart, rho, vpred,
-            dpart, gpart, dotpart, xpart, step, vhist, veff, pwork, vh,
-            total;
+            dpart, gpart, dotpart, xpart, step, vhist, veff, pwork, vh, cpart,
+            cnl, total;
     } lay{};
     int ntiles_max = 64;
     int nchunk = 1;
@@ -435,6 +436,8 @@ void layout(ks_grid *g)
     g->lay.veff = take(N * 8);
     g->lay.pwork = take(g->hartree ? g->pp.work_elems * 16 : 0);
     g->lay.vh = take(g->hartree ? N * 8 : 0);
+    g->lay.cpart = take(S * current_chunks((long)N) * 3 * 8);
+    g->lay.cnl = take(S * std::max(1, g->natoms) * 3 * 8);
     g->lay.total = off;
 }
 
@@ -938,6 +941,93 @@ int ks_hartree(ks_grid *g, const double *d_rho, double *d_vh)
     Timed tm(g, 2);
     KS_HIP(launch_hartree(g->pp, g->geo, d_rho, d_vh, false,
                           wsp<double2>(g, g->lay.pwork), g->stream));
+    return KS_OK;
+}
+
+int ks_current(ks_grid *g, const void *d_psi, double t, double out_host[3])
+{
+    if (!g || !d_psi || !out_host)
+        return fail(KS_E_ARG, "NULL argument");
+    if (!std::isfinite(t))
+        return fail(KS_E_ARG, "t must be finite");
+    int rc = need_ws(g);
+    if (rc)
+        return rc;
+    CurArgs a;
+    a.geo = g->geo;
+    a.psi = static_cast<const double2 *>(d_psi);
+    a.kph = g->d_kph;
+    a.nstates = g->ns;
+    a.sg0 = 0;
+    laser_A(g, t, a.A);
+    a.pj = g->pj;
+    a.part = wsp<double>(g, g->lay.cpart);
+    a.nl = wsp<double>(g, g->lay.cnl);
+    {
+        Timed tm(g, 2);
+        KS_HIP(launch_current(a, g->stot, g->stream));
+    }
+    const int nch = current_chunks(g->geo.N);
+    const int na = g->natoms;
+    std::vector<double> hp((size_t)g->stot * nch * 3);
+    std::vector<double> hn((size_t)g->stot * std::max(1, na) * 3, 0.0);
+    KS_HIP(hipMemcpyAsync(hp.data(), a.part, hp.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, g->stream));
+    if (na > 0)
+        KS_HIP(hipMemcpyAsync(hn.data(), a.nl,
+                              (size_t)g->stot * na * 3 * sizeof(double),
+                              hipMemcpyDeviceToHost, g->stream));
+    KS_HIP(hipStreamSynchronize(g->stream));
+    const double h3 = g->geo.h[0] * g->geo.h[1] * g->geo.h[2];
+    const double vol = g->geo.nx * g->geo.h[0] * g->geo.ny * g->geo.h[1] *
+                       g->geo.nz * g->geo.h[2];
+    for (int ax = 0; ax < 3; ++ax) {
+        double J = 0.0;
+        for (int s = 0; s < g->stot; ++s) {
+            double loc = 0.0, nl = 0.0;
+            for (int c = 0; c < nch; ++c)
+                loc += hp[((size_t)s * nch + c) * 3 + ax];
+            for (int at = 0; at < na; ++at)
+                nl += hn[((size_t)s * na + at) * 3 + ax];
+            J += g->wocc[s] * (h3 * loc + nl);
+        }
+        out_host[ax] = J / vol;
+    }
+    if (!std::isfinite(out_host[0]) || !std::isfinite(out_host[1]) ||
+        !std::isfinite(out_host[2]))
+        return fail(KS_E_NONFINITE, "current is not finite");
+    return KS_OK;
+}
+
+int ks_strength_function(const double *d_trace, int nt, int stride,
+                         double dt, double kappa, double gamma,
+                         const double *d_omega, int nw, double *d_out,
+                         void *stream)
+{
+    if (!d_trace || (nw > 0 && (!d_omega || !d_out)))
+        return fail(KS_E_ARG, "NULL argument");
+    if (nt < 2 || stride < 1 || nw < 0 || !(dt > 0.0) || kappa == 0.0 ||
+        !std::isfinite(kappa) || !(gamma >= 0.0))
+        return fail(KS_E_ARG, "need nt >= 2, stride >= 1, nw >= 0, dt > 0, "
+                              "kappa != 0, gamma >= 0");
+    KS_HIP(launch_damped_ft(d_trace, nt, stride, dt, kappa, gamma, d_omega,
+                            nw, 0, d_out, static_cast<hipStream_t>(stream)));
+    return KS_OK;
+}
+
+int ks_conductivity(const double *d_trace, int nt, int stride, double dt,
+                    double E0, double gamma, const double *d_omega, int nw,
+                    void *d_out, void *stream)
+{
+    if (!d_trace || (nw > 0 && (!d_omega || !d_out)))
+        return fail(KS_E_ARG, "NULL argument");
+    if (nt < 2 || stride < 1 || nw < 0 || !(dt > 0.0) || E0 == 0.0 ||
+        !std::isfinite(E0) || !(gamma >= 0.0))
+        return fail(KS_E_ARG, "need nt >= 2, stride >= 1, nw >= 0, dt > 0, "
+                              "E0 != 0, gamma >= 0");
+    KS_HIP(launch_damped_ft(d_trace, nt, stride, dt, E0, gamma, d_omega, nw,
+                            1, static_cast<double *>(d_out),
+                            static_cast<hipStream_t>(stream)));
     return KS_OK;
 }
 

@@ -85,6 +85,15 @@ EXPORTS = {
                                     C.c_int, C.c_double, C.c_double,
                                     C.c_void_p, C.c_void_p]),
     "ks_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ks_current": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double,
+                             C.POINTER(C.c_double)]),
+    "ks_strength_function": (C.c_int, [C.c_void_p, C.c_int, C.c_int,
+                                       C.c_double, C.c_double, C.c_double,
+                                       C.c_void_p, C.c_int, C.c_void_p,
+                                       C.c_void_p]),
+    "ks_conductivity": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double,
+                                  C.c_double, C.c_double, C.c_void_p,
+                                  C.c_int, C.c_void_p, C.c_void_p]),
     "ks_dipole": (C.c_int, [C.c_void_p, C.c_void_p,
                             C.POINTER(C.c_double)]),
     "ks_kick": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double]),
@@ -236,6 +245,64 @@ def ks_propagate_etrs(h, psi, vion, nsteps, dt, t0, dipole, norms):
 def ks_propagate_cfm4(h, psi, vion, nsteps, dt, t0, dipole, norms):
     return _check(lib().ks_propagate_cfm4(h, _ptr(psi), _ptr(vion), nsteps,
                                           dt, t0, _ptr(dipole), _ptr(norms)))
+
+
+def ks_current(h, psi, t):
+    out = (C.c_double * 3)()
+    _check(lib().ks_current(h, _ptr(psi), float(t), out))
+    return np.array(out[:])
+
+
+def ks_strength_function(trace, nt, stride, dt, kappa, gamma, omega, out,
+                         stream=None):
+    return _check(lib().ks_strength_function(
+        _ptr(trace), int(nt), int(stride), float(dt), float(kappa),
+        float(gamma), _ptr(omega), int(omega.numel()), _ptr(out),
+        _stream_handle(stream)))
+
+
+def ks_conductivity(trace, nt, stride, dt, E0, gamma, omega, out,
+                    stream=None):
+    return _check(lib().ks_conductivity(
+        _ptr(trace), int(nt), int(stride), float(dt), float(E0),
+        float(gamma), _ptr(omega), int(omega.numel()), _ptr(out),
+        _stream_handle(stream)))
+
+
+def _trace_view(trace, component):
+    """(tensor, samples, stride) for a 1-D trace or one column of an
+    (nt, k) trace (the column view's data pointer is offset to it)."""
+    import torch
+    if not (isinstance(trace, torch.Tensor) and trace.is_cuda and
+            trace.dtype == torch.float64):
+        raise TypeError("trace must be a float64 tensor on the GPU")
+    if trace.dim() == 1:
+        return trace, trace.numel(), 1
+    if trace.dim() == 2 and trace.is_contiguous():
+        return trace[:, component], trace.shape[0], trace.shape[1]
+    raise ValueError("trace must be 1-D or a contiguous (nt, k) array")
+
+
+def strength_function(trace, dt, kappa, gamma, omega, component=2):
+    """S(w) of a kicked run from a device dipole trace ((nt, 3) as
+    propagate_etrs returns it, or 1-D); omega: device float64 tensor."""
+    import torch
+    _dev(omega, torch.float64, None, "omega")
+    col, nt, stride = _trace_view(trace, component)
+    out = torch.empty_like(omega)
+    ks_strength_function(col, nt, stride, dt, kappa, gamma, omega, out)
+    return out
+
+
+def conductivity(trace, dt, E0, gamma, omega, component=0):
+    """sigma(w) (complex128 device tensor) from a device current trace."""
+    import torch
+    _dev(omega, torch.float64, None, "omega")
+    col, nt, stride = _trace_view(trace, component)
+    out = torch.empty(omega.numel(), dtype=torch.complex128,
+                      device=omega.device)
+    ks_conductivity(col, nt, stride, dt, E0, gamma, omega, out)
+    return out
 
 
 def ks_density(h, psi, rho):
@@ -401,6 +468,23 @@ class Grid:
         if rho is not None:
             _dev(rho, self.torch.float64, self.N, "rho")
         ks_update_vlocal(self.h, vion, rho)
+
+    def current(self, psi, t=0.0):
+        """Macroscopic current J(t) of the states (3 values, host)."""
+        self._psi(psi)
+        return ks_current(self.h, psi, float(t))
+
+    def current_trace(self, psi, vion, nsteps, dt, t0=0.0,
+                      method="etrs"):
+        """Propagate psi in place by nsteps steps, recording J(t_n) before
+        the first and after every step: an (nsteps+1, 3) host array."""
+        prop = getattr(self, "propagate_" + method)
+        out = np.zeros((nsteps + 1, 3))
+        out[0] = self.current(psi, t0)
+        for n in range(nsteps):
+            prop(psi, vion, 1, dt, t0 + n * dt, dipole=False, norms=False)
+            out[n + 1] = self.current(psi, t0 + (n + 1) * dt)
+        return out
 
     def hartree(self, rho, out=None):
         """Hartree potential v_H[rho] (FP64, N values on the device)."""
