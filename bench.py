@@ -11,8 +11,9 @@ Prints one JSON line with the FP64 rate, the roofline of the dominant kernel
 (the H.psi stencil, timed live with HIP events on its stream, beside a plain
 device copy timed in the same run), the CPU oracle timed on the host on a
 bounded sample, the FP32-mixed form, the CFM4 propagator and the step with
-the Hartree term on the same workload, and the serving mix (continuous
-batching of propagation requests) in both precisions.
+the Hartree term, the macroscopic current and the strength function on the
+same workload, and the serving mix (continuous batching of propagation
+requests) in both precisions.
 """
 from __future__ import annotations
 
@@ -235,6 +236,48 @@ def run_hartree(w, torch, steps, warmup, tune, reps=50):
     return res
 
 
+def run_observables(w, torch, dip, reps=20):
+    """The macroscopic current of the workload's states (kernel time from
+    the grid's events, and per call with the host sums) and the strength
+    function of the benchmark's own dipole trace on 2000 frequencies."""
+    from paper_1912_07921_amd import ks
+    g = ks.Grid(w.spec)
+    psi = torch.from_numpy(w.psi0).cuda()
+    g.current(psi, 0.0)
+    torch.cuda.synchronize()
+    g.profile_begin(4 * reps + 16, classes=("reduce",))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        J = g.current(psi, 0.0)
+    wall = (time.perf_counter() - t0) / reps
+    prof = g.profile_end()
+    ms, n = prof["reduce"]
+    N, S = w.spec.npoints, w.spec.nk * w.spec.nstates
+    kern_us = 1e3 * ms / max(n, 1)
+    res = dict(current_kernel_us=round(kern_us, 2),
+               current_call_us=round(1e6 * wall, 2),
+               current_states_GBs=round(16.0 * N * S / (kern_us * 1e-6) /
+                                        1e9, 1),
+               current_sample=[float(x) for x in J])
+    if dip is not None:
+        d = torch.from_numpy(np.ascontiguousarray(dip)).cuda()
+        om = torch.linspace(0.0, 2.0, 2000, dtype=torch.float64,
+                            device="cuda")
+        ks.strength_function(d, w.dt, w.kick or 1.0, 0.1, om)
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            ks.strength_function(d, w.dt, w.kick or 1.0, 0.1, om)
+        e1.record(st)
+        torch.cuda.synchronize()
+        res["spectrum_us"] = round(1e3 * e0.elapsed_time(e1) / reps, 2)
+        res["spectrum_samples_x_freqs"] = [int(d.shape[0]), 2000]
+    return res
+
+
 def serving_requests(torch, nreq, steps, rate):
     """The serving mix: request inputs built on the GPU, then held in pinned
     host memory as the payload each request brings (copied to HBM on
@@ -342,6 +385,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cfm4", action="store_true")
     ap.add_argument("--no-hartree", action="store_true")
+    ap.add_argument("--no-observables", action="store_true")
     ap.add_argument("--hartree-only", action="store_true",
                     help="only the step with the Hartree term and the solve "
                          "alone (profiling runs)")
@@ -490,6 +534,10 @@ def main():
         hr["fp64"]["step_cost_vs_no_hartree"] = round(
             hr["fp64"]["ms_per_step"] / out["ms_per_step"], 4)
         out["hartree"] = hr
+
+    if not args.no_observables:
+        log("observables: current and strength function")
+        out["observables"] = run_observables(w, torch, dip64)
 
     if not args.no_serving:
         out["serving"] = run_serving(torch, args.serving_requests,
