@@ -102,6 +102,9 @@ def test_strength_function_and_conductivity_match_oracle(torch_cuda,
     want = oracle_mod.strength_function(d.cpu().numpy()[:, 2], w.dt, 0.01,
                                         0.1, om.cpu().numpy())
     assert np.abs(S - want).max() < 1e-12 * np.abs(want).max()
+    # a 1-D trace (stride 1) gives the same as the column of the (nt, 3) one
+    S1 = ks.strength_function(d[:, 2].contiguous(), w.dt, 0.01, 0.1, om)
+    assert np.array_equal(S1.cpu().numpy(), S)
     t = w.dt * np.arange(400)
     J = 0.1 * np.exp(-0.3 * t) * np.cos(0.7 * t)
     Jt = dev(torch, np.stack([J, -J, 2 * J], axis=1))
