@@ -181,17 +181,19 @@ def hartree_pipeline_bytes(spec):
     """HBM bytes one Hartree solve moves through its five passes (x forward
     from the density, y forward, z forward * K * inverse, y inverse, x
     inverse into the potential): the work array holds nz planes of
-    My x Mx complex values, K an octant of real values."""
+    My x (Mx/2 + 1) complex values (the half spectrum of the real density
+    along x), K an octant of real values."""
     nx, ny, nz = spec.n
     per = all(spec.periodic)
     Mx, My, Mz = (fft_length(n, per) for n in spec.n)
+    Mh = Mx // 2 + 1
     c = 16
-    xf = nx * ny * nz * 8 + ny * nz * Mx * c
-    yf = Mx * nz * ny * c + Mx * nz * My * c
-    zc = 2 * Mx * My * nz * c + (Mx // 2 + 1) * (My // 2 + 1) * \
+    xf = nx * ny * nz * 8 + ny * nz * Mh * c
+    yf = Mh * nz * ny * c + Mh * nz * My * c
+    zc = 2 * Mh * My * nz * c + (Mx // 2 + 1) * (My // 2 + 1) * \
         (Mz // 2 + 1) * 8
-    yi = Mx * nz * My * c + Mx * nz * ny * c
-    xi = ny * nz * Mx * c + nx * ny * nz * 8
+    yi = Mh * nz * My * c + Mh * nz * ny * c
+    xi = ny * nz * Mh * c + nx * ny * nz * 8
     return xf + yf + zc + yi + xi, (Mx, My, Mz)
 
 

@@ -36,7 +36,7 @@ struct PoissonPlan {
     FftAxis ax[3];
     double2 *tw[3] = {nullptr, nullptr, nullptr};
     double *K = nullptr;
-    // work array of one solve: [nz][My][Mx] complex
+    // work array of one solve: [nz][My][Mx/2 + 1] complex
     size_t work_elems = 0;
 };
 

@@ -10,12 +10,15 @@
 //  - Periodic grid: K = 4 pi / |G|^2 / (Mx My Mz), G = 2 pi k / L, K(0) = 0
 //    (uniform compensating background).
 //
-// One solve is five launches over a work array of nz planes of My x Mx
-// complex values: x forward (the density rows, zero padded), y forward (only
+// One solve is five launches over a work array of nz planes of My x
+// (Mx/2 + 1) complex values (the density is real, so along x only the half
+// spectrum k <= Mx/2 is kept): x forward (two density rows per complex
+// line, zero padded, split into the rows' half spectra), y forward (only
 // the nz planes that hold density), z forward + product with K + z inverse
 // in one launch (lines of the z axis; only z < nz is read or written back),
-// y inverse (keeping y < ny), x inverse (keeping x < nx, real part into v).
-// Lines that would transform zeros are never touched.
+// y inverse (keeping y < ny), x inverse (two rows per line rebuilt from
+// their half spectra; the real and imaginary parts are the two rows of v,
+// x < nx).  Lines that would transform zeros are never touched.
 //
 // Each 1D transform is a mixed-radix Stockham FFT (radices 16, 8, 4, 2, 3,
 // 5; the 8- and 16-point butterflies are computed in registers from 2- and
@@ -38,16 +41,25 @@ namespace {
 
 constexpr int kFftThreads = 256;
 
-enum InKind : int { kFromWork = 0, kFromDensity = 1, kFromGreen = 2 };
-enum OutKind : int { kToWork = 0, kToPotential = 1, kToPotentialAdd = 2 };
+// Paired kinds work on two real rows per complex line (rows 2l and 2l + 1
+// of the density / potential, the second one absent past the last row):
+// kFromDensityPair loads rho_a + i rho_b; kToWorkUnpack splits the
+// transform into the two rows' half spectra (k <= M/2, by Hermitian
+// symmetry); kFromWorkPair rebuilds the full spectrum of X_a + i X_b from
+// the two half spectra; kToPotentialPair writes Re to row a, Im to row b.
+enum InKind : int { kFromWork = 0, kFromDensityPair = 1, kFromGreen = 2,
+                    kFromWorkPair = 3 };
+enum OutKind : int { kToWork = 0, kToPotentialPair = 1,
+                     kToPotentialPairAdd = 2, kToWorkUnpack = 3 };
 enum Op : int { kForward = 0, kInverse = 1, kConvolve = 2 };
 
 // One launch: lines l = a + la * b (l < nlines) of the work array, line
-// element i at a * sa + b * sb + i * sp.  Density / potential rows (x
-// passes) are rows l of length nrow.
+// element i at a * sa + b * sb + i * sp.  In the paired x passes line l
+// holds rows r = 2l and 2l + 1 (r < nrows) of the density / potential
+// (length nrow each), whose work rows sit at (r % la) * sa + (r / la) * sb.
 struct LinePass {
     FftAxis ax;
-    int nlines = 0, la = 1;
+    int nlines = 0, la = 1, nrows = 0;
     long sa = 0, sb = 0, sp = 1;
     int nin = 0, nout = 0;          // points read (rest zero) / written
     int in_kind = kFromWork, out_kind = kToWork, op = kForward;
@@ -289,7 +301,9 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(LinePass p)
 {
     extern __shared__ double2 lds[];
     __shared__ long lbase[NL];     // work-array offset of each line
+    __shared__ long lbase1[NL];    // paired: offset of the second row
     __shared__ int lcoord[NL][2];  // its (a, b); a < 0: past the last line
+    __shared__ int lpair[NL];      // paired: the second row exists
     constexpr int PS = NL + 1;
     const int M = p.ax.M;
     double2 *A = lds, *B = lds + (size_t)M * PS;
@@ -298,12 +312,23 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(LinePass p)
     const bool rows = p.sp == 1;   // whole contiguous lines (x axis)
     for (int m = threadIdx.x; m < M; m += kFftThreads)
         tw[m] = p.ax.tw[m];
+    const bool paired = p.in_kind == kFromDensityPair ||
+                        p.in_kind == kFromWorkPair;
     if (threadIdx.x < NL) {
         const int l = l0 + threadIdx.x;
-        const int a = l % p.la, b = l / p.la;
-        lbase[threadIdx.x] = a * p.sa + b * p.sb;
-        lcoord[threadIdx.x][0] = l < p.nlines ? a : -1;
-        lcoord[threadIdx.x][1] = b;
+        if (paired) {
+            const int r0 = 2 * l, r1 = 2 * l + 1;
+            lbase[threadIdx.x] = (r0 % p.la) * p.sa + (r0 / p.la) * p.sb;
+            lbase1[threadIdx.x] = (r1 % p.la) * p.sa + (r1 / p.la) * p.sb;
+            lpair[threadIdx.x] = r1 < p.nrows;
+            lcoord[threadIdx.x][0] = l < p.nlines ? 0 : -1;
+            lcoord[threadIdx.x][1] = 0;
+        } else {
+            const int a = l % p.la, b = l / p.la;
+            lbase[threadIdx.x] = a * p.sa + b * p.sb;
+            lcoord[threadIdx.x][0] = l < p.nlines ? a : -1;
+            lcoord[threadIdx.x][1] = b;
+        }
     }
     __syncthreads();
     Points q;
@@ -315,12 +340,26 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(LinePass p)
             val[n] = cmk<double2>(0.0, 0.0);
             const int i = q.i[n], li = q.li[n];
             if (q.ok[n] && i < p.nin && lcoord[li][0] >= 0) {
-                if (p.in_kind == kFromWork)
+                const long r0 = 2L * (l0 + li);
+                if (p.in_kind == kFromWork) {
                     val[n] = p.work[lbase[li] + i * p.sp];
-                else if (p.in_kind == kFromDensity)
-                    val[n].x = p.rho[(long)(l0 + li) * p.nrow + i];
-                else
+                } else if (p.in_kind == kFromDensityPair) {
+                    val[n].x = p.rho[r0 * p.nrow + i];
+                    if (lpair[li])
+                        val[n].y = p.rho[(r0 + 1) * p.nrow + i];
+                } else if (p.in_kind == kFromWorkPair) {
+                    // Z_i = X_a,i + i X_b,i; past the half spectrum from
+                    // X_{M-i} = conj(X_i) of each real row
+                    const int h = M / 2 + 1;
+                    const int m = i < h ? i : M - i;
+                    const double2 xa = p.work[lbase[li] + m];
+                    const double2 xb = lpair[li] ? p.work[lbase1[li] + m]
+                                                 : cmk<double2>(0.0, 0.0);
+                    val[n] = i < h ? cmk<double2>(xa.x - xb.y, xa.y + xb.x)
+                                   : cmk<double2>(xa.x + xb.y, xb.x - xa.y);
+                } else {
                     val[n].x = green(p, i, lcoord[li][0], lcoord[li][1]);
+                }
             }
         }
 #pragma unroll
@@ -352,12 +391,28 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(LinePass p)
         const int i = q.i[n], li = q.li[n];
         if (q.ok[n] && i < p.nout && lcoord[li][0] >= 0) {
             const double2 val = R[i * PS + li];
-            if (p.out_kind == kToWork)
+            const long r0 = 2L * (l0 + li);
+            if (p.out_kind == kToWork) {
                 p.work[lbase[li] + i * p.sp] = val;
-            else if (p.out_kind == kToPotential)
-                p.v[(long)(l0 + li) * p.nrow + i] = val.x;
-            else
-                p.v[(long)(l0 + li) * p.nrow + i] += val.x;
+            } else if (p.out_kind == kToWorkUnpack) {
+                // the two real rows' spectra: (Z_i + conj Z_{M-i}) / 2 and
+                // (Z_i - conj Z_{M-i}) / (2i)
+                const double2 zm = R[((M - i) % M) * PS + li];
+                p.work[lbase[li] + i] = cmk<double2>(0.5 * (val.x + zm.x),
+                                                     0.5 * (val.y - zm.y));
+                if (lpair[li])
+                    p.work[lbase1[li] + i] =
+                        cmk<double2>(0.5 * (val.y + zm.y),
+                                     0.5 * (zm.x - val.x));
+            } else if (p.out_kind == kToPotentialPair) {
+                p.v[r0 * p.nrow + i] = val.x;
+                if (lpair[li])
+                    p.v[(r0 + 1) * p.nrow + i] = val.y;
+            } else {
+                p.v[r0 * p.nrow + i] += val.x;
+                if (lpair[li])
+                    p.v[(r0 + 1) * p.nrow + i] += val.y;
+            }
         }
     }
 }
@@ -542,7 +597,7 @@ hipError_t poisson_plan_create(const Geo &g, bool periodic, PoissonPlan *pp,
     e = hipMalloc(&pp->K, sizeof(double) * nK);
     if (e != hipSuccess)
         return e;
-    pp->work_elems = (size_t)g.nz * My * Mx;
+    pp->work_elems = (size_t)g.nz * My * (Mx / 2 + 1);
     const double vol = (double)Mx * My * Mz;
     const int nb = (int)((nK + 255) / 256);
     if (periodic) {
@@ -619,47 +674,52 @@ hipError_t launch_hartree(const PoissonPlan &pp, const Geo &g,
                           const double *rho, double *v, bool add,
                           double2 *work, hipStream_t st)
 {
-    const int Mx = pp.ax[0].M, My = pp.ax[1].M, Mz = pp.ax[2].M;
-    const long plane = (long)Mx * My;
+    const int Mx = pp.ax[0].M, My = pp.ax[1].M;
+    const int Mh = Mx / 2 + 1;                 // half spectrum along x
+    const long plane = (long)Mh * My;
+    const int nrows = g.ny * g.nz;
     hipError_t e;
     LinePass p;
     p.work = work;
     p.rho = rho;
     p.v = v;
     p.nrow = g.nx;
-    // x forward: density rows (y < ny, z < nz), zero padded to Mx
+    // x forward: density rows (y < ny, z < nz) two at a time, zero padded
+    // to Mx, split into the two rows' half spectra
     p.ax = pp.ax[0];
-    p.nlines = g.ny * g.nz;
+    p.nlines = (nrows + 1) / 2;
+    p.nrows = nrows;
     p.la = g.ny;
-    p.sa = Mx;
+    p.sa = Mh;
     p.sb = plane;
     p.sp = 1;
     p.nin = g.nx;
-    p.nout = Mx;
-    p.in_kind = kFromDensity;
-    p.out_kind = kToWork;
+    p.nout = Mh;
+    p.in_kind = kFromDensityPair;
+    p.out_kind = kToWorkUnpack;
     p.op = kForward;
     if ((e = run_pass(p, st)) != hipSuccess)
         return e;
-    // y forward: lines (x < Mx, z < nz), rows y >= ny are zero
+    // y forward: lines (x < Mh, z < nz), rows y >= ny are zero
     p.ax = pp.ax[1];
-    p.nlines = Mx * g.nz;
-    p.la = Mx;
+    p.nlines = Mh * g.nz;
+    p.la = Mh;
     p.sa = 1;
     p.sb = plane;
-    p.sp = Mx;
+    p.sp = Mh;
     p.nin = g.ny;
     p.nout = My;
     p.in_kind = kFromWork;
+    p.out_kind = kToWork;
     if ((e = run_pass(p, st)) != hipSuccess)
         return e;
     // z: forward, times K, inverse; planes z >= nz are zero on input and
     // not needed on output
     p.ax = pp.ax[2];
-    p.nlines = Mx * My;
-    p.la = Mx;
+    p.nlines = Mh * My;
+    p.la = Mh;
     p.sa = 1;
-    p.sb = Mx;
+    p.sb = Mh;
     p.sp = plane;
     p.nin = p.nout = g.nz;
     p.op = kConvolve;
@@ -670,26 +730,29 @@ hipError_t launch_hartree(const PoissonPlan &pp, const Geo &g,
         return e;
     // y inverse, keeping y < ny
     p.ax = pp.ax[1];
-    p.nlines = Mx * g.nz;
-    p.la = Mx;
+    p.nlines = Mh * g.nz;
+    p.la = Mh;
     p.sa = 1;
     p.sb = plane;
-    p.sp = Mx;
+    p.sp = Mh;
     p.nin = My;
     p.nout = g.ny;
     p.op = kInverse;
     if ((e = run_pass(p, st)) != hipSuccess)
         return e;
-    // x inverse, keeping x < nx; the real part is the potential
+    // x inverse, two rows at a time from their half spectra, keeping
+    // x < nx: the real part is row a, the imaginary part row b
     p.ax = pp.ax[0];
-    p.nlines = g.ny * g.nz;
+    p.nlines = (nrows + 1) / 2;
+    p.nrows = nrows;
     p.la = g.ny;
-    p.sa = Mx;
+    p.sa = Mh;
     p.sb = plane;
     p.sp = 1;
     p.nin = Mx;
     p.nout = g.nx;
-    p.out_kind = add ? kToPotentialAdd : kToPotential;
+    p.in_kind = kFromWorkPair;
+    p.out_kind = add ? kToPotentialPairAdd : kToPotentialPair;
     return run_pass(p, st);
 }
 
