@@ -436,7 +436,7 @@ void layout(ks_grid *g)
     g->lay.veff = take(N * 8);
     g->lay.pwork = take(g->hartree ? g->pp.work_elems * 16 : 0);
     g->lay.vh = take(g->hartree ? N * 8 : 0);
-    g->lay.cpart = take(S * current_chunks((long)N) * 3 * 8);
+    g->lay.cpart = take(S * (size_t)g->geo.ny * g->geo.nz * 3 * 8);
     g->lay.cnl = take(S * std::max(1, g->natoms) * 3 * 8);
     g->lay.total = off;
 }
@@ -953,25 +953,52 @@ int ks_current(ks_grid *g, const void *d_psi, double t, double out_host[3])
     int rc = need_ws(g);
     if (rc)
         return rc;
+    // stencil part: the H.psi kernel's tiles (one row per thread, the
+    // tallest tile within 512 threads and the default LDS share), each
+    // writing its three partial sums
+    const Geo &G = g->geo;
+    int TY = std::max(1, std::min(G.ny, kRowThreads / G.nx));
+    while (TY > 1 && (!tile_ok(g, TY, 1) ||
+                      hpsi_lds_bytes(G.nx, TY, g->zchunk, false) >
+                          kLdsDefault))
+        --TY;
+    if (!tile_ok(g, TY, 1))
+        return fail(KS_E_UNSUPPORTED, "no tile shape for the current");
+    HArgs h = base_hargs(g);
+    h.rowinfo = nullptr;
+    h.W = nullptr;
+    h.in = d_psi;
+    h.TY = TY;
+    h.rpt = 1;
+    h.ntile_y = (G.ny + TY - 1) / TY;
+    h.nzc = (G.nz + g->zchunk - 1) / g->zchunk;
+    h.sg0 = 0;
+    double A[3];
+    laser_A(g, t, A);
+    for (int d = 0; d < 3; ++d)
+        h.A[d] = A[d];
+    h.normpart = wsp<double>(g, g->lay.cpart);
+    // projector part
     CurArgs a;
     a.geo = g->geo;
     a.psi = static_cast<const double2 *>(d_psi);
     a.kph = g->d_kph;
     a.nstates = g->ns;
     a.sg0 = 0;
-    laser_A(g, t, a.A);
+    for (int d = 0; d < 3; ++d)
+        a.A[d] = A[d];
     a.pj = g->pj;
-    a.part = wsp<double>(g, g->lay.cpart);
     a.nl = wsp<double>(g, g->lay.cnl);
     {
         Timed tm(g, 2);
-        KS_HIP(launch_current(a, g->stot, g->stream));
+        KS_HIP(launch_hpsi_current(h, g->stot, g->stream));
+        KS_HIP(launch_current_nl(a, g->stot, g->stream));
     }
-    const int nch = current_chunks(g->geo.N);
+    const int nch = h.ntile_y * h.nzc;
     const int na = g->natoms;
     std::vector<double> hp((size_t)g->stot * nch * 3);
     std::vector<double> hn((size_t)g->stot * std::max(1, na) * 3, 0.0);
-    KS_HIP(hipMemcpyAsync(hp.data(), a.part, hp.size() * sizeof(double),
+    KS_HIP(hipMemcpyAsync(hp.data(), h.normpart, hp.size() * sizeof(double),
                           hipMemcpyDeviceToHost, g->stream));
     if (na > 0)
         KS_HIP(hipMemcpyAsync(hn.data(), a.nl,

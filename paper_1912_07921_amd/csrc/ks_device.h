@@ -381,7 +381,7 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
     int4 *sRow = reinterpret_cast<int4 *>(sPz + 9);   // hull rows of tile
 
     const InT *in = reinterpret_cast<const InT *>(a.in) + (size_t)sl * N;
-    const bool proj = a.rowinfo != nullptr;
+    const bool proj = MODE != kCurrent && a.rowinfo != nullptr;
     const V *Wst = reinterpret_cast<const V *>(a.W) + (size_t)sl * a.nhull;
 
     // ---- Bloch phases of x/y wraps by -4..4 cells: sPh[(wy+4)*9 + wx+4],
@@ -498,6 +498,8 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
         return v;
     };
     auto v_val = [&](int r, int zq) -> double {
+        if constexpr (MODE == kCurrent)
+            return 0.0;   // the local potential commutes with r
         return act[r] ? gp(a.v)[(long)zq * P + po[r]] : 0.0;
     };
 
@@ -549,6 +551,7 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
     const double w_occ = (MODE == kFinal || MODE == kFinalPred)
                              ? gp(a.wocc)[sg] : 0.0;
     double nrm = 0.0;
+    double jc[3] = {0.0, 0.0, 0.0};   // kCurrent: Im(conj psi [H, r_a] psi)
     V *cur = buf0, *nxt = buf1;
     for (int z = z0; z < z1; ++z) {
         const bool more2 = z + 2 < z1;
@@ -576,6 +579,7 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
             const V *rp = cur + own[r];
             V sx = czero<V>(), sy = czero<V>(), sz = czero<V>();
             V gx = czero<V>(), gy = czero<V>(), gz = czero<V>();
+            V ux = czero<V>(), uy = czero<V>(), uz = czero<V>();
 #pragma unroll
             for (int m = 1; m <= kHalf; ++m) {
                 const V xp = rp[m], xn = rp[-m];
@@ -589,6 +593,30 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
                     gy = cadd(gy, cscale(csub(yp, yn), GD[m]));
                     gz = cadd(gz, cscale(csub(zp, zn), GD[m]));
                 }
+                if constexpr (MODE == kCurrent) {
+                    // taps of the gauge term weighted by their
+                    // displacement: sum m d_m (psi_+m + psi_-m)
+                    const R wm = (R)m * GD[m];
+                    ux = cadd(ux, cscale(cadd(xp, xn), wm));
+                    uy = cadd(uy, cscale(cadd(yp, yn), wm));
+                    uz = cadd(uz, cscale(cadd(zp, zn), wm));
+                }
+            }
+            if constexpr (MODE == kCurrent) {
+                // [H, r_a] psi = -grad_a psi - i A_a sum m d_m (psi_+ +
+                // psi_-): the kinetic taps -c_m/(2h^2) at displacement m h
+                // give -d_m/h (m c_m = 2 d_m for these weights)
+                const V gg[3] = {gx, gy, gz}, uu[3] = {ux, uy, uz};
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    const double ih = 1.0 / a.geo.h[ax];
+                    const double A = ax == 0 ? Avec.x
+                                             : (ax == 1 ? Avec.y : Avec.z);
+                    const double tx = -gg[ax].x * ih + A * uu[ax].y;
+                    const double ty = -gg[ax].y * ih - A * uu[ax].x;
+                    jc[ax] += c.x * ty - c.y * tx;
+                }
+                continue;
             }
             const long g = (long)z * P + po[r];
             V lap = cadd(cadd(cscale(sx, ih2x), cscale(sy, ih2y)),
@@ -676,6 +704,15 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
         block_sum<double, 1>(vals, reinterpret_cast<double *>(smem_raw));
         if (tid == 0)
             gp(a.normpart)[(size_t)sl * ntiles + tile] = vals[0];
+    }
+    if constexpr (MODE == kCurrent) {
+        __syncthreads();
+        block_sum<double, 3>(jc, reinterpret_cast<double *>(smem_raw));
+        if (tid == 0)
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax)
+                gp(a.normpart)[((size_t)sl * ntiles + tile) * 3 + ax] =
+                    jc[ax];
     }
 }
 

@@ -129,6 +129,37 @@ hipError_t launch_hpsi(int mode, bool mixed, bool in_is_f64, const HArgs &a,
     }
     return hipErrorInvalidValue;
 }
+
+hipError_t launch_hpsi_current(const HArgs &a, int ns, hipStream_t st)
+{
+    if (ns <= 0)
+        return hipSuccess;
+    if (a.rpt != 1)
+        return hipErrorInvalidValue;
+    const int nthr = hpsi_threads(a.geo.nx, a.TY, 1);
+    const size_t lds = hpsi_lds_bytes(a.geo.nx, a.TY, a.zchunk, false);
+    dim3 grid((unsigned)(a.ntile_y * a.nzc * ns));
+    using D2 = double2;
+    switch (hpsi_halo_per_thread(a.geo, a.TY, nthr)) {
+    case 2:
+        hipLaunchKernelGGL((k_hpsi<double, D2, D2, kCurrent, true, 2, 1>),
+                           grid, dim3(nthr), lds, st, a);
+        break;
+    case 4:
+        hipLaunchKernelGGL((k_hpsi<double, D2, D2, kCurrent, true, 4, 1>),
+                           grid, dim3(nthr), lds, st, a);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_hpsi<double, D2, D2, kCurrent, true, 8, 1>),
+                           grid, dim3(nthr), lds, st, a);
+        break;
+    default:
+        hipLaunchKernelGGL((k_hpsi<double, D2, D2, kCurrent, true, 16, 1>),
+                           grid, dim3(nthr), lds, st, a);
+        break;
+    }
+    return hipGetLastError();
+}
 #else
 hipError_t launch_hpsi_mixed(int mode, bool in_is_f64, const HArgs &a, int ns,
                              hipStream_t st)

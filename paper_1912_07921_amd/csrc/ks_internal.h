@@ -18,8 +18,11 @@ enum Mode : int {
     kTerm = 1,       // out = c * H in                           (t-term type)
     kFinal = 2,      // t4 = c * H t3; out = base + t1 + t2 + t3 + t4,
                      // density partials and norms of out        (complex128)
-    kFinalPred = 3   // as kFinal, plus the predictor
+    kFinalPred = 3,  // as kFinal, plus the predictor
                      // base + 2 t1 + 4 t2 + 8 t3 + 16 t4 feeds the density
+    kCurrent = 4     // no output: per tile, sum over its points of
+                     // Im(conj(psi) [H_stencil, r_a] psi), a = x, y, z,
+                     // into normpart[tile][3] (FP64 only)
 };
 
 struct Geo {
@@ -129,6 +132,8 @@ size_t hpsi_lds_bytes(int nx, int TY, int zchunk, bool mixed);
 // Launchers (ks_kernels.hip).  All asynchronous on `st`.
 hipError_t launch_hpsi(int mode, bool mixed, bool in_is_f64, const HArgs &a,
                        int ns, hipStream_t st);
+// The stencil part of the current (mode kCurrent, one row per thread).
+hipError_t launch_hpsi_current(const HArgs &a, int ns, hipStream_t st);
 // KB projectors: D = coefficients of `in` (gather), then W = V_NL in on
 // the hull (apply).  Both no-ops without atoms.
 hipError_t launch_gather(bool mixed, bool in_is_f64, const GArgs &a, int ns,

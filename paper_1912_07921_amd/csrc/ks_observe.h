@@ -17,14 +17,12 @@ struct CurArgs {
     int sg0 = 0;                    // global index of launch state 0
     double A[3] = {0.0, 0.0, 0.0};  // vector potential at the time
     ProjDev pj;
-    // per state: [current_chunks(N)][3] stencil partials (without h^3) and
-    // [natoms][3] projector terms
-    double *part = nullptr;
-    double *nl = nullptr;
+    double *nl = nullptr;           // [ns][natoms][3] projector terms
 };
 
-int current_chunks(long N);
-hipError_t launch_current(const CurArgs &a, int ns, hipStream_t st);
+// Projector part of the current (the stencil part is the H.psi kernel's
+// mode kCurrent).
+hipError_t launch_current_nl(const CurArgs &a, int ns, hipStream_t st);
 
 // mode 0: strength function (scale = kick), mode 1: conductivity (scale =
 // field, out holds nw complex values)

@@ -14,7 +14,10 @@
 //   + 2i h^3 sum_atoms sum_j N_j^2 h^3 E_j Im(conj(C_j) D_ja)   (projectors)
 // with C_j = sum p_j e^{ik.T} psi and D_ja = sum p_j e^{ik.T} (r - R)_a psi
 // over the atom's sphere (p_j without its grid normalisation N_j).  Both
-// parts are imaginary, so J_a = (1/Omega) sum_s w_s Im(...).
+// parts are imaginary, so J_a = (1/Omega) sum_s w_s Im(...).  The stencil
+// part runs in the H.psi kernel (mode kCurrent: its LDS-staged planes give
+// the neighbours, m c_m = 2 d_m turns the kinetic taps into -grad); this
+// file holds the projector part and the transforms.
 #include "ks_observe.h"
 
 #include "ks_device.h"
@@ -23,73 +26,6 @@ namespace ks {
 namespace {
 
 constexpr int kCurThreads = 256;
-
-// psi of state sl at (x, y, z) shifted by m along `axis`, with the boundary
-// rule of the grid: zero outside a non-periodic axis, Bloch phase per wrap.
-__device__ __forceinline__ double2 neighbour(const Geo &G,
-                                             const double2 *__restrict__ psi,
-                                             const double2 *kph, int axis,
-                                             int x, int y, int z, int m)
-{
-    int c[3] = {x, y, z};
-    const int n = axis == 0 ? G.nx : axis == 1 ? G.ny : G.nz;
-    int q = c[axis] + m, w = 0;
-    while (q < 0) {
-        q += n;
-        --w;
-    }
-    while (q >= n) {
-        q -= n;
-        ++w;
-    }
-    if (w != 0 && !G.per[axis])
-        return cmk<double2>(0.0, 0.0);
-    c[axis] = q;
-    double2 v = gld(psi + ((long)c[2] * G.ny + c[1]) * G.nx + c[0]);
-    if (w != 0)
-        v = cmul(v, phase_pow<double2>(kph, axis, w));
-    return v;
-}
-
-// Stencil part: part[(sl * gridDim.x + block) * 3 + a] = sum over the
-// block's points of Im(conj(psi) (stencil [H, r_a] psi)).
-__global__ __launch_bounds__(kCurThreads) void k_current_local(CurArgs a)
-{
-    __shared__ double sbuf[(kCurThreads / 64) * 3];
-    const Geo G = a.geo;
-    const int sl = blockIdx.y;
-    const int kk = (a.sg0 + sl) / a.nstates;
-    const double2 *psi = a.psi + (size_t)sl * G.N;
-    const double2 *kph = a.kph + 3 * kk;
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (long g = (long)blockIdx.x * kCurThreads + threadIdx.x; g < G.N;
-         g += (long)gridDim.x * kCurThreads) {
-        const int x = (int)(g % G.nx), y = (int)((g / G.nx) % G.ny);
-        const int z = (int)(g / ((long)G.nx * G.ny));
-        const double2 c = gld(psi + g);
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            double2 t = cmk<double2>(0.0, 0.0);
-#pragma unroll
-            for (int m = 1; m <= 4; ++m) {
-                const double2 fp = neighbour(G, psi, kph, ax, x, y, z, m);
-                const double2 fm = neighbour(G, psi, kph, ax, x, y, z, -m);
-                // kinetic: -c_m m / (2 h) (fp - fm)
-                t = cadd(t, cscale(csub(fp, fm),
-                                   -0.5 * kLap[m] * m / G.h[ax]));
-                // gauge: -i A m d_m (fp + fm)
-                const double2 s = cscale(cadd(fp, fm), a.A[ax] * m * kGrad[m]);
-                t = cadd(t, cmk<double2>(s.y, -s.x));
-            }
-            // Im(conj(c) t)
-            acc[ax] += c.x * t.y - c.y * t.x;
-        }
-    }
-    block_sum<double, 3>(acc, sbuf);
-    if (threadIdx.x == 0)
-        for (int ax = 0; ax < 3; ++ax)
-            a.part[((size_t)sl * gridDim.x + blockIdx.x) * 3 + ax] = acc[ax];
-}
 
 // Projector part of atom blockIdx.x, state blockIdx.y and axis blockIdx.z:
 // nl[(sl * natoms + at) * 3 + a] = 2 h^3 sum_j N_j^2 h^3 E_j
@@ -210,20 +146,10 @@ __global__ __launch_bounds__(256) void k_damped_ft(const double *f, int nt,
 
 }  // namespace
 
-int current_chunks(long N)
+hipError_t launch_current_nl(const CurArgs &a, int ns, hipStream_t st)
 {
-    return (int)std::min<long>(256, (N + kCurThreads - 1) / kCurThreads);
-}
-
-hipError_t launch_current(const CurArgs &a, int ns, hipStream_t st)
-{
-    if (ns <= 0)
+    if (ns <= 0 || a.pj.natoms == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_current_local, dim3(current_chunks(a.geo.N), ns),
-                       dim3(kCurThreads), 0, st, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || a.pj.natoms == 0)
-        return e;
     hipLaunchKernelGGL(k_current_nl, dim3(a.pj.natoms, ns, 3),
                        dim3(kCurThreads), 0, st, a);
     return hipGetLastError();
