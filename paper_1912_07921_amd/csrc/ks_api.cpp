@@ -1269,13 +1269,18 @@ int ks_autotune(ks_grid *g, const void *d_psi, int reps, int out_shape[3],
     const bool mx = g->mixed;
     // candidate (tile rows, rows per thread): for one and two rows per
     // thread the tallest tile of 512 threads, the one that splits ny evenly
-    // into as many tiles, and 3/4, 1/2 and 1/4 of it
+    // into as many tiles, 3/4, 1/2 and 1/4 of it, and the tallest tile (and
+    // its half) whose thread rows fill whole wavefronts
     std::vector<std::pair<int, int>> shapes;
     for (int rpt = 1; rpt <= 2; ++rpt) {
         const int m = std::max(1, std::min(G.ny, rpt * kRowThreads / G.nx));
         const int nt = (G.ny + m - 1) / m;
+        int full = 0;
+        for (int ty = m; ty >= rpt && !full; --ty)
+            if ((G.nx * ((ty + rpt - 1) / rpt)) % 64 == 0)
+                full = ty;
         for (int ty : {m, m - 1, (m * 3) / 4, m / 2, m / 4,
-                       (G.ny + nt - 1) / nt})
+                       (G.ny + nt - 1) / nt, full, full / 2})
             if (ty >= rpt)
                 shapes.push_back({ty, rpt});
     }
@@ -1316,6 +1321,13 @@ int ks_autotune(ks_grid *g, const void *d_psi, int reps, int out_shape[3],
         HArgs a = base_hargs(g);
         a.v = g->d_v;
         a.cre = 0.0;
+        // a grid with a laser runs the passes with the gradient term: time
+        // that kernel, at the pulse's amplitude
+        if (g->laser[0] != 0.0) {
+            for (int d = 0; d < 3; ++d)
+                a.A[d] = g->laser[0] * g->laser[3 + d];
+            a.a2half = half_a2(a.A);
+        }
         auto expo = [&]() -> int {
             void *tb[3] = {g->ws + g->lay.t1, g->ws + g->lay.t2,
                            g->ws + g->lay.t3};
