@@ -417,12 +417,15 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_lines(LinePass p)
     }
 }
 
-// Lines per workgroup: both LDS buffers and the twiddles within 96 KiB and
-// at most kMaxPts points per thread.  (Fewer lines per group leave most of
-// the 256 threads idle in the 16-point stages; measured slower.)
-int lines_per_group(int M)
+// Lines per workgroup: both LDS buffers and the twiddles within 96 KiB, at
+// most kMaxPts points per thread, and, down to 8 lines, at least one
+// workgroup per CU.  (Groups of 4 lines leave most of the 256 threads idle
+// in the 16-point stages; measured slower.)
+int lines_per_group(int M, int nlines)
 {
     int nl = 32;
+    while (nl > 8 && (nlines + nl - 1) / nl < 256)
+        nl /= 2;
     while (nl > 2 && ((2 * (size_t)M * (nl + 1) + M) * sizeof(double2) >
                           98304 ||
                       nl * M > kFftThreads * kMaxPts))
@@ -434,7 +437,7 @@ hipError_t run_pass(const LinePass &p, hipStream_t st)
 {
     if (p.nlines <= 0)
         return hipSuccess;
-    const int nl = lines_per_group(p.ax.M);
+    const int nl = lines_per_group(p.ax.M, p.nlines);
     if (nl * p.ax.M > kFftThreads * kMaxPts)
         return hipErrorInvalidValue;   // more points than a thread holds
     // two line buffers and the twiddle table
