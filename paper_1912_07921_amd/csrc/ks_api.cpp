@@ -428,6 +428,15 @@ void layout(ks_grid *g)
     g->lay.rho = take(N * 8);
     g->lay.vpred = take(N * 8);
     g->lay.dpart = take(ndb * 3 * 8);
+    // Gram: split the grid so that about 2048 workgroups share the work
+    // (32 x 32 state tiles per k-point), each slice at least 512 points
+    {
+        const long tiles = (long)((g->ns + 31) / 32) * ((g->ns + 31) / 32) *
+                           g->nk;
+        const long want = std::max<long>(1, (2048 + tiles - 1) / tiles);
+        const long most = std::max<long>(1, (long)N / 512);
+        g->gram_ksplit = (int)std::max<long>(1, std::min(want, most));
+    }
     g->lay.gpart = take((size_t)g->gram_ksplit * g->nk * g->ns * g->ns * 16);
     g->lay.dotpart = take(S * g->norm_chunks * 16);
     g->lay.xpart = take(ndb * 8);
