@@ -37,6 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # passes: 3 x (read t_{j-1}, write t_j) + (read t3, psi, t1, t2; write the
 # sum), twice): FP64 16-byte terms / mixed 8-byte terms with 16-byte psi
 STEP_BYTES = {0: 352.0, 1: 224.0}
+# the timed steps carry events around one H.psi launch in this many (prime
+# to the 8 passes of a step)
+HPSI_SAMPLE = 7
 METRIC = ("H·ψ grid-point·states/s + HBM GB/s frac; serving p50/p99 step, "
           "FP32-mix vs FP64")
 
@@ -141,9 +144,11 @@ def run_gpu(w, precision, steps, warmup, torch, tune=True, shape=None,
     st = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    # events around the H.psi launches only (events around every launch
-    # would cost ~20 % of the step; these cost ~6 %)
-    g.profile_begin(64 * steps + 64, classes=("hpsi",))
+    # events around one H.psi launch in seven (seven is prime to the eight
+    # passes of a step, so every pass type is sampled alike): events around
+    # every launch cost ~6 % of the step, around every launch of every
+    # class ~20 %
+    g.profile_begin(64 * steps + 64, classes=("hpsi",), every=HPSI_SAMPLE)
     e0.record(st)
     d, n = prop(psi, vion, steps, w.dt, t0=warmup * w.dt,
                 dipole=not periodic, norms=True)
@@ -153,7 +158,7 @@ def run_gpu(w, precision, steps, warmup, torch, tune=True, shape=None,
     sec = e0.elapsed_time(e1) / 1e3
     dip = d.cpu().numpy() if d is not None else None
     # per-class kernel times over a few more steps (all classes timed)
-    g.profile_begin(4096)
+    g.profile_begin(4096, every=1)
     prop(psi, vion, 10, w.dt, t0=(warmup + steps) * w.dt,
          dipole=not periodic, norms=True)
     prof_all = g.profile_end()

@@ -284,6 +284,11 @@ int ks_get_launch(const ks_grid *g, int out[5]);
 int ks_profile_begin(ks_grid *g, int capacity, int class_mask);
 int ks_profile_end(ks_grid *g, double out_ms[4], long out_count[4]);
 
+/* Time only every `every`-th launch of each class (counted from
+ * ks_profile_begin; default 1 = all), so that a long run is sampled with
+ * few events.  Takes effect at the next ks_profile_begin. */
+int ks_profile_every(ks_grid *g, int every);
+
 /* Autotuner: time the four H.psi passes of one Taylor exponential (the
  * three term passes and the final sum, the mix a step runs; projector
  * terms included as they are) on the caller's states `d_psi`

@@ -95,6 +95,8 @@ struct ks_grid {
     int ev_used = 0;
     bool profiling = false;
     int prof_mask = 0xf;
+    int prof_every = 1;          // time one launch in prof_every per class
+    long prof_seen[4] = {0, 0, 0, 0};
     // second stream: the states are propagated in two halves whose pass
     // chains overlap (one half's projector kernels beside the other half's
     // stencil)
@@ -484,6 +486,7 @@ struct Timed {
     Timed(ks_grid *gg, int c) : g(gg)
     {
         if (g->profiling && ((g->prof_mask >> c) & 1) &&
+            g->prof_seen[c]++ % g->prof_every == 0 &&
             g->ev_used < (int)g->ev_class.size()) {
             slot = g->ev_used++;
             g->ev_class[slot] = c;
@@ -1431,7 +1434,17 @@ int ks_profile_begin(ks_grid *g, int capacity, int class_mask)
         g->ev_class.push_back(0);
     }
     g->ev_used = 0;
+    for (int c = 0; c < 4; ++c)
+        g->prof_seen[c] = 0;
     g->profiling = true;
+    return KS_OK;
+}
+
+int ks_profile_every(ks_grid *g, int every)
+{
+    if (!g || every < 1)
+        return fail(KS_E_ARG, "grid is NULL or every < 1");
+    g->prof_every = every;
     return KS_OK;
 }
 

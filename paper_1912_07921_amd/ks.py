@@ -107,6 +107,7 @@ EXPORTS = {
     "ks_profile_begin": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "ks_profile_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
                                  C.POINTER(C.c_long)]),
+    "ks_profile_every": (C.c_int, [C.c_void_p, C.c_int]),
     "ks_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int,
                               C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "ks_batch_create": (C.c_int, [C.POINTER(ks_job), C.c_int, C.c_void_p,
@@ -359,6 +360,10 @@ def ks_profile_begin(h, capacity, classes=PROFILE_CLASSES):
     return _check(lib().ks_profile_begin(h, int(capacity), mask))
 
 
+def ks_profile_every(h, every):
+    return _check(lib().ks_profile_every(h, int(every)))
+
+
 def ks_profile_end(h):
     """{class: (total_ms, launches)} for classes hpsi, gather, reduce,
     kbapply."""
@@ -587,7 +592,11 @@ class Grid:
         self._psi(psi)
         return ks_autotune(self.h, psi, reps)
 
-    def profile_begin(self, capacity=100000, classes=PROFILE_CLASSES):
+    def profile_begin(self, capacity=100000, classes=PROFILE_CLASSES,
+                      every=1):
+        """Start event timing of the given kernel classes, one launch in
+        `every` of each."""
+        ks_profile_every(self.h, every)
         ks_profile_begin(self.h, capacity, classes)
 
     def profile_end(self):
