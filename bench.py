@@ -411,7 +411,8 @@ def main():
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the "
               "path would shard over states with one density all-reduce per "
-              "half step, which this build does not run.", file=sys.stderr)
+              "half step, which this benchmark does not run.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
