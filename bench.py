@@ -148,7 +148,10 @@ def run_gpu(w, precision, steps, warmup, torch, tune=True, shape=None,
     # passes of a step, so every pass type is sampled alike): events around
     # every launch cost ~6 % of the step, around every launch of every
     # class ~20 %
-    g.profile_begin(64 * steps + 64, classes=("hpsi",), every=HPSI_SAMPLE)
+    # (short runs time every launch: a sample of few launches would not
+    # hold the pass types in their proportions)
+    every = HPSI_SAMPLE if steps >= 7 * HPSI_SAMPLE else 1
+    g.profile_begin(64 * steps + 64, classes=("hpsi",), every=every)
     e0.record(st)
     d, n = prop(psi, vion, steps, w.dt, t0=warmup * w.dt,
                 dipole=not periodic, norms=True)
