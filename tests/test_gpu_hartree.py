@@ -181,9 +181,11 @@ def test_mixed_precision_with_hartree_dipole(torch_cuda, oracle_mod):
     assert np.abs(d.cpu().numpy() - wd).max() < 1e-6
 
 
-def test_batch_with_hartree_equals_each_job_alone(torch_cuda):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_with_hartree_equals_each_job_alone(torch_cuda, prec):
     """Jobs with and without the Hartree term in one batch (captured graph)
-    give bitwise the results of propagating each alone."""
+    give bitwise the results of propagating each alone, in FP64 and in the
+    mixed form."""
     from paper_1912_07921_amd import ks
     torch = torch_cuda
     specs = [system(), system((1, 1, 1), nk=2)]
@@ -195,7 +197,7 @@ def test_batch_with_hartree_equals_each_job_alone(torch_cuda):
     nsteps, dt = 4, 0.01
     alone = []
     for spec, v, psi in specs:
-        g = grid(spec)
+        g = grid(spec, prec)
         p = dev(torch, psi)
         d, n = g.propagate_etrs(p, dev(torch, v), nsteps, dt,
                                 dipole=not any(spec.periodic), norms=True)
@@ -203,7 +205,7 @@ def test_batch_with_hartree_equals_each_job_alone(torch_cuda):
                       n.cpu().numpy()))
     jobs = []
     for spec, v, psi in specs:
-        g = grid(spec)
+        g = grid(spec, prec)
         jobs.append(ks.Job(g, dev(torch, psi), dev(torch, v), dt, nsteps,
                            dipole=not any(spec.periodic)))
     b = ks.Batch(jobs, use_graph=True)
