@@ -311,10 +311,11 @@ def serving_requests(torch, nreq, steps, rate):
 def run_serving(torch, nreq, steps, budget_gib, slots):
     """FP64 and FP32-mixed serving of the same requests.  A saturated run
     (every request waiting at t = 0) gives the FP64 capacity C in
-    requests/s; both precisions are then run with Poisson arrivals at 0.8 C.
-    Each run reports p50/p99 per-(request, step) latency and aggregate
-    point-states/s; the mixed runs also report their largest dipole
-    deviation from the FP64 run of the same request."""
+    requests/s; both precisions are then run with Poisson arrivals at 0.5,
+    0.8 and 1.2 C.  Each run reports p50/p99 per-(request, step) latency and
+    aggregate point-states/s (for the saturated runs also as algorithmic
+    bandwidth against the HBM peak); the mixed runs also report their
+    largest dipole deviation from the FP64 run of the same request."""
     from paper_1912_07921_amd.serving import Request, Server
     from paper_1912_07921_amd import workloads as W
     base = serving_requests(torch, nreq, steps, 1.0)
@@ -361,6 +362,13 @@ def run_serving(torch, nreq, steps, budget_gib, slots):
                 errs.append(max(float(np.abs(dd[k] - d64[k]).max())
                                 for k in d64))
     out["mixed"]["dipole_err_vs_fp64_max"] = max(errs)
+    # aggregate roofline of the saturated runs: the H.psi passes' algorithmic
+    # bytes (STEP_BYTES / 8 per point-state and pass) at the aggregate rate
+    for prec, key in ((0, "fp64"), (1, "mixed")):
+        gbs = out[key]["saturated"]["value"] * STEP_BYTES[prec] / 8.0 / 1e9
+        out[key]["aggregate_roofline"] = dict(
+            achieved_GBs=round(gbs, 1), peak=HBM_PEAK_GBS,
+            frac=round(gbs / HBM_PEAK_GBS, 4))
     return out
 
 
