@@ -147,3 +147,39 @@ def test_current_full_size_periodic_workload(torch_cuda, oracle_mod):
     want = oracle_mod.Oracle(sub).current(psi, t)
     got = ks.Grid(sub).current(dev(torch, psi), t)
     assert np.abs(got - want).max() < 1e-10 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("periodic", [(0, 0, 0), (1, 1, 1)])
+def test_mixed_projector_counts(torch_cuda, oracle_mod, periodic):
+    """Atoms with 1, 4 and 9 projectors (s; s+p; s+p+d) on one grid: H.psi,
+    a propagation and the current against the oracle."""
+    from paper_1912_07921_amd import ks
+    torch = torch_cuda
+    spec, v, psi = W.tiny(n=(18, 16, 15), h=(0.35, 0.35, 0.35),
+                          periodic=periodic, nk=2 if any(periodic) else 1,
+                          nstates=3, natoms=3, lmax=2, rc=1.2, sigma=0.4,
+                          xc=1, laser=LASER, seed=9)
+    spec.lmax = np.array([0, 1, 2], dtype=np.int32)
+    psi = normalised(spec, psi)
+    o = oracle_mod.Oracle(spec)
+    g = ks.Grid(spec)
+    g.update_vlocal(dev(torch, v))
+    A = o.laser_A(1.3)
+    for k in range(spec.nk):
+        want = o.apply_h(v, psi[k], k=k, A=A)
+        got = g.apply_h(dev(torch, psi[k]), k=k, t=1.3).cpu().numpy()
+        err = np.linalg.norm(got - want, axis=-1) / np.linalg.norm(want,
+                                                                  axis=-1)
+        assert err.max() < 1e-12, err
+    Jw = o.current(psi, 1.3)
+    Jg = g.current(dev(torch, psi), 1.3)
+    assert np.abs(Jg - Jw).max() < 1e-10 * np.abs(Jw).max()
+    want, _, wn = o.propagate_etrs(psi, 0.3 * v, 3, 0.01, 0.5)
+    p = dev(torch, psi)
+    _, n = g.propagate_etrs(p, dev(torch, 0.3 * v), 3, 0.01, 0.5,
+                            dipole=False, norms=True)
+    N = spec.npoints
+    e = np.linalg.norm(p.cpu().numpy().reshape(-1, N) - want.reshape(-1, N),
+                       axis=1) / np.linalg.norm(want.reshape(-1, N), axis=1)
+    assert e.max() < 1e-10
+    assert np.abs(n.cpu().numpy() - wn).max() < 1e-10
