@@ -293,9 +293,49 @@ int build_projectors(ks_grid *g, const ks_grid_desc *d)
                         chunk_atoms[c].end());
     }
     g->nhull = nhull;
+    // hull entries: every sphere point as (hull point, atom), grouped by
+    // hull point with atoms in index order; the apply's phase code is the
+    // negated wrap of the point's image
+    const long nent = (long)sidx.size();
+    std::vector<int> he_off(nhull + 1, 0), he_slot(nent), he_code(nent);
+    std::vector<int2> ent(nent);
+    {
+        std::vector<long> hof(nent);
+        for (int a = 0; a < na; ++a)
+            for (int i = 0; i < npts[a]; ++i) {
+                const long k = ioff[a] + i;
+                const int gg = sidx[k];
+                const long row = gg / G.nx;
+                hof[k] = rowinfo[row].z + (gg % G.nx - rowinfo[row].x);
+                ++he_off[hof[k] + 1];
+            }
+        for (long h = 0; h < nhull; ++h)
+            he_off[h + 1] += he_off[h];
+        std::vector<int> fill(he_off.begin(), he_off.end() - 1);
+        for (int a = 0; a < na; ++a)
+            for (int i = 0; i < npts[a]; ++i) {
+                const long k = ioff[a] + i;
+                const long h = hof[k];
+                const int e = fill[h]++;
+                const int c = (int)(h / kHullChunk);
+                const auto &ca = chunk_atoms[c];
+                he_slot[e] = (int)(std::find(ca.begin(), ca.end(), a) -
+                                   ca.begin());
+                const int w = sshift[k];
+                int code = 0;
+                for (int ax = 0; ax < 3; ++ax) {
+                    const int t = (int)(signed char)((w >> (8 * ax)) & 0xff);
+                    code |= ((-t) & 0xff) << (8 * ax);
+                }
+                he_code[e] = code;
+                ent[e] = make_int2(a, i);
+            }
+    }
 
     int *d_nproj, *d_npts, *d_sidx, *d_sxyz, *d_sshift, *d_hxyz, *d_hc_off,
-        *d_hc_atoms;
+        *d_hc_atoms, *d_he_off, *d_he_slot, *d_he_code;
+    int2 *d_ent;
+    double *d_he_p;
     long *d_ioff;
     double *d_EjN2;
     double4 *d_apos;
@@ -314,7 +354,12 @@ int build_projectors(ks_grid *g, const ks_grid_desc *d)
         (rc = dev_upload(g, &d_rowinfo, rowinfo)) ||
         (rc = dev_upload(g, &d_hxyz, hxyz)) ||
         (rc = dev_upload(g, &d_hc_off, hc_off)) ||
-        (rc = dev_upload(g, &d_hc_atoms, hc_atoms)))
+        (rc = dev_upload(g, &d_hc_atoms, hc_atoms)) ||
+        (rc = dev_upload(g, &d_he_off, he_off)) ||
+        (rc = dev_upload(g, &d_he_slot, he_slot)) ||
+        (rc = dev_upload(g, &d_he_code, he_code)) ||
+        (rc = dev_upload(g, &d_ent, ent)) ||
+        (rc = dev_alloc(g, &d_he_p, (size_t)nent * kMaxProj)))
         return rc;
     g->pj.nproj = d_nproj;
     g->pj.npts = d_npts;
@@ -331,6 +376,14 @@ int build_projectors(ks_grid *g, const ks_grid_desc *d)
     g->pj.nhchunk = nhch;
     g->pj.hc_off = d_hc_off;
     g->pj.hc_atoms = d_hc_atoms;
+    g->pj.he_off = d_he_off;
+    g->pj.he_slot = d_he_slot;
+    g->pj.he_code = d_he_code;
+    g->pj.he_p = d_he_p;
+    // projector values of the entries, evaluated on the device as the
+    // gather evaluates them (synchronous: creation is)
+    KS_HIP(launch_hull_table(g->pj, G, d_ent, nent, d_he_p, g->stream));
+    KS_HIP(hipStreamSynchronize(g->stream));
     return KS_OK;
 }
 

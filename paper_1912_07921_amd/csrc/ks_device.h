@@ -902,18 +902,18 @@ __device__ __forceinline__ void gather_finalize_item(const GArgs &a,
 // V_NL in on the hull: W[s][h] = sum over atoms a whose sphere holds hull
 // point h of sum_j P_j(r) rad(r) D[s][a][j] exp(-i k.T).  A workgroup takes
 // a chunk of 64 hull points and 4 * kApplySPW states (kApplySPW per
-// wavefront); atoms in index order (deterministic).  The atoms of the chunk
-// (centre, radii, projector count) and their coefficients for the
-// workgroup's states are staged in LDS, kApplyAtoms at a time, with one
-// round of coalesced loads, so the atom loop reads only LDS.
+// wavefront).  The coefficients of the chunk's atoms for the workgroup's
+// states are staged in LDS, kApplyAtoms at a time, with one round of
+// coalesced loads; each lane then walks only the spheres that contain its
+// point (the hull entries, in atom order: deterministic), with projector
+// values tabulated once per grid, so no lane works on an atom whose sphere
+// misses its point and no shape is evaluated per pass.
 constexpr int kApplySPW = KS_APPLY_SPW;
 constexpr int kApplyStates = 4 * kApplySPW;
 constexpr int kApplyAtoms = 12;
 
 template <class R> struct ApplyLds {
     using V = typename Cplx<R>::T;
-    double4 apos[kApplyAtoms];
-    double2 arad[kApplyAtoms];
     int np[kApplyAtoms];
     V D[kApplyAtoms][kApplyStates][kMaxProj];
 };
@@ -931,14 +931,9 @@ __device__ __forceinline__ void kbapply_item(const GArgs &a, const int chunk,
     const int s0 = sb + wave * kApplySPW;
     const int h = chunk * kHullChunk + lane;
     const bool valid = h < a.pj.nhull;
-    const int nx = a.geo.nx, ny = a.geo.ny, nz = a.geo.nz;
-    const int perx = a.geo.per[0], pery = a.geo.per[1], perz = a.geo.per[2];
-    const double Lx = nx * a.geo.h[0], Ly = ny * a.geo.h[1],
-                 Lz = nz * a.geo.h[2];
-    const int pk = valid ? gp(a.pj.hxyz)[h] : 0;
-    const double xc = axis_coord(nx, a.geo.h[0], perx, pk & 0x3ff);
-    const double yc = axis_coord(ny, a.geo.h[1], pery, (pk >> 10) & 0x3ff);
-    const double zc = axis_coord(nz, a.geo.h[2], perz, pk >> 20);
+    // the spheres containing this hull point (entries in atom order)
+    const int e0 = valid ? gp(a.pj.he_off)[h] : 0;
+    const int e1 = valid ? gp(a.pj.he_off)[h + 1] : 0;
     V acc[kApplySPW];
 #pragma unroll
     for (int q = 0; q < kApplySPW; ++q)
@@ -947,12 +942,8 @@ __device__ __forceinline__ void kbapply_item(const GArgs &a, const int chunk,
     for (int b0 = c0; b0 < c1; b0 += kApplyAtoms) {
         const int nb = min(kApplyAtoms, c1 - b0);
         __syncthreads();              // the previous batch has been read
-        if (tid < nb) {
-            const int at = gp(a.pj.hc_atoms)[b0 + tid];
-            sh.apos[tid] = gld(a.pj.apos + at);
-            sh.arad[tid] = gld(a.pj.arad + at);
-            sh.np[tid] = gp(a.pj.nproj)[at];
-        }
+        if (tid < nb)
+            sh.np[tid] = gp(a.pj.nproj)[gp(a.pj.hc_atoms)[b0 + tid]];
         for (int t = tid; t < nb * kApplyStates * kMaxProj; t += blockDim.x) {
             const int i = t / (kApplyStates * kMaxProj);
             const int r = t - i * (kApplyStates * kMaxProj);
@@ -966,30 +957,16 @@ __device__ __forceinline__ void kbapply_item(const GArgs &a, const int chunk,
             sh.D[i][q][j] = d;
         }
         __syncthreads();
-        for (int i = 0; i < nb; ++i) {
-            const double4 ap = sh.apos[i];
-            double dx = xc - ap.x, dy = yc - ap.y, dz = zc - ap.z;
-            int mx = 0, my = 0, mz = 0;
-            if (perx) {
-                mx = (int)rint(dx / Lx);
-                dx -= mx * Lx;
-            }
-            if (pery) {
-                my = (int)rint(dy / Ly);
-                dy -= my * Ly;
-            }
-            if (perz) {
-                mz = (int)rint(dz / Lz);
-                dz -= mz * Lz;
-            }
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (!valid || !(r2 < ap.w))
-                continue;
+        for (int e = e0; e < e1; ++e) {
+            const int i = gp(a.pj.he_slot)[e] - (b0 - c0);
+            if (i < 0 || i >= nb)
+                continue;                 // an atom of another batch
             const int np = sh.np[i];
+            const int code = gp(a.pj.he_code)[e];
             R p[kMaxProj];
-            proj_shape<R>(dx, dy, dz, r2, sh.arad[i], np, p);
-            const int code =
-                (mx & 0xff) | ((my & 0xff) << 8) | ((mz & 0xff) << 16);
+#pragma unroll
+            for (int j = 0; j < kMaxProj; ++j)
+                p[j] = (R)gp(a.pj.he_p)[(size_t)e * kMaxProj + j];
 #pragma unroll
             for (int q = 0; q < kApplySPW; ++q) {
                 const int sl = s0 + q;

@@ -61,6 +61,15 @@ struct ProjDev {
     int nhchunk = 0;
     const int *hc_off = nullptr;
     const int *hc_atoms = nullptr;
+    // per hull point h, the spheres containing it: entries
+    // [he_off[h], he_off[h+1]) in atom order, each with the atom's slot in
+    // its hull chunk's atom list, the Bloch phase code of the apply
+    // (lattice shift from the point to its image in the sphere, negated)
+    // and the 9 projector values at the image (zero past nproj)
+    const int *he_off = nullptr;
+    const int *he_slot = nullptr;
+    const int *he_code = nullptr;
+    const double *he_p = nullptr;
 };
 
 constexpr int kHullChunk = 64;
@@ -139,6 +148,12 @@ hipError_t launch_hpsi_current(const HArgs &a, int ns, hipStream_t st);
 hipError_t launch_gather(bool mixed, bool in_is_f64, const GArgs &a, int ns,
                          hipStream_t st);
 hipError_t launch_kbapply(bool mixed, const GArgs &a, int ns, hipStream_t st);
+// Projector values of the hull entries: he_p[e][j] for the atom and sphere
+// point of entry e (ent[e] = (atom, index of the point in the atom's
+// sphere list)), evaluated as the gather evaluates them.
+hipError_t launch_hull_table(const ProjDev &pj, const Geo &g,
+                             const int2 *ent, long nent, double *he_p,
+                             hipStream_t st);
 int gather_chunks(int max_npts);
 int density_blocks(long N);
 hipError_t launch_density(const DArgs &a, hipStream_t st);

@@ -310,6 +310,51 @@ hipError_t launch_kbapply(bool mixed, const GArgs &a, int ns, hipStream_t st)
     return hipGetLastError();
 }
 
+// he_p[e][j] = p_j (without N_j) of entry e's atom at its sphere point, by
+// the gather's own evaluation (the same point image, the same shapes).
+__global__ __launch_bounds__(256) void k_hull_table(ProjDev pj, Geo G,
+                                                    const int2 *ent,
+                                                    long nent, double *he_p)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nent)
+        return;
+    const int2 ai = ent[e];
+    const int at = ai.x;
+    const long ip = gp(pj.ioff)[at] + ai.y;
+    const int pk = gp(pj.sxyz)[ip];
+    const int code = gp(pj.sshift)[ip];
+    const int ix = pk & 0x3ff, iy = (pk >> 10) & 0x3ff, iz = pk >> 20;
+    const int tx = (int)(signed char)(code & 0xff);
+    const int ty = (int)(signed char)((code >> 8) & 0xff);
+    const int tz = (int)(signed char)((code >> 16) & 0xff);
+    const double4 ap = gld(pj.apos + at);
+    const double2 ar = gld(pj.arad + at);
+    const double dx = axis_coord(G.nx, G.h[0], G.per[0], ix) +
+                      tx * (G.nx * G.h[0]) - ap.x;
+    const double dy = axis_coord(G.ny, G.h[1], G.per[1], iy) +
+                      ty * (G.ny * G.h[1]) - ap.y;
+    const double dz = axis_coord(G.nz, G.h[2], G.per[2], iz) +
+                      tz * (G.nz * G.h[2]) - ap.z;
+    double p[kMaxProj];
+    proj_shape<double>(dx, dy, dz, dx * dx + dy * dy + dz * dz, ar,
+                       gp(pj.nproj)[at], p);
+#pragma unroll
+    for (int j = 0; j < kMaxProj; ++j)
+        he_p[e * kMaxProj + j] = p[j];
+}
+
+hipError_t launch_hull_table(const ProjDev &pj, const Geo &g,
+                             const int2 *ent, long nent, double *he_p,
+                             hipStream_t st)
+{
+    if (nent <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_hull_table, dim3((unsigned)((nent + 255) / 256)),
+                       dim3(256), 0, st, pj, g, ent, nent, he_p);
+    return hipGetLastError();
+}
+
 // out[g] = sum_j w[j] src[j][g], j = 0 .. h-1 in order (potential
 // extrapolation of the CFM4 propagator).
 struct VComb {
