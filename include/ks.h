@@ -83,7 +83,9 @@ typedef enum {
 } ks_precision;
 
 typedef struct {
-    int n[3];            /* nx, ny, nz >= 1; nx <= 192 */
+    int n[3];            /* nx, ny, nz >= 1; nx <= 192; with atoms also
+                            ny <= 1024 and nz <= 2048 (else
+                            KS_E_UNSUPPORTED) */
     double h[3];         /* grid spacing per axis (bohr), > 0 */
     int periodic[3];     /* 1: Bloch-periodic axis, 0: zero boundary */
     int fd_half_width;   /* must be 4 (25-point star); else KS_E_UNSUPPORTED */

@@ -772,6 +772,11 @@ int ks_grid_create(const ks_grid_desc *d, ks_grid **out)
         return fail(KS_E_UNSUPPORTED, "nk*nstates > 65535");
     if (d->natoms > 0 && (!d->pos || !d->lmax || !d->rc || !d->sigma || !d->E))
         return fail(KS_E_ARG, "atom arrays missing");
+    // sphere and hull points carry their (x, y, z) packed in 10 + 10 + 11
+    // bits of one int
+    if (d->natoms > 0 && (d->n[1] > 1024 || d->n[2] > 2048))
+        return fail(KS_E_UNSUPPORTED, "projectors need ny <= 1024 and "
+                    "nz <= 2048 (ny = %d, nz = %d)", d->n[1], d->n[2]);
     if (d->xc != 0 && d->xc != 1)
         return fail(KS_E_ARG, "xc must be 0 or 1");
     if (d->hartree != 0 && d->hartree != 1)

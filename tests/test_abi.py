@@ -72,6 +72,25 @@ def test_grid_description_errors_need_no_gpu():
     assert b"Hartree" in ks.lib().ks_last_error()
 
 
+def test_grid_size_limits_need_no_gpu():
+    """Axis lengths the kernels cannot index are refused before any device
+    call: nx above 192 (tile rows of at most 512 threads), and with atoms
+    ny above 1024 or nz above 2048 (packed point coordinates)."""
+    from types import SimpleNamespace
+    from paper_1912_07921_amd import ks
+    null_stream = SimpleNamespace(cuda_stream=0)
+    atom = dict(pos=[[0.0, 0.0, 0.0]], Z=[1.0], lmax=[1], rc=[1.0],
+                sigma=[0.5], E=[[1.0, -1.0, 0.0]])
+    for n, kw, word in [((193, 4, 4), {}, b"nx"),
+                        ((8, 1025, 4), atom, b"ny"),
+                        ((8, 4, 2049), atom, b"nz")]:
+        spec = W.SystemSpec(n=n, h=(0.4,) * 3, nstates=1, **kw)
+        with pytest.raises(ks.KSError) as e:
+            ks.ks_grid_create(spec, 0, null_stream)
+        assert e.value.code == -4, n
+        assert word in ks.lib().ks_last_error(), n
+
+
 def test_oracle_builds_and_loads(oracle_mod):
     lib = oracle_mod._load()
     for name in ["orc_create", "orc_apply_h", "orc_propagate_etrs",
