@@ -308,10 +308,11 @@ int ks_autotune(ks_grid *g, const void *d_psi, int reps, int out_shape[3],
 
 /* ---- batched form ----
  * Several grid objects ("jobs") propagated together: every Taylor pass of
- * all jobs runs as one persistent H.psi launch over a job table (with one
- * batched projector gather and apply), the density / potential / dipole /
- * norm reductions per job, and one ETRS step (the same step as
- * ks_propagate_etrs) is captured once as a HIP graph and replayed.  Results
+ * all jobs runs as one H.psi launch over the work items of a job table
+ * (with one batched projector gather and apply), the density / potential /
+ * dipole / norm reductions of all jobs as one launch each, and one ETRS
+ * step (the same step as ks_propagate_etrs) is captured once as a HIP graph
+ * and replayed.  Results
  * equal those of ks_propagate_etrs on each job alone, for the same launch
  * shapes.  Grids must share the precision, have a workspace, and not be used
  * on their own while the batch exists (the batch sets their stream). */

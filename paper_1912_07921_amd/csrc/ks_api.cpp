@@ -1780,9 +1780,10 @@ int ks_propagate_cfm4(ks_grid *g, void *d_psi, const double *d_vion,
 
 // ---------------------------------------------------------------------------
 // Batched form: several grid objects (jobs) propagated together.  Every
-// Taylor pass of all jobs is one persistent H.psi launch (plus one batched
-// projector gather, finalize and apply launch); the density, potential,
-// dipole and norm reductions are per job; one ETRS step is captured as a HIP
+// Taylor pass of all jobs is one H.psi launch (plus one batched projector
+// gather, finalize and apply launch); the density, potential, dipole and
+// norm reductions are one launch each for all jobs (the Hartree term, where
+// a job has it, one solve per job); one ETRS step is captured as a HIP
 // graph once and replayed.  Time-dependent inputs (A(t), output slots) come
 // from per-job device step counters, so the replayed graph needs no change.
 // ---------------------------------------------------------------------------
@@ -1801,6 +1802,15 @@ struct ks_batch {
     int *d_off[4] = {nullptr, nullptr, nullptr, nullptr};
     int off_total[4] = {0, 0, 0, 0};
     int **d_steps = nullptr;
+    // reductions of a step, one launch each for all jobs: the predictor
+    // densities (jobs whose potential depends on the density), the
+    // end-of-step densities, the dipoles and the norms
+    DArgs *d_dpred = nullptr, *d_dend = nullptr;
+    int *d_dpred_off = nullptr, *d_dend_off = nullptr;
+    int npred = 0, nend = 0, blk_pred = 0, blk_end = 0;
+    DipJob *d_dip = nullptr;
+    NormJob *d_norm = nullptr;
+    int ndip = 0, nnorm = 0, max_ns = 0;
     std::vector<int> steps_done;
     bool use_graph = true;
     hipGraph_t graph = nullptr;
@@ -1848,48 +1858,30 @@ int batch_enqueue_step(ks_batch *b)
                                      b->grad, b->hm, b->rpt, b->nthr, b->lds,
                                      b->grid_hpsi, st));
         }
-        if (e == 0)
-            for (size_t i = 0; i < b->grids.size(); ++i) {
-                ks_grid *g = b->grids[i];
-                if (!g->nonlin)
-                    continue;
-                DArgs a;
-                a.geo = g->geo;
-                a.nsrc = g->stot;
-                a.npart = b->hjobs[i].npart;
-                a.rho = wsp<double>(g, g->lay.rho);
-                a.vion = b->jobs[i].d_vion;
-                a.vout = wsp<double>(g, g->lay.vpred);
-                a.xc = g->xc;
-                KS_TRY(density_potential(g, a, st));
-            }
+        if (e == 0) {
+            // v(t + dt) from the predicted density: the exchange term in
+            // the batched launch, the Hartree term per job
+            KS_HIP(launch_density_batch(b->d_dpred, b->d_dpred_off, b->npred,
+                                        b->blk_pred, st));
+            for (ks_grid *g : b->grids)
+                if (g->nonlin && g->hartree)
+                    KS_HIP(launch_hartree(g->pp, g->geo,
+                                          wsp<double>(g, g->lay.rho),
+                                          wsp<double>(g, g->lay.vpred), true,
+                                          wsp<double2>(g, g->lay.pwork), st));
+        }
     }
+    KS_HIP(launch_density_batch(b->d_dend, b->d_dend_off, b->nend, b->blk_end,
+                                st));
     for (size_t i = 0; i < b->grids.size(); ++i) {
         ks_grid *g = b->grids[i];
-        const ks_job &jb = b->jobs[i];
-        const double h3 = g->geo.h[0] * g->geo.h[1] * g->geo.h[2];
-        const int *step = wsp<int>(g, g->lay.step);
-        if (b->hjobs[i].npart_end) {
-            DArgs a;
-            a.geo = g->geo;
-            a.nsrc = g->stot;
-            a.npart = b->hjobs[i].npart;
-            a.rho = wsp<double>(g, g->lay.rho);
-            a.vion = jb.d_vion;
-            a.vout = g->d_v;
-            a.xc = g->xc;
-            a.dpart = jb.d_dipole ? wsp<double>(g, g->lay.dpart) : nullptr;
-            KS_TRY(density_potential(g, a, st));
-            if (jb.d_dipole)
-                KS_HIP(launch_dipole_finalize(a.dpart,
-                                              density_blocks(g->geo.N), h3,
-                                              jb.d_dipole, st, step));
-        }
-        if (jb.d_norms)
-            KS_HIP(launch_norm_finalize(wsp<double>(g, g->lay.normpart),
-                                        g->stot, g->ntile_y * g->nzc, h3,
-                                        jb.d_norms, st, step));
+        if (b->hjobs[i].npart_end && g->hartree)
+            KS_HIP(launch_hartree(g->pp, g->geo, wsp<double>(g, g->lay.rho),
+                                  g->d_v, true, wsp<double2>(g, g->lay.pwork),
+                                  st));
     }
+    KS_HIP(launch_dipole_finalize_batch(b->d_dip, b->ndip, st));
+    KS_HIP(launch_norm_finalize_batch(b->d_norm, b->nnorm, b->max_ns, st));
     KS_HIP(launch_step_advance(b->d_steps, (int)b->grids.size(), st));
     return KS_OK;
 }
@@ -2016,8 +2008,16 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
     }
     for (int kind = 0; kind < 4; ++kind) {
         std::vector<int> off(njobs + 1, 0);
-        for (int i = 0; i < njobs; ++i)
-            off[i + 1] = off[i] + batch_items(kind, b->hjobs[i]);
+        long sum = 0;
+        for (int i = 0; i < njobs; ++i) {
+            sum += batch_items(kind, b->hjobs[i]);
+            if (sum >= (1L << 31)) {
+                ks_batch_destroy(b);
+                return fail(KS_E_UNSUPPORTED, "batch of %ld work items",
+                            sum);
+            }
+            off[i + 1] = (int)sum;
+        }
         b->off_total[kind] = off[njobs];
         if ((rc = batch_alloc(b, &b->d_off[kind], njobs + 1))) {
             ks_batch_destroy(b);
@@ -2075,16 +2075,102 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
         ks_batch_destroy(b);
         return fail(KS_E_HIP, "upload of the job table failed");
     }
-    // persistent grids: a multiple of 8 workgroups (XCD-aware order), at
-    // most what the work needs
-    auto pgrid = [](int items, int cap) {
-        const int g = std::min(std::max(items, 1), cap);
+    // tables of the batched reductions (the same arguments the single-job
+    // propagator passes)
+    {
+        std::vector<DArgs> dpred, dend;
+        std::vector<int> opred(1, 0), oend(1, 0);
+        std::vector<DipJob> dip;
+        std::vector<NormJob> nrm;
+        for (int i = 0; i < njobs; ++i) {
+            ks_grid *g = b->grids[i];
+            const ks_job &jb = b->jobs[i];
+            const double h3 = g->geo.h[0] * g->geo.h[1] * g->geo.h[2];
+            const int *step = b->hjobs[i].step;
+            const int nb = density_blocks(g->geo.N);
+            DArgs a;
+            a.geo = g->geo;
+            a.nsrc = g->stot;
+            a.npart = b->hjobs[i].npart;
+            a.rho = wsp<double>(g, g->lay.rho);
+            a.vion = jb.d_vion;
+            a.xc = g->xc;
+            if (g->nonlin) {
+                a.vout = wsp<double>(g, g->lay.vpred);
+                dpred.push_back(a);
+                opred.push_back(opred.back() + nb);
+            }
+            if (b->hjobs[i].npart_end) {
+                a.vout = g->d_v;
+                a.dpart = jb.d_dipole ? wsp<double>(g, g->lay.dpart)
+                                      : nullptr;
+                dend.push_back(a);
+                oend.push_back(oend.back() + nb);
+                if (jb.d_dipole) {
+                    DipJob d;
+                    d.dpart = a.dpart;
+                    d.nblocks = nb;
+                    d.h3 = h3;
+                    d.out = jb.d_dipole;
+                    d.step = step;
+                    dip.push_back(d);
+                }
+            }
+            if (jb.d_norms) {
+                NormJob n;
+                n.part = wsp<double>(g, g->lay.normpart);
+                n.ns = g->stot;
+                n.ntiles = g->ntile_y * g->nzc;
+                n.h3 = h3;
+                n.out = jb.d_norms;
+                n.step = step;
+                nrm.push_back(n);
+                b->max_ns = std::max(b->max_ns, g->stot);
+            }
+        }
+        if ((long)opred.back() + oend.back() >= (1L << 31)) {
+            ks_batch_destroy(b);
+            return fail(KS_E_UNSUPPORTED, "batch densities too large");
+        }
+        b->npred = (int)dpred.size();
+        b->nend = (int)dend.size();
+        b->blk_pred = opred.back();
+        b->blk_end = oend.back();
+        b->ndip = (int)dip.size();
+        b->nnorm = (int)nrm.size();
+        auto put = [&](auto **dst, const auto &v) -> int {
+            int r = batch_alloc(b, dst, v.size());
+            if (r)
+                return r;
+            if (!v.empty() &&
+                hipMemcpy(*dst, v.data(), v.size() * sizeof(v[0]),
+                          hipMemcpyHostToDevice) != hipSuccess)
+                return fail(KS_E_HIP, "upload of the reduction tables failed");
+            return KS_OK;
+        };
+        if ((rc = put(&b->d_dpred, dpred)) ||
+            (rc = put(&b->d_dpred_off, opred)) ||
+            (rc = put(&b->d_dend, dend)) || (rc = put(&b->d_dend_off, oend)) ||
+            (rc = put(&b->d_dip, dip)) || (rc = put(&b->d_norm, nrm))) {
+            ks_batch_destroy(b);
+            return rc;
+        }
+    }
+    // grids of one work item per workgroup (a multiple of 8, XCD-aware
+    // order): items of different jobs differ in cost, and the hardware
+    // dispatcher hands the next item to whichever CU frees first, where a
+    // fixed chain of items per workgroup would end with its longest chain
+    // (measured on the serving mix: 6 % shorter steps than chains of ~6
+    // items on 1024 workgroups).  At most 2^22 workgroups (2^31 threads of
+    // 512); beyond that each takes every 2^22-th item.
+    auto pgrid = [](int items) {
+        const int g = std::min(std::max(items, 1), 1 << 22);
         return ((g + 7) / 8) * 8;
     };
-    b->grid_hpsi = pgrid(b->off_total[kItemHpsi], 1024);
+    b->grid_hpsi = pgrid(b->off_total[kItemHpsi]);
     b->grid_proj = pgrid(std::max({b->off_total[kItemGather],
                                    b->off_total[kItemGatherFin],
-                                   b->off_total[kItemApply]}), 2048);
+                                   b->off_total[kItemApply]}));
     // initial potential, dipole and norms of every job that starts at step
     // 0; a resumed job keeps the potential its grid holds from the end of
     // its last step (eager)

@@ -1,5 +1,5 @@
-// Batched (multi-job) form: persistent H.psi and projector launches over a
-// job table.
+// Batched (multi-job) form: H.psi and projector launches over the work
+// items of every job of a job table.
 #ifndef KS_HPSI_PART
 #define KS_HPSI_PART 0
 #endif
@@ -11,11 +11,12 @@
 namespace ks {
 
 // ---------------------------------------------------------------------------
-// Batched (multi-job) passes.  One persistent launch covers the work items of
-// every job of a batch: workgroup b takes launch indices b, b + G, b + 2G,
-// ... (G, the grid size, a multiple of 8, so every index of one workgroup
-// stays on its XCD), remapped per XCD as above, and decodes (job, item)
-// from the job's item offset.  The pointers of Taylor pass p (exponential
+// Batched (multi-job) passes.  One launch covers the work items of every
+// job of a batch: workgroup b takes launch indices b, b + G, b + 2G, ...
+// (G, the grid size, a multiple of 8, so every index of one workgroup stays
+// on its XCD; the host sizes G to the item count, so each workgroup
+// usually takes one item), remapped per XCD as above, and decodes (job,
+// item) from the job's item offset.  The pointers of Taylor pass p (exponential
 // e = (p-1)/4, term j = (p-1)%4 + 1) and the time of the pass come from the
 // job table and the job's device step counter, so a captured step replays
 // unchanged.

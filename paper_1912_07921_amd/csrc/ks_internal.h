@@ -167,6 +167,31 @@ hipError_t launch_norm_finalize(const double *normpart, int ns, int ntiles,
                                 const int *step = nullptr);
 hipError_t launch_kick(const Geo &g, double2 *psi, int ns, double kappa,
                        hipStream_t st);
+
+// Reductions of several grids in one launch each (the batched form).  The
+// tables are device arrays; every entry is computed exactly as the
+// single-grid launch computes it.
+struct DipJob {
+    const double *dpart = nullptr;   // density_blocks(N) x 3 partials
+    int nblocks = 0;
+    double h3 = 0.0;
+    double *out = nullptr;           // trace; slot step + 1
+    const int *step = nullptr;
+};
+struct NormJob {
+    const double *part = nullptr;    // [ns][ntiles] partials
+    int ns = 0, ntiles = 0;
+    double h3 = 0.0;
+    double *out = nullptr;           // [steps + 1][ns]; slot step + 1
+    const int *step = nullptr;
+};
+// blk_off[j] = first launch block of job j (blk_off[njobs] = nblocks)
+hipError_t launch_density_batch(const DArgs *args, const int *blk_off,
+                                int njobs, int nblocks, hipStream_t st);
+hipError_t launch_dipole_finalize_batch(const DipJob *jobs, int njobs,
+                                        hipStream_t st);
+hipError_t launch_norm_finalize_batch(const NormJob *jobs, int njobs,
+                                      int max_ns, hipStream_t st);
 hipError_t launch_gram(const Geo &g, const double2 *psi, int nk, int ns,
                        double2 *part, int ksplit, double2 *out,
                        hipStream_t st);

@@ -30,11 +30,12 @@ __global__ __launch_bounds__(256) void k_kbapply(GArgs a)
 // ---------------------------------------------------------------------------
 constexpr int kDensThreads = 256;
 
-__global__ __launch_bounds__(kDensThreads) void k_density(DArgs a)
+// block blk of the density launch of `a` (sbuf: 3 doubles per wavefront)
+__device__ __forceinline__ void density_block(const DArgs &a, long blk,
+                                              double *sbuf)
 {
-    __shared__ double sbuf[(kDensThreads / 64) * 3];
     const Geo G = a.geo;
-    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long g = blk * kDensThreads + threadIdx.x;
     double rho = 0.0;
     if (g < G.N) {
         if (a.npart) {
@@ -66,21 +67,43 @@ __global__ __launch_bounds__(kDensThreads) void k_density(DArgs a)
         block_sum<double, 3>(d, sbuf);
         if (threadIdx.x == 0)
             for (int c = 0; c < 3; ++c)
-                a.dpart[(size_t)blockIdx.x * 3 + c] = d[c];
+                a.dpart[(size_t)blk * 3 + c] = d[c];
+    }
+}
+
+__global__ __launch_bounds__(kDensThreads) void k_density(DArgs a)
+{
+    __shared__ double sbuf[(kDensThreads / 64) * 3];
+    density_block(a, blockIdx.x, sbuf);
+}
+
+// The densities of several grids in one launch: launch block L is block
+// L - off[j] of job j (off[j] <= L < off[j + 1]), each computed exactly as
+// k_density computes it.
+__global__ __launch_bounds__(kDensThreads) void k_density_batch(
+    const DArgs *args, const int *off, int njobs, int total)
+{
+    __shared__ double sbuf[(kDensThreads / 64) * 3];
+    for (int L = blockIdx.x; L < total; L += gridDim.x) {
+        int j = 0;
+        while (j + 1 < njobs && L >= off[j + 1])
+            ++j;
+        const DArgs a = args[j];
+        density_block(a, L - off[j], sbuf);
+        __syncthreads();   // sbuf is reused by the next block
     }
 }
 
 // sum of nblocks dipole partials in fixed order, times h^3; with a device
 // step counter, into out[3 * (step + 1) ...]
-__global__ __launch_bounds__(256) void k_dipole_finalize(const double *dpart,
-                                                         int nblocks,
-                                                         double h3,
-                                                         double *out,
-                                                         const int *step)
+__device__ __forceinline__ void dipole_finalize_job(const double *dpart,
+                                                    int nblocks, double h3,
+                                                    double *out,
+                                                    const int *step,
+                                                    double *sbuf)
 {
     if (step)
         out += 3 * (*step + 1);
-    __shared__ double sbuf[4 * 3];
     double d[3] = {0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
         for (int c = 0; c < 3; ++c)
@@ -89,6 +112,25 @@ __global__ __launch_bounds__(256) void k_dipole_finalize(const double *dpart,
     if (threadIdx.x == 0)
         for (int c = 0; c < 3; ++c)
             out[c] = h3 * d[c];
+}
+
+__global__ __launch_bounds__(256) void k_dipole_finalize(const double *dpart,
+                                                         int nblocks,
+                                                         double h3,
+                                                         double *out,
+                                                         const int *step)
+{
+    __shared__ double sbuf[4 * 3];
+    dipole_finalize_job(dpart, nblocks, h3, out, step, sbuf);
+}
+
+// one workgroup per job
+__global__ __launch_bounds__(256) void k_dipole_finalize_batch(
+    const DipJob *jobs)
+{
+    __shared__ double sbuf[4 * 3];
+    const DipJob J = jobs[blockIdx.x];
+    dipole_finalize_job(J.dpart, J.nblocks, J.h3, J.out, J.step, sbuf);
 }
 
 // per-state partial sums of |psi|^2 over chunks of the grid
@@ -113,21 +155,42 @@ __global__ __launch_bounds__(256) void k_norm_partial(Geo G,
         part[(size_t)s * nchunks + blockIdx.x] = acc[0];
 }
 
-__global__ __launch_bounds__(64) void k_norm_finalize(const double *part,
-                                                      int ntiles, double h3,
-                                                      double *out,
-                                                      const int *step)
+__device__ __forceinline__ void norm_finalize_state(const double *part,
+                                                    int ns, int ntiles,
+                                                    double h3, double *out,
+                                                    const int *step, int s,
+                                                    double *sbuf)
 {
     if (step)
-        out += (size_t)gridDim.x * (*step + 1);
-    __shared__ double sbuf[1];
-    const int s = blockIdx.x;
+        out += (size_t)ns * (*step + 1);
     double acc[1] = {0.0};
     for (int t = threadIdx.x; t < ntiles; t += blockDim.x)
         acc[0] += part[(size_t)s * ntiles + t];
     block_sum<double, 1>(acc, sbuf);
     if (threadIdx.x == 0)
         out[s] = h3 * acc[0];
+}
+
+__global__ __launch_bounds__(64) void k_norm_finalize(const double *part,
+                                                      int ntiles, double h3,
+                                                      double *out,
+                                                      const int *step)
+{
+    __shared__ double sbuf[1];
+    norm_finalize_state(part, gridDim.x, ntiles, h3, out, step, blockIdx.x,
+                        sbuf);
+}
+
+// state blockIdx.x of job blockIdx.y
+__global__ __launch_bounds__(64) void k_norm_finalize_batch(
+    const NormJob *jobs)
+{
+    __shared__ double sbuf[1];
+    const NormJob J = jobs[blockIdx.y];
+    if ((int)blockIdx.x >= J.ns)
+        return;
+    norm_finalize_state(J.part, J.ns, J.ntiles, J.h3, J.out, J.step,
+                        blockIdx.x, sbuf);
 }
 
 // psi <- exp(i kappa z) psi
@@ -398,6 +461,37 @@ hipError_t launch_density(const DArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_density, dim3(density_blocks(a.geo.N)),
                        dim3(kDensThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_density_batch(const DArgs *args, const int *blk_off,
+                                int njobs, int nblocks, hipStream_t st)
+{
+    if (njobs <= 0 || nblocks <= 0)
+        return hipSuccess;
+    const int grid = std::min(nblocks, 1 << 22);
+    hipLaunchKernelGGL(k_density_batch, dim3(grid), dim3(kDensThreads), 0, st,
+                       args, blk_off, njobs, nblocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_dipole_finalize_batch(const DipJob *jobs, int njobs,
+                                        hipStream_t st)
+{
+    if (njobs <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_dipole_finalize_batch, dim3(njobs), dim3(256), 0, st,
+                       jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_finalize_batch(const NormJob *jobs, int njobs,
+                                      int max_ns, hipStream_t st)
+{
+    if (njobs <= 0 || max_ns <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_norm_finalize_batch, dim3(max_ns, njobs), dim3(64), 0,
+                       st, jobs);
     return hipGetLastError();
 }
 

@@ -6,9 +6,9 @@ time.  A request is admitted, first come first served, when a job slot is
 free and its HBM footprint (states, the grid's workspace, v_ion, its dipole
 and norm traces) fits the budget next to the jobs already resident; its
 states and potentials then stay in HBM until its last step.  All resident
-jobs advance together through one libks batch (ks_batch_*: one persistent
-H.psi launch per Taylor pass over every job, one step captured as a HIP
-graph).  When a job joins or leaves, the batch is rebuilt and every job
+jobs advance together through one libks batch (ks_batch_*: one H.psi
+launch per Taylor pass over the work items of every job, one step captured
+as a HIP graph).  When a job joins or leaves, the batch is rebuilt and every job
 resumes where it stopped; the trajectory of each request is bitwise the
 one it has when propagated alone.
 
