@@ -38,12 +38,35 @@ __device__ __forceinline__ void density_block(const DArgs &a, long blk,
     const long g = blk * kDensThreads + threadIdx.x;
     double rho = 0.0;
     if (g < G.N) {
+        // sources in order; eight loads issued before their adds
+        constexpr int U = 8;
+        int s = 0;
         if (a.npart) {
-            for (int s = 0; s < a.nsrc; ++s)
-                rho += a.npart[(size_t)s * G.N + g];
+            const double *p = a.npart + g;
+            for (; s + U <= a.nsrc; s += U) {
+                double v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    v[u] = p[(size_t)(s + u) * G.N];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    rho += v[u];
+            }
+            for (; s < a.nsrc; ++s)
+                rho += p[(size_t)s * G.N];
         } else {
-            for (int s = 0; s < a.nsrc; ++s) {
-                double2 v = a.psi[(size_t)s * G.N + g];
+            const double2 *p = a.psi + g;
+            for (; s + U <= a.nsrc; s += U) {
+                double2 v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    v[u] = p[(size_t)(s + u) * G.N];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    rho += a.wocc[s + u] * (v[u].x * v[u].x + v[u].y * v[u].y);
+            }
+            for (; s < a.nsrc; ++s) {
+                const double2 v = p[(size_t)s * G.N];
                 rho += a.wocc[s] * (v.x * v.x + v.y * v.y);
             }
         }
