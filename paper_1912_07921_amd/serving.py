@@ -26,6 +26,21 @@ import numpy as np
 from . import ks
 
 
+def set_serving_launch(grid, spec):
+    """Launch shape of a served job: the default tile rows with z-chunks of
+    the whole axis.  With many jobs resident the batch has work items to
+    spare, and every z-chunk re-reads the 8 planes around it (saturated
+    serving mix, FP64: 10 % shorter steps than the single-grid default of up
+    to two chunks).  States and dipoles do not depend on the shape; the norm
+    diagnostics (sums of per-tile partials) do in their last bits, so a
+    request is compared with its lone run in this same shape.  A grid whose
+    LDS cannot hold the whole-axis chunk keeps its default."""
+    try:
+        grid.set_launch(0, spec.n[2])
+    except ks.KSError:
+        pass
+
+
 @dataclass
 class Request:
     rid: int
@@ -142,6 +157,7 @@ class Server:
                 r = pending.popleft()
                 g = ks.Grid(r.spec, precision=self.precision,
                             device=self.device, workspace=False)
+                set_serving_launch(g, r.spec)
                 fp = self._footprint(r, g)
                 if fp > self.budget:
                     g.close()

@@ -33,7 +33,9 @@ def make_requests(torch, arrivals, nsteps):
 
 def alone(torch, r):
     from paper_1912_07921_amd import ks
+    from paper_1912_07921_amd.serving import set_serving_launch
     g = ks.Grid(r.spec)
+    set_serving_launch(g, r.spec)
     psi = r.psi.cuda().contiguous()
     g.kick(psi, r.kick)
     d, n = g.propagate_etrs(psi, r.vion.cuda(), r.nsteps, r.dt)
