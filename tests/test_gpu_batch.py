@@ -105,6 +105,56 @@ def test_batch_equals_each_job_alone(torch_cuda, prec):
     b.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_reductions_with_every_table_membership(torch_cuda, prec):
+    """The batched reductions (predictor and end-of-step densities, dipoles,
+    norms: one launch each over tables of the jobs that need them) with jobs
+    in every combination of those tables: a periodic job without exchange
+    (no density at all) and without norms, a finite job with exchange but
+    no dipole and no norms, a finite job with only a dipole, and one with
+    everything.  Each must end bitwise as it does alone."""
+    torch = torch_cuda
+    from paper_1912_07921_amd import ks
+    cases = []
+    spec, v, psi = W.tiny(n=(14, 13, 12), h=(0.35, 0.35, 0.35),
+                          periodic=(1, 1, 1), nk=2, nstates=2, natoms=1,
+                          lmax=1, rc=1.1, sigma=0.4, xc=0, seed=21)
+    cases.append((spec, 0.3 * v, normalised(spec, psi), False, False))
+    spec, v, psi = W.tiny(n=(15, 14, 13), nstates=3, natoms=2, lmax=1,
+                          rc=1.2, sigma=0.4, xc=1, seed=22)
+    cases.append((spec, 0.3 * v, normalised(spec, psi), False, False))
+    spec, v, psi = W.tiny(n=(13, 16, 14), nstates=2, natoms=0, xc=0,
+                          seed=23)
+    cases.append((spec, 0.5 * v, normalised(spec, psi), True, False))
+    spec, v, psi = W.tiny(n=(16, 15, 17), nstates=4, natoms=2, lmax=2,
+                          rc=1.2, sigma=0.4, xc=1, seed=24)
+    cases.append((spec, 0.3 * v, normalised(spec, psi), True, True))
+    dt, nsteps = 0.01, 4
+    alone = []
+    for spec, v, psi, dip, nrm in cases:
+        g = ks.Grid(spec, precision=prec)
+        p = dev(torch, psi)
+        d, n = g.propagate_etrs(p, dev(torch, v), nsteps, dt, dipole=dip,
+                                norms=nrm)
+        alone.append((p.cpu().numpy(),
+                      None if d is None else d.cpu().numpy(),
+                      None if n is None else n.cpu().numpy()))
+    jobs = []
+    for spec, v, psi, dip, nrm in cases:
+        g = ks.Grid(spec, precision=prec)
+        jobs.append(ks.Job(g, dev(torch, psi), dev(torch, v), dt, nsteps,
+                           dipole=dip, norms=nrm))
+    b = ks.Batch(jobs)
+    b.step(nsteps)
+    torch.cuda.synchronize()
+    got = [(j.psi.cpu().numpy(),
+            None if j.dipole is None else j.dipole.cpu().numpy(),
+            None if j.norms is None else j.norms.cpu().numpy())
+           for j in jobs]
+    assert_same(got, alone, f"precision {prec}")
+    b.close()
+
+
 def test_batch_matches_oracle(torch_cuda, oracle_mod):
     torch = torch_cuda
     specs = job_specs()
