@@ -2010,7 +2010,10 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
         std::vector<int> off(njobs + 1, 0);
         long sum = 0;
         for (int i = 0; i < njobs; ++i) {
-            sum += batch_items(kind, b->hjobs[i]);
+            const long n = batch_items(kind, b->hjobs[i]);
+            // H.psi: every job's launch range starts at a multiple of 8
+            // (the kernel's per-job XCD remap)
+            sum += kind == kItemHpsi ? (n + 7) / 8 * 8 : n;
             if (sum >= (1L << 31)) {
                 ks_batch_destroy(b);
                 return fail(KS_E_UNSUPPORTED, "batch of %ld work items",

@@ -15,8 +15,8 @@ namespace ks {
 // job of a batch: workgroup b takes launch indices b, b + G, b + 2G, ...
 // (G, the grid size, a multiple of 8, so every index of one workgroup stays
 // on its XCD; the host sizes G to the item count, so each workgroup
-// usually takes one item), remapped per XCD as above, and decodes (job,
-// item) from the job's item offset.  The pointers of Taylor pass p (exponential
+// usually takes one item) and decodes (job, item) from the job's item
+// offset (the H.psi items remapped per XCD within each job, below).  The pointers of Taylor pass p (exponential
 // e = (p-1)/4, term j = (p-1)%4 + 1) and the time of the pass come from the
 // job table and the job's device step counter, so a captured step replays
 // unchanged.
@@ -55,22 +55,34 @@ __device__ __forceinline__ const void *pass_input(cptr_t<JobDev> J, int p)
     return J->t[j - 2];
 }
 
+// H.psi items: the launch-index range of every job starts at a multiple of
+// 8 (its item count padded up), so launch index L of a job sits on XCD
+// L % 8 = r % 8 with r = L - off[job]; each job's items are remapped within
+// the job, giving every XCD a contiguous eighth of every job (neighbouring
+// y-tiles share halo rows in that XCD's L2, and jobs of different cost load
+// all XCDs alike).  Indices past the job's items are padding.
+#ifndef KS_BATCH_REMAP
+#define KS_BATCH_REMAP 1
+#endif
 template <class R, class InT, class TT, int MODE, bool GRAD, int HM, int RPT>
 __global__ __launch_bounds__(512) void k_hpsi_batch(BArgs b)
 {
     const int total = cp(b.off)[b.njobs];
     for (int L = blockIdx.x; L < total; L += gridDim.x) {
-        const int item = xcd_remap(L, total);
-        const int jb = find_job(b.off, b.njobs, item);
+        const int jb = find_job(b.off, b.njobs, L);
         const cptr_t<JobDev> J = cp(b.jobs) + jb;
-        const int e = (b.pass - 1) / 4;
-        // A(t0 + (step + e) dt)
-        const double4 Av = cload<double4>(cp(J->Atab) + 2 * *cp(J->step) + e);
         // the pass's arguments stay in the constant address space (read by
         // scalar loads where used, like kernel arguments)
         const HArgs &a = *(const HArgs *)(cp(b.hargs) + 8 * jb + b.pass - 1);
-        hpsi_item<R, InT, TT, MODE, GRAD, HM, RPT>(a, item - cp(b.off)[jb],
-                                                   Av);
+        const int r = L - cp(b.off)[jb];
+        const int n = a.ntile_y * a.nzc * J->stot;
+        if (r >= n)
+            continue;                      // padding (uniform per workgroup)
+        const int item = KS_BATCH_REMAP ? xcd_remap(r, n) : r;
+        const int e = (b.pass - 1) / 4;
+        // A(t0 + (step + e) dt)
+        const double4 Av = cload<double4>(cp(J->Atab) + 2 * *cp(J->step) + e);
+        hpsi_item<R, InT, TT, MODE, GRAD, HM, RPT>(a, item, Av);
         __syncthreads();   // LDS is reused by the next item
     }
 }
