@@ -72,3 +72,34 @@ def test_budget_below_one_request_is_refused(torch_cuda):
     reqs = make_requests(torch, [0], [2])
     with pytest.raises(ValueError):
         Server(1 << 20, clock="steps").run(reqs)
+
+
+def test_whole_axis_chunks_of_a_larger_grid(torch_cuda):
+    """A 64^3 request, whose single-grid default splits z into two chunks,
+    is served with one chunk per column (set_serving_launch) beside a small
+    request, and still ends bitwise as its lone run in that shape."""
+    torch = torch_cuda
+    from paper_1912_07921_amd import ks
+    from paper_1912_07921_amd.serving import Request, Server, \
+        set_serving_launch
+    reqs = []
+    for i, (n, ns) in enumerate([(64, 4), (24, 4)]):
+        rng = np.random.Generator(np.random.PCG64(W.SEED_BASE + 450 + i))
+        w = W.serving_request(rng, grids=(n,), states=(ns,), nsteps=3)
+        reqs.append(Request(rid=i, arrival=0.0, spec=w.spec,
+                            vion=torch.from_numpy(w.vion),
+                            psi=torch.from_numpy(w.psi0.copy()),
+                            nsteps=3, dt=w.dt, kick=w.kick))
+    g = ks.Grid(reqs[0].spec)
+    assert g.get_launch()["zchunk"] < 64
+    set_serving_launch(g, reqs[0].spec)
+    assert g.get_launch()["zchunk"] == 64
+    g.close()
+    srv = Server(1 << 34, max_slots=2, clock="steps", keep_states=True)
+    st = srv.run(reqs)
+    assert st["max_concurrent"] == 2
+    for r in reqs:
+        p, d, n = alone(torch, r)
+        assert np.array_equal(r.final_psi, p), r.rid
+        assert np.array_equal(r.dipole, d), r.rid
+        assert np.array_equal(r.norms, n), r.rid
