@@ -117,8 +117,33 @@ def log(msg):
 
 
 def make_workload(name):
+    """The workload's inputs; the molecule workloads (c2, c5) are built on
+    the GPU (same random draws as the CPU build, values equal to rounding)
+    so that 256 states of 128^3 points take seconds."""
     from paper_1912_07921_amd import workloads as W
-    return {"c1": W.c1, "c2": W.c2, "c3": W.c3, "c5": W.c5}[name]()
+    if name in ("c2", "c5"):
+        return {"c2": W.c2, "c5": W.c5}[name](device="cuda")
+    return {"c1": W.c1, "c3": W.c3}[name]()
+
+
+def sample_workload(name, nstates):
+    """The same system with only its first `nstates` states, built on the
+    CPU (the oracle's input); None when the workload has no fewer states."""
+    from paper_1912_07921_amd import workloads as W
+    if name == "c5":
+        return W.c5(nstates=nstates)
+    if name == "c2":
+        return W.c2(nstates=nstates)
+    if name == "c3":
+        return W.c3(nstates=max(1, nstates // 4))
+    return W.c1()
+
+
+def to_dev(torch, x):
+    """A fresh device copy of an input (numpy array or tensor)."""
+    if isinstance(x, np.ndarray):
+        return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    return x.detach().clone().cuda()
 
 
 def run_gpu(w, precision, steps, warmup, torch, tune=True, shape=None,
@@ -128,8 +153,8 @@ def run_gpu(w, precision, steps, warmup, torch, tune=True, shape=None,
     the autotuner's choice (tune) or the default."""
     from paper_1912_07921_amd import ks
     g = ks.Grid(w.spec, precision=precision)
-    psi = torch.from_numpy(w.psi0.copy()).cuda()
-    vion = torch.from_numpy(w.vion).cuda()
+    psi = to_dev(torch, w.psi0)
+    vion = to_dev(torch, w.vion)
     if w.kick:
         g.kick(psi, w.kick)
     if shape:
@@ -222,7 +247,7 @@ def run_hartree(w, torch, steps, warmup, tune, reps=50):
         res[key] = dict(value=8.0 * N * S * steps / sec,
                         ms_per_step=1e3 * sec / steps, launch_shape=shape)
     g = ks.Grid(wh.spec)
-    rho = g.density(torch.from_numpy(w.psi0).cuda())
+    rho = g.density(to_dev(torch, w.psi0))
     vh = torch.empty_like(rho)
     for _ in range(5):
         g.hartree(rho, vh)
@@ -252,7 +277,7 @@ def run_observables(w, torch, dip, reps=20):
     function of the benchmark's own dipole trace on 2000 frequencies."""
     from paper_1912_07921_amd import ks
     g = ks.Grid(w.spec)
-    psi = torch.from_numpy(w.psi0).cuda()
+    psi = to_dev(torch, w.psi0)
     g.current(psi, 0.0)
     torch.cuda.synchronize()
     g.profile_begin(4 * reps + 16, classes=("reduce",))
@@ -308,7 +333,7 @@ def serving_requests(torch, nreq, steps, rate):
     return reqs
 
 
-def run_serving(torch, nreq, steps, budget_gib, slots):
+def run_serving(torch, nreq, steps, budget_gib, slots, loads=(0.8,)):
     """FP64 and FP32-mixed serving of the same requests.  A saturated run
     (every request waiting at t = 0) gives the FP64 capacity C in
     requests/s; both precisions are then run with Poisson arrivals at 0.5,
@@ -337,7 +362,7 @@ def run_serving(torch, nreq, steps, budget_gib, slots):
                         "{4,...,64}, 2-12 atoms s+p, LDA exchange, kick "
                         "0.01 z", requests=nreq, steps_per_request=steps,
                mean_points_x_states=mean_ns, hbm_budget_gib=budget_gib,
-               slots=slots)
+               slots=slots, offered_loads_of_capacity=list(loads))
     log(f"serving FP64: saturated run, {nreq} requests x {steps} steps")
     sat, d64 = serve(0, np.zeros(nreq))
     cap = nreq / sat["wall_s"]
@@ -350,7 +375,7 @@ def run_serving(torch, nreq, steps, budget_gib, slots):
     errs = [max(float(np.abs(dmx[k] - d64[k]).max()) for k in d64)]
     # offered loads relative to the FP64 capacity C; both precisions see the
     # same arrival times
-    for f in (0.5, 0.8, 1.2):
+    for f in loads:
         lam = f * cap
         arrivals, _ = W.c4_stream(nreq, rate=lam, nsteps=steps)
         for prec, key in ((0, "fp64"), (1, "mixed")):
@@ -372,19 +397,86 @@ def run_serving(torch, nreq, steps, budget_gib, slots):
     return out
 
 
-def cpu_baseline(w, sample_steps):
+def cpu_baseline(ws, sample_steps, full_states):
+    """The oracle, as it stands, on the host cores: `sample_steps` ETRS steps
+    of the sample workload `ws` (the benchmark's system with a subset of its
+    states).  Returns the baseline record and the oracle's results (final
+    states, dipole trace, norms, density, energy) for the error report."""
     from oracle import oracle
-    o = oracle.Oracle(w.spec)
-    psi = o.kick(w.psi0, w.kick) if w.kick else w.psi0
+    o = oracle.Oracle(ws.spec)
+    psi = o.kick(ws.psi0, ws.kick) if ws.kick else ws.psi0
     t = time.perf_counter()
-    o.propagate_etrs(psi, w.vion, sample_steps, w.dt)
+    psi, dip, nrm = o.propagate_etrs(psi, ws.vion, sample_steps, ws.dt)
     sec = time.perf_counter() - t
-    N, S = w.spec.npoints, w.spec.nk * w.spec.nstates
-    return dict(value=8.0 * N * S * sample_steps / sec,
-                unit="grid-point·states/s", cores=oracle.num_threads(),
-                kind="oracle",
-                sample=f"{sample_steps} ETRS steps of the same workload "
-                       f"({w.name}, all {S} states), {sec:.2f} s wall")
+    N, S = ws.spec.npoints, ws.spec.nk * ws.spec.nstates
+    finite = not any(ws.spec.periodic)
+    ref = dict(psi=psi, dipole=dip if finite else None, norms=nrm,
+               rho=o.density(psi),
+               energy=o.energy(psi, ws.vion, sample_steps * ws.dt))
+    rec = dict(value=8.0 * N * S * sample_steps / sec,
+               unit="grid-point·states/s", cores=oracle.num_threads(),
+               kind="oracle",
+               sample=f"{sample_steps} ETRS steps of the same system "
+                      f"({ws.name}) with {S} of its {full_states} states "
+                      f"(exchange from their density), {sec:.2f} s wall")
+    return rec, ref
+
+
+def errors_vs_oracle(ws, ref, sample_steps, precision, shape, torch):
+    """The library's run of the oracle's sample (same states, steps and
+    launch shape as the timed run) and its errors against the oracle:
+    states (largest relative 2-norm), density and energy at the end
+    (relative), dipole trace (absolute a.u. and relative to its largest
+    component), norms (absolute)."""
+    from paper_1912_07921_amd import ks
+    finite = not any(ws.spec.periodic)
+    g = ks.Grid(ws.spec, precision=precision)
+    g.set_launch(*shape)
+    psi = to_dev(torch, ws.psi0)
+    vion = to_dev(torch, ws.vion)
+    if ws.kick:
+        g.kick(psi, ws.kick)
+    d, n = g.propagate_etrs(psi, vion, sample_steps, ws.dt, dipole=finite,
+                            norms=True)
+    g64 = ks.Grid(ws.spec)
+    rho = g64.density(psi).cpu().numpy()
+    E = g64.energy(psi, vion, sample_steps * ws.dt)
+    got = psi.cpu().numpy()
+    g64.close()
+    g.close()
+    want = ref["psi"]
+    err = dict(
+        states_rel=max(float(np.linalg.norm(got[k, s] - want[k, s]) /
+                             np.linalg.norm(want[k, s]))
+                       for k in range(ws.spec.nk)
+                       for s in range(ws.spec.nstates)),
+        density_rel=float(np.abs(rho - ref["rho"]).max() /
+                          np.abs(ref["rho"]).max()),
+        energy_rel=abs(E - ref["energy"]) / abs(ref["energy"]),
+        energy_Ha=E,
+        norms_abs=float(np.abs(n.cpu().numpy() - ref["norms"]).max()))
+    if finite:
+        dd = float(np.abs(d.cpu().numpy() - ref["dipole"]).max())
+        err["dipole_abs_au"] = dd
+        err["dipole_rel"] = dd / float(np.abs(ref["dipole"]).max())
+    return err
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo where there is one)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def shape_tuple(shape):
+    """(tile rows, z-chunk, rows per thread) of a get_launch() record."""
+    return (shape["tile_rows"], shape["zchunk"], shape["rows_per_thread"])
 
 
 def main():
@@ -392,10 +484,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3",
+    ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c3",
                                                          "c5"])
     ap.add_argument("--cpu-steps", type=int, default=3,
                     help="oracle ETRS steps timed for the CPU baseline")
+    ap.add_argument("--cpu-states", type=int, default=16,
+                    help="states of the workload the oracle runs (its "
+                         "first ones; all of them if fewer)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -413,9 +508,13 @@ def main():
                     help="FP64 launch shape 'tile_rows,zchunk,rows_per_thread'"
                          " instead of the autotuner's (profiling runs)")
     ap.add_argument("--serving-only", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=128)
-    ap.add_argument("--serving-steps", type=int, default=50,
-                    help="ETRS steps per request (the full mix asks 200)")
+    ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--serving-steps", type=int, default=200,
+                    help="ETRS steps per request")
+    ap.add_argument("--serving-loads", default="0.8",
+                    help="offered loads (fractions of the saturated FP64 "
+                         "capacity) of the Poisson-arrival runs, e.g. "
+                         "0.5,0.8,1.2")
     ap.add_argument("--serving-budget-gib", type=float, default=96.0)
     ap.add_argument("--serving-slots", type=int, default=64)
     args = ap.parse_args()
@@ -426,6 +525,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    loads = tuple(float(v) for v in args.serving_loads.split(",") if v)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.calibrate_copy:
@@ -435,7 +535,7 @@ def main():
         print(json.dumps(run_serving(torch, args.serving_requests,
                                      args.serving_steps,
                                      args.serving_budget_gib,
-                                     args.serving_slots)), flush=True)
+                                     args.serving_slots, loads)), flush=True)
         return
     log(f"workload {args.workload}: generating inputs")
     w = make_workload(args.workload)
@@ -471,6 +571,12 @@ def main():
     copy_gbs = copy_bandwidth(torch)
     roofline["copy_GBs"] = round(copy_gbs, 1)
     roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    # the whole step against the same peak: the algorithmic bytes of the
+    # eight passes over the measured step time
+    step_gbs = STEP_BYTES[0] * N * S / (sec / args.steps) / 1e9
+    step_roofline = dict(achieved=round(step_gbs, 1), peak=HBM_PEAK_GBS,
+                         unit="GB/s", frac=round(step_gbs / HBM_PEAK_GBS, 4),
+                         algorithmic_bytes_per_step=STEP_BYTES[0] * N * S)
     kernel_times = {k: dict(total_ms=round(v[0], 3), launches=v[1],
                             avg_us=round(1e3 * v[0] / max(v[1], 1), 2))
                     for k, v in prof.items()}
@@ -499,6 +605,7 @@ def main():
             "dt": w.dt, "kick": w.kick,
         },
         "roofline": roofline,
+        "step_roofline": step_roofline,
         "kernels": kernel_times,
         # the paper reports no H.psi rate or bandwidth, only relative
         # whole-run GPU speed-ups on other hardware (context, not a target)
@@ -521,6 +628,9 @@ def main():
                      speedup_vs_fp64=sec / msec,
                      roofline_achieved_GBs=round(mach, 1),
                      roofline_frac=round(mach / HBM_PEAK_GBS, 4),
+                     step_frac=round(STEP_BYTES[1] * N * S /
+                                     (msec / args.steps) / 1e9 /
+                                     HBM_PEAK_GBS, 4),
                      norm_drift_max=float(abs(nrmm - nrm64).max()),
                      launch_shape=mshape)
         if dip64 is not None:
@@ -562,13 +672,25 @@ def main():
         out["serving"] = run_serving(torch, args.serving_requests,
                                      args.serving_steps,
                                      args.serving_budget_gib,
-                                     args.serving_slots)
+                                     args.serving_slots, loads)
 
     if not args.no_cpu:
-        log(f"CPU oracle: {args.cpu_steps} steps")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
-        out["cpu_baseline"]["cpu_model"] = platform.processor() or \
-            platform.machine()
+        ws = sample_workload(args.workload, min(args.cpu_states, S))
+        log(f"CPU oracle: {args.cpu_steps} steps of {ws.name} with "
+            f"{ws.spec.nk * ws.spec.nstates} states")
+        rec, ref = cpu_baseline(ws, args.cpu_steps, S)
+        rec["cpu_model"] = cpu_model()
+        out["cpu_baseline"] = rec
+        # the error of every result against the FP64 oracle, on the
+        # oracle's sample, in the launch shapes of the timed runs
+        log("errors against the oracle on its sample")
+        ev = dict(sample=rec["sample"].rsplit(",", 1)[0])
+        ev["fp64"] = errors_vs_oracle(ws, ref, args.cpu_steps, 0,
+                                      shape_tuple(shape), torch)
+        if "mixed" in out:
+            ev["mixed"] = errors_vs_oracle(ws, ref, args.cpu_steps, 1,
+                                           shape_tuple(mshape), torch)
+        out["error_vs_oracle"] = ev
     print(json.dumps(out), flush=True)
 
 

@@ -73,7 +73,7 @@ typedef enum {
     KS_E_HIP = -3,          /* a HIP runtime call failed */
     KS_E_UNSUPPORTED = -4,  /* valid input this library does not handle */
     KS_E_STATE = -5,        /* call out of order (no potential, no workspace) */
-    KS_E_NONFINITE = -6     /* a norm became NaN or Inf */
+    KS_E_NONFINITE = -6     /* a norm (or checked value) is NaN or Inf */
 } ks_status;
 
 typedef enum {
@@ -162,7 +162,11 @@ int ks_apply_h(ks_grid *g, const void *d_psi, void *d_hpsi, int k, int s0,
  * d_dipole: device (nsteps+1)*3 doubles, d(t_i) = h^3 sum r n (zero-boundary
  * grids only; NULL to skip).  d_norms: device (nsteps+1)*nk*nstates doubles,
  * h^3 sum |psi|^2 per state (NULL to skip).  d_vion must stay valid until
- * the stream drains.  Needs a workspace. */
+ * the stream drains.  Needs a workspace.  With nsteps >= 1 the call ends by
+ * copying the norms after the last step to the host (they are computed
+ * also when d_norms is NULL) and synchronising the stream: it returns
+ * KS_E_NONFINITE, naming the state, when one of them is NaN or Inf (the
+ * states and outputs then hold what the steps produced). */
 int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
                       int nsteps, double dt, double t0, double *d_dipole,
                       double *d_norms);
@@ -175,8 +179,9 @@ int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
  * takes A(t_i) and the local potential extrapolated from the potentials at
  * the ends of the most recent steps of this call (cubic through four; fewer
  * in its first three steps).  Each exponential is Taylor-4 with 4 H.psi, so
- * a step costs 8 H.psi like an ETRS step.  Arguments, outputs, errors and
- * the grid's potential afterwards as for ks_propagate_etrs. */
+ * a step costs 8 H.psi like an ETRS step.  Arguments, outputs, errors
+ * (KS_E_NONFINITE included), the end-of-call synchronisation and the grid's
+ * potential afterwards as for ks_propagate_etrs. */
 int ks_propagate_cfm4(ks_grid *g, void *d_psi, const double *d_vion,
                       int nsteps, double dt, double t0, double *d_dipole,
                       double *d_norms);
@@ -341,7 +346,11 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
                     ks_batch **out);
 
 /* Advance every job by nsteps ETRS steps (KS_E_ARG if a job would pass its
- * max_steps).  The first call with graphs on captures one step. */
+ * max_steps).  The first call with graphs on captures one step.  Does not
+ * wait for the device.  A job that records norms and whose norm becomes NaN
+ * or Inf is reported as KS_E_NONFINITE (naming the job) by the first
+ * ks_batch_step call after the step that produced it has completed, and at
+ * the latest by ks_batch_destroy; the steps are not enqueued then. */
 int ks_batch_step(ks_batch *b, int nsteps);
 
 /* Graph replay (1, the default) or eager launches (0) for later steps. */
@@ -350,8 +359,17 @@ int ks_batch_set_graph(ks_batch *b, int use_graph);
 /* Steps job `job` has taken so far. */
 int ks_batch_steps_done(const ks_batch *b, int job, int *out);
 
-/* Wait for the stream and free the batch (not the grids). */
+/* Wait for the stream and free the batch (not the grids).  Returns
+ * KS_E_NONFINITE (after freeing) if a job's recorded norm became NaN or Inf
+ * and no earlier call has reported it. */
 int ks_batch_destroy(ks_batch *b);
+
+/* KS_OK if all n host values are finite, else KS_E_NONFINITE with the
+ * index of the first NaN or Inf in ks_last_error() (KS_E_ARG for a NULL
+ * pointer or n < 0).  The propagators apply it to the norms they copy back
+ * at the end of a call; a caller may apply it to any trace it copies back
+ * (dipoles, norms, energies).  Needs no GPU. */
+int ks_check_finite(const double *values, long n);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *ks_last_error(void);

@@ -82,7 +82,7 @@ struct ks_grid {
     struct {
         size_t t1, t2, t3, half, npart, normpart, D, W, Dpart, rho, vpred,
             dpart, gpart, dotpart, xpart, step, vhist, veff, pwork, vh, cpart,
-            cnl, total;
+            cnl, normchk, total;
     } lay{};
     int ntiles_max = 64;
     int nchunk = 1;
@@ -103,6 +103,8 @@ struct ks_grid {
     hipStream_t side = nullptr;
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     int halves = 1;
+    // end-of-call norms copied back by the propagators (pinned, stot)
+    double *h_norms = nullptr;
 };
 
 namespace {
@@ -502,6 +504,7 @@ void layout(ks_grid *g)
     g->lay.vh = take(g->hartree ? N * 8 : 0);
     g->lay.cpart = take(S * (size_t)g->geo.ny * g->geo.nz * 3 * 8);
     g->lay.cnl = take(S * std::max(1, g->natoms) * 3 * 8);
+    g->lay.normchk = take(S * 8);
     g->lay.total = off;
 }
 
@@ -707,6 +710,30 @@ int exp_chain(ks_grid *g, hipStream_t st, int s0, int ns, const double2 *in,
     return KS_OK;
 }
 
+// End of a propagation call: the norms after its last step (row nsteps of
+// d_norms, or finalized from the last step's partials into the workspace)
+// are copied back and checked; KS_E_NONFINITE names the first state whose
+// norm is NaN or Inf.  Synchronises the stream.
+int check_end_norms(ks_grid *g, int nsteps, const double *d_norms,
+                    const double *normpart)
+{
+    if (nsteps < 1)
+        return KS_OK;
+    const int S = g->stot;
+    const double *src = d_norms ? d_norms + (size_t)nsteps * S : nullptr;
+    if (!src) {
+        double *chk = wsp<double>(g, g->lay.normchk);
+        const double h3 = g->geo.h[0] * g->geo.h[1] * g->geo.h[2];
+        KS_HIP(launch_norm_finalize(normpart, S, g->ntile_y * g->nzc, h3,
+                                    chk, g->stream));
+        src = chk;
+    }
+    KS_HIP(hipMemcpyAsync(g->h_norms, src, sizeof(double) * S,
+                          hipMemcpyDeviceToHost, g->stream));
+    KS_HIP(hipStreamSynchronize(g->stream));
+    return ks_check_finite(g->h_norms, S);
+}
+
 // One Taylor-4 exponential of H (potential v, vector potential A) for all
 // states.  With two halves (and projectors, whose small kernels are what
 // the overlap hides) the second half runs on the side stream, forked from
@@ -744,6 +771,17 @@ int taylor_exponential(ks_grid *g, const double2 *in, double2 *out,
 extern "C" {
 
 const char *ks_last_error(void) { return g_err.c_str(); }
+
+int ks_check_finite(const double *values, long n)
+{
+    if (!values || n < 0)
+        return fail(KS_E_ARG, "values is NULL or n < 0");
+    for (long i = 0; i < n; ++i)
+        if (!std::isfinite(values[i]))
+            return fail(KS_E_NONFINITE, "value %ld is %s", i,
+                        std::isnan(values[i]) ? "NaN" : "infinite");
+    return KS_OK;
+}
 
 int ks_grid_create(const ks_grid_desc *d, ks_grid **out)
 {
@@ -838,6 +876,13 @@ int ks_grid_create(const ks_grid_desc *d, ks_grid **out)
             g->kph[3 * k + a] = make_double2(std::cos(ang), std::sin(ang));
         }
     (void)hipGetDevice(&g->device);
+    if (hipHostMalloc(reinterpret_cast<void **>(&g->h_norms),
+                      sizeof(double) * g->stot, hipHostMallocDefault) !=
+        hipSuccess) {
+        g->h_norms = nullptr;
+        ks_grid_destroy(g);
+        return fail(KS_E_OOM, "pinned host buffer of %d norms", g->stot);
+    }
     int rc;
     if ((rc = dev_upload(g, &g->d_kph, g->kph)) ||
         (rc = dev_upload(g, &g->d_wocc, g->wocc)) ||
@@ -889,6 +934,8 @@ int ks_grid_destroy(ks_grid *g)
         (void)hipEventDestroy(e);
     for (void *p : g->owned)
         (void)hipFree(p);
+    if (g->h_norms)
+        (void)hipHostFree(g->h_norms);
     poisson_plan_destroy(&g->pp);
     delete g;
     return KS_OK;
@@ -1606,10 +1653,12 @@ int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
             vnext = vpred;
         }
         // exponential 2: H_{t+dt}, tau = dt/2, from psi_half into psi
+        // (norm partials when recorded, and always on the last step)
+        const bool norm_now = d_norms || step == nsteps - 1;
         rc = taylor_exponential(g, half, psi, vnext, An, half_a2(An),
                                 0.5 * dt, kFinal,
                                 want_n_end ? npart : nullptr,
-                                d_norms ? normpart : nullptr);
+                                norm_now ? normpart : nullptr);
         if (rc)
             return rc;
         if (want_n_end) {
@@ -1636,7 +1685,7 @@ int ks_propagate_etrs(ks_grid *g, void *d_psi, const double *d_vion,
                                         g->stream));
         }
     }
-    return KS_OK;
+    return check_end_norms(g, nsteps, d_norms, normpart);
 }
 
 int ks_propagate_cfm4(ks_grid *g, void *d_psi, const double *d_vion,
@@ -1734,7 +1783,9 @@ int ks_propagate_cfm4(ks_grid *g, void *d_psi, const double *d_vion,
                         : taylor_exponential(g, half, psi, veff, Aw, a2w,
                                              0.5 * dt, kFinal,
                                              want_n_end ? npart : nullptr,
-                                             d_norms ? normpart : nullptr);
+                                             (d_norms || step == nsteps - 1)
+                                                 ? normpart
+                                                 : nullptr);
             if (rc)
                 return rc;
         }
@@ -1773,7 +1824,7 @@ int ks_propagate_cfm4(ks_grid *g, void *d_psi, const double *d_vion,
     KS_HIP(hipMemcpyAsync(g->d_v, vh[ring[0]], sizeof(double) * g->geo.N,
                           hipMemcpyDeviceToDevice, g->stream));
     g->vloc_set = true;
-    return KS_OK;
+    return check_end_norms(g, nsteps, d_norms, normpart);
 }
 
 }  // extern "C"
@@ -1815,6 +1866,12 @@ struct ks_batch {
     bool use_graph = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // per-job sticky flags of a NaN / Inf norm (device), their copy after
+    // the latest ks_batch_step (pinned host) and its completion event
+    int *d_flags = nullptr;
+    int *h_flags = nullptr;
+    hipEvent_t flag_ev = nullptr;
+    bool flag_pending = false;
 };
 
 namespace {
@@ -1840,6 +1897,30 @@ BArgs batch_args(const ks_batch *b, int kind, int pass)
     a.pass = pass;
     a.hargs = b->d_hargs;
     return a;
+}
+
+// Report a non-finite norm of any job from the flags copied back after an
+// earlier ks_batch_step: only once that copy has completed, unless `wait`.
+int batch_poll_flags(ks_batch *b, bool wait)
+{
+    if (!b->flag_pending)
+        return KS_OK;
+    if (wait) {
+        KS_HIP(hipEventSynchronize(b->flag_ev));
+    } else {
+        const hipError_t e = hipEventQuery(b->flag_ev);
+        if (e == hipErrorNotReady) {
+            (void)hipGetLastError();   // not an error: leave none behind
+            return KS_OK;
+        }
+        KS_HIP(e);
+    }
+    b->flag_pending = false;
+    for (size_t i = 0; i < b->jobs.size(); ++i)
+        if (b->h_flags[i])
+            return fail(KS_E_NONFINITE, "job %zu: a norm became NaN or Inf",
+                        i);
+    return KS_OK;
 }
 
 // Enqueue one ETRS step of every job on the batch stream.
@@ -2078,6 +2159,17 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
         ks_batch_destroy(b);
         return fail(KS_E_HIP, "upload of the job table failed");
     }
+    // non-finite norm flags, cleared once (they stay set once raised)
+    if ((rc = batch_alloc(b, &b->d_flags, njobs)) ||
+        hipMemset(b->d_flags, 0, njobs * sizeof(int)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&b->h_flags),
+                      njobs * sizeof(int), hipHostMallocDefault) !=
+            hipSuccess ||
+        hipEventCreateWithFlags(&b->flag_ev, hipEventDisableTiming) !=
+            hipSuccess) {
+        ks_batch_destroy(b);
+        return rc ? rc : fail(KS_E_HIP, "batch flag buffers");
+    }
     // tables of the batched reductions (the same arguments the single-job
     // propagator passes)
     {
@@ -2127,6 +2219,7 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
                 n.h3 = h3;
                 n.out = jb.d_norms;
                 n.step = step;
+                n.flag = b->d_flags + i;
                 nrm.push_back(n);
                 b->max_ns = std::max(b->max_ns, g->stot);
             }
@@ -2254,6 +2347,9 @@ int ks_batch_step(ks_batch *b, int nsteps)
                         b->jobs[i].max_steps);
     if (nsteps == 0)
         return KS_OK;
+    int frc = batch_poll_flags(b, false);
+    if (frc)
+        return frc;
     if (b->use_graph) {
         if (!b->exec) {
             KS_HIP(hipStreamBeginCapture(b->stream,
@@ -2283,6 +2379,11 @@ int ks_batch_step(ks_batch *b, int nsteps)
     }
     for (auto &d : b->steps_done)
         d += nsteps;
+    KS_HIP(hipMemcpyAsync(b->h_flags, b->d_flags,
+                          b->jobs.size() * sizeof(int),
+                          hipMemcpyDeviceToHost, b->stream));
+    KS_HIP(hipEventRecord(b->flag_ev, b->stream));
+    b->flag_pending = true;
     return KS_OK;
 }
 
@@ -2299,14 +2400,20 @@ int ks_batch_destroy(ks_batch *b)
     if (!b)
         return KS_OK;
     (void)hipStreamSynchronize(b->stream);
+    const int rc = b->h_flags && b->flag_ev ? batch_poll_flags(b, true)
+                                            : KS_OK;
     if (b->exec)
         (void)hipGraphExecDestroy(b->exec);
     if (b->graph)
         (void)hipGraphDestroy(b->graph);
     for (void *p : b->owned)
         (void)hipFree(p);
+    if (b->h_flags)
+        (void)hipHostFree(b->h_flags);
+    if (b->flag_ev)
+        (void)hipEventDestroy(b->flag_ev);
     delete b;
-    return KS_OK;
+    return rc;
 }
 
 }  // extern "C"

@@ -184,6 +184,7 @@ struct NormJob {
     double h3 = 0.0;
     double *out = nullptr;           // [steps + 1][ns]; slot step + 1
     const int *step = nullptr;
+    int *flag = nullptr;             // set to 1 (sticky) by a NaN / Inf norm
 };
 // blk_off[j] = first launch block of job j (blk_off[njobs] = nblocks)
 hipError_t launch_density_batch(const DArgs *args, const int *blk_off,

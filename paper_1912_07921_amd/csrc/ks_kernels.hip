@@ -182,7 +182,7 @@ __device__ __forceinline__ void norm_finalize_state(const double *part,
                                                     int ns, int ntiles,
                                                     double h3, double *out,
                                                     const int *step, int s,
-                                                    double *sbuf)
+                                                    double *sbuf, int *flag)
 {
     if (step)
         out += (size_t)ns * (*step + 1);
@@ -190,8 +190,13 @@ __device__ __forceinline__ void norm_finalize_state(const double *part,
     for (int t = threadIdx.x; t < ntiles; t += blockDim.x)
         acc[0] += part[(size_t)s * ntiles + t];
     block_sum<double, 1>(acc, sbuf);
-    if (threadIdx.x == 0)
-        out[s] = h3 * acc[0];
+    if (threadIdx.x == 0) {
+        const double v = h3 * acc[0];
+        out[s] = v;
+        // every writer stores the same value, so the order does not matter
+        if (flag && !isfinite(v))
+            *flag = 1;
+    }
 }
 
 __global__ __launch_bounds__(64) void k_norm_finalize(const double *part,
@@ -201,7 +206,7 @@ __global__ __launch_bounds__(64) void k_norm_finalize(const double *part,
 {
     __shared__ double sbuf[1];
     norm_finalize_state(part, gridDim.x, ntiles, h3, out, step, blockIdx.x,
-                        sbuf);
+                        sbuf, nullptr);
 }
 
 // state blockIdx.x of job blockIdx.y
@@ -213,7 +218,7 @@ __global__ __launch_bounds__(64) void k_norm_finalize_batch(
     if ((int)blockIdx.x >= J.ns)
         return;
     norm_finalize_state(J.part, J.ns, J.ntiles, J.h3, J.out, J.step,
-                        blockIdx.x, sbuf);
+                        blockIdx.x, sbuf, J.flag);
 }
 
 // psi <- exp(i kappa z) psi

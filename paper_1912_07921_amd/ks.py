@@ -117,6 +117,7 @@ EXPORTS = {
     "ks_batch_steps_done": (C.c_int, [C.c_void_p, C.c_int,
                                       C.POINTER(C.c_int)]),
     "ks_batch_destroy": (C.c_int, [C.c_void_p]),
+    "ks_check_finite": (C.c_int, [C.c_void_p, C.c_long]),
     "ks_last_error": (C.c_char_p, []),
 }
 
@@ -410,6 +411,14 @@ def ks_batch_destroy(b):
     return _check(lib().ks_batch_destroy(b))
 
 
+def ks_check_finite(values):
+    """Raise KSError (KS_E_NONFINITE) if a value of the host float64 array
+    is NaN or Inf."""
+    a = np.ascontiguousarray(values, dtype=np.float64)
+    return _check(lib().ks_check_finite(a.ctypes.data_as(C.c_void_p),
+                                        a.size))
+
+
 # ---------------------------------------------------------------------------
 # convenience objects
 # ---------------------------------------------------------------------------
@@ -674,11 +683,11 @@ class Batch:
         if getattr(self, "h", None) is not None:
             for i, j in enumerate(self.jobs):
                 j.first_step = ks_batch_steps_done(self.h, i)
-            ks_batch_destroy(self.h)
-            self.h = None
+            h, self.h = self.h, None
             for j in self.jobs:
                 if j.grid.h is not None:
                     j.grid.set_stream(self._cur)
+            ks_batch_destroy(h)
 
     def __del__(self):
         try:

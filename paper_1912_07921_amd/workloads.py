@@ -248,21 +248,29 @@ def c1(nsteps=50):
 
 
 def molecule(n, h, natoms, nstates, radius, lmax, rc, sigma, seed,
-             xc=1, name="molecule"):
+             xc=1, name="molecule", device=None):
+    """A finite molecule-like system.  With `device` (a torch device) the
+    potential and states are built there by torch from the same random
+    draws (values equal to the CPU build up to rounding) and returned as
+    device tensors."""
     rng = np.random.Generator(np.random.PCG64(seed))
     pos, Z = _atoms_in_ball(rng, natoms, radius)
     E = rng.uniform(-2.0, 2.0, (natoms, 3))
     spec = SystemSpec(n=(n, n, n), h=(h,) * 3, nstates=nstates, pos=pos, Z=Z,
                       lmax=np.full(natoms, lmax), rc=np.full(natoms, rc),
                       sigma=np.full(natoms, sigma), E=E, xc=xc)
+    if device is not None:
+        v = vion_erf_device(spec, device)
+        psi = smooth_random_states_device(spec, rng, nstates, device)
+        return spec, v, psi.reshape(1, nstates, -1)
     v = vion_erf(spec)
     psi = smooth_random_states(spec, rng, nstates).reshape(1, nstates, -1)
     return spec, v, psi
 
 
-def c2(nsteps=500, nstates=32):
+def c2(nsteps=500, nstates=32, device=None):
     spec, v, psi = molecule(64, 0.2, 8, nstates, 4.0, 1, 2.0, 0.5,
-                            SEED_BASE + 2)
+                            SEED_BASE + 2, device=device)
     return Workload("c2_molecule_64", spec, v, psi, dt=0.005, nsteps=nsteps,
                     kick=0.01)
 
@@ -293,9 +301,9 @@ def c3(nsteps=1000, nstates=64, n=48, h=0.3):
     return Workload("c3_crystal_48", spec, v, psi, dt=0.02, nsteps=nsteps)
 
 
-def c5(nsteps=100, nstates=256):
+def c5(nsteps=100, nstates=256, device=None):
     spec, v, psi = molecule(128, 0.18, 64, nstates, 10.0, 2, 2.5, 0.625,
-                            SEED_BASE + 5)
+                            SEED_BASE + 5, device=device)
     return Workload("c5_large_128", spec, v, psi, dt=0.005, nsteps=nsteps,
                     kick=0.01)
 

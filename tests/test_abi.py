@@ -110,3 +110,30 @@ def test_product_does_not_import_the_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert not pat.search(text), f
+
+
+def test_check_finite_reports_injected_nan_and_inf():
+    """The host check the propagators apply to the norms they copy back:
+    a NaN or an Inf among finite norms is KS_E_NONFINITE naming its index;
+    finite values (zeros, huge and tiny norms included) pass."""
+    import numpy as np
+    from paper_1912_07921_amd import ks
+    L = ks.lib()
+    ok = np.array([1.0, 0.0, 1e300, 5e-324, -2.0])
+    assert ks.ks_check_finite(ok) == 0
+    assert ks.ks_check_finite(np.zeros(0)) == 0
+    for bad, what in ((np.nan, b"NaN"), (np.inf, b"infinite"),
+                      (-np.inf, b"infinite")):
+        v = np.ones(7)
+        v[4] = bad
+        with pytest.raises(ks.KSError) as e:
+            ks.ks_check_finite(v)
+        assert e.value.code == -6
+        msg = L.ks_last_error()
+        assert b"value 4" in msg and what in msg
+    # the first bad index is named
+    v = np.array([1.0, np.inf, np.nan])
+    with pytest.raises(ks.KSError):
+        ks.ks_check_finite(v)
+    assert b"value 1" in L.ks_last_error()
+    assert L.ks_check_finite(None, 3) == -1

@@ -1,13 +1,21 @@
 """Parity at the full sizes of the periodic (48^3, 4 k-points x 64 states,
 16 atoms, laser) and large (128^3, 256 states, 64 atoms with s+p+d
-projectors) workloads, in the launch shape the autotuner picks (the one the
-benchmark times).
+projectors) workloads, in the launch shape the autotuner picks on the full
+system (the shape the benchmark times).
 
-The oracle cannot propagate every state of these systems in seconds, so the
-checks use what holds at any size: with the exchange term off the states
-evolve independently, and every sampled state (its own k-point) must match
-the oracle run on that state alone; H.psi is compared on sampled states.
-Tolerances as for the small systems: 1e-12 (H.psi), 1e-10 (propagation).
+The oracle cannot propagate every state of these systems in seconds, so two
+kinds of checks are made:
+  - linear: with the exchange term off the states evolve independently, and
+    every sampled state of the full run (its own k-point) must match the
+    oracle run on that state alone; H.psi is compared on sampled states;
+  - non-linear: the same grid, atoms, potential and laser with LDA exchange
+    on (the density of all states drives the potential of every state), with
+    fewer states, in FP64 and in the mixed form, compared with the oracle
+    on the states, the density, the energy and the dipole.
+Tolerances: 1e-12 (FP64 H.psi), 1e-10 (FP64 propagation: states relative,
+dipole relative to its largest component, density and energy relative);
+mixed form: states 1e-6 relative, dipole 1e-6 a.u. absolute, density and
+energy 1e-6 relative.
 """
 import numpy as np
 import pytest
@@ -37,17 +45,47 @@ def rel(got, want):
     return float(np.linalg.norm(got - want) / np.linalg.norm(want))
 
 
-def linear_propagation_parity(torch, oracle_mod, w, samples, nsteps, t0):
-    """samples: (k, s) pairs; every state of w is propagated on the GPU."""
-    from paper_1912_07921_amd import ks
+class Full:
+    """A full-size workload on the GPU with its autotuned launch shape."""
+
+    def __init__(self, torch, w):
+        from paper_1912_07921_amd import ks
+        self.w = w
+        w.spec.xc = 0
+        self.g = ks.Grid(w.spec)
+        self.psi0 = torch.from_numpy(w.psi0).cuda()
+        tr, zc, rpt, _ = self.g.autotune(self.psi0, reps=1)
+        self.shape = (tr, zc, rpt)
+
+
+@pytest.fixture(scope="module")
+def c5_full(torch_cuda):
+    f = Full(torch_cuda, W.c5(nsteps=2))
+    yield f
+    f.g.close()
+    del f.psi0
+    torch_cuda.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def c3_full(torch_cuda):
+    f = Full(torch_cuda, W.c3(nsteps=3))
+    yield f
+    f.g.close()
+    del f.psi0
+    torch_cuda.cuda.empty_cache()
+
+
+def linear_propagation_parity(torch, oracle_mod, f, samples, nsteps, t0):
+    """samples: (k, s) pairs; every state of the workload is propagated on
+    the GPU (exchange off)."""
+    w = f.w
     spec = w.spec
-    spec.xc = 0
-    g = ks.Grid(spec)
-    psi = torch.from_numpy(w.psi0).cuda()
-    g.autotune(psi, reps=1)
-    d, n = g.propagate_etrs(psi, torch.from_numpy(w.vion).cuda(), nsteps,
-                            w.dt, t0, dipole=False, norms=True)
+    psi = f.psi0.clone()
+    d, n = f.g.propagate_etrs(psi, torch.from_numpy(w.vion).cuda(), nsteps,
+                              w.dt, t0, dipole=False, norms=True)
     got = psi.cpu().numpy()
+    del psi
     nrm = n.cpu().numpy()
     sub = sub_spec(spec, [k for k, _ in samples])
     o = oracle_mod.Oracle(sub)
@@ -59,32 +97,108 @@ def linear_propagation_parity(torch, oracle_mod, w, samples, nsteps, t0):
         assert abs(nrm[-1, k * spec.nstates + s] - wn[-1, i]) < 1e-10
 
 
-def test_periodic_kpoints_laser_full_size(torch_cuda, oracle_mod):
-    w = W.c3(nsteps=3)
+def test_periodic_kpoints_laser_full_size(torch_cuda, oracle_mod, c3_full):
     # A(t) inside the pulse, large enough to matter: start at the envelope
     # peak region
-    t0 = 0.5 * w.spec.laser[2]
-    linear_propagation_parity(torch_cuda, oracle_mod, w,
+    t0 = 0.5 * c3_full.w.spec.laser[2]
+    linear_propagation_parity(torch_cuda, oracle_mod, c3_full,
                               [(0, 3), (1, 40), (3, 63)], 3, t0)
 
 
-def test_large_system_full_size(torch_cuda, oracle_mod):
-    w = W.c5(nsteps=2)
-    linear_propagation_parity(torch_cuda, oracle_mod, w, [(0, 0), (0, 255)],
-                              2, 0.0)
+def test_large_system_full_size(torch_cuda, oracle_mod, c5_full):
+    linear_propagation_parity(torch_cuda, oracle_mod, c5_full,
+                              [(0, 0), (0, 255)], 2, 0.0)
 
 
-def test_large_system_apply_h_sampled(torch_cuda, oracle_mod):
-    from paper_1912_07921_amd import ks
-    torch = torch_cuda
-    w = W.c5(nsteps=1)
-    g = ks.Grid(w.spec)
-    psi = torch.from_numpy(w.psi0).cuda()
-    g.autotune(psi, reps=1)
+def test_large_system_apply_h_sampled(torch_cuda, oracle_mod, c5_full):
+    w = c5_full.w
+    g = c5_full.g
     v = w.vion
-    g.update_vlocal(torch.from_numpy(v).cuda())
-    hp = g.apply_h(psi[0]).cpu().numpy()
+    g.update_vlocal(torch_cuda.from_numpy(v).cuda())
+    hp = g.apply_h(c5_full.psi0[0])
     o = oracle_mod.Oracle(sub_spec(w.spec, [0]))
     for s in (0, 131, 255):
         want = o.apply_h(v, w.psi0[0, s][None])[0]
-        assert rel(hp[s], want) < 1e-12, s
+        assert rel(hp[s].cpu().numpy(), want) < 1e-12, s
+    del hp
+
+
+# --------------------------------------------------------------------------
+# non-linear (LDA exchange on) at the full grids, fewer states
+# --------------------------------------------------------------------------
+# oracle runs shared by the FP64 and mixed cases of one system
+_ORACLE_RUNS = {}
+TOL = {0: dict(psi=1e-10, dip=None, rho=1e-10, energy=1e-10, norm=1e-10),
+       1: dict(psi=1e-6, dip=1e-6, rho=1e-6, energy=1e-6, norm=1e-7)}
+
+
+def nonlinear_parity(torch, oracle_mod, w, shape, nsteps, t0, precision):
+    """Propagate w (exchange on) on the GPU in `shape` and compare states,
+    final density, energy, norms and (finite grids) the dipole trace with
+    the oracle; returns the errors."""
+    from paper_1912_07921_amd import ks
+    spec = w.spec
+    assert spec.xc == 1
+    finite = not any(spec.periodic)
+    g = ks.Grid(spec, precision=precision)
+    g.set_launch(*shape)
+    psi = torch.from_numpy(w.psi0.copy()).cuda()
+    vion = torch.from_numpy(w.vion).cuda()
+    if w.kick:
+        g.kick(psi, w.kick)
+    d, n = g.propagate_etrs(psi, vion, nsteps, w.dt, t0, dipole=finite,
+                            norms=True)
+    got = psi.cpu().numpy()
+    # density and energy of the propagated states, by the FP64 library
+    g64 = ks.Grid(spec)
+    rho = g64.density(psi).cpu().numpy()
+    E = g64.energy(psi, vion, t0 + nsteps * w.dt)
+    g64.close()
+    g.close()
+    key = (w.name, spec.nstates, nsteps, t0)
+    if key not in _ORACLE_RUNS:
+        o = oracle_mod.Oracle(spec)
+        p0 = o.kick(w.psi0, w.kick) if w.kick else w.psi0
+        want, wd, wn = o.propagate_etrs(p0, w.vion, nsteps, w.dt, t0)
+        _ORACLE_RUNS[key] = (want, wd, wn, o.density(want),
+                             o.energy(want, w.vion, t0 + nsteps * w.dt))
+    want, wd, wn, wrho, wE = _ORACLE_RUNS[key]
+    tol = TOL[precision]
+    err = dict(
+        psi=max(rel(got[k, s], want[k, s]) for k in range(spec.nk)
+                for s in range(spec.nstates)),
+        rho=float(np.abs(rho - wrho).max() / np.abs(wrho).max()),
+        energy=abs(E - wE) / abs(wE),
+        norm=float(np.abs(n.cpu().numpy() - wn).max()))
+    if finite:
+        dd = np.abs(d.cpu().numpy() - wd).max()
+        err["dip"] = float(dd / np.abs(wd).max()) if precision == 0 \
+            else float(dd)
+    print(f"{w.name} precision {precision}: " +
+          ", ".join(f"{k} {v:.2e}" for k, v in err.items()), flush=True)
+    for key, e in err.items():
+        bound = tol[key] if tol[key] is not None else tol["psi"]
+        assert e < bound, (key, e)
+    return err
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_large_system_lda_states_density_energy_dipole(torch_cuda,
+                                                      oracle_mod, c5_full,
+                                                      precision):
+    """128^3 grid, the 64 atoms with s+p+d projectors, LDA exchange on,
+    kick 0.01 z: 12 states, 2 ETRS steps."""
+    w = W.c5(nsteps=2, nstates=12)
+    nonlinear_parity(torch_cuda, oracle_mod, w, c5_full.shape, 2, 0.0,
+                     precision)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_periodic_lda_laser_states_density_energy(torch_cuda, oracle_mod,
+                                                  c3_full, precision):
+    """48^3 periodic cell, the 16 atoms, 4 k-points x 3 states, LDA
+    exchange on, laser inside its envelope: 3 ETRS steps."""
+    w = W.c3(nsteps=3, nstates=3)
+    t0 = 0.5 * w.spec.laser[2]
+    nonlinear_parity(torch_cuda, oracle_mod, w, c3_full.shape, 3, t0,
+                     precision)

@@ -1,7 +1,10 @@
 """Serving form on the GPU: requests of different grids and state counts
 joining and leaving one continuously rebuilt batch must each end bitwise
 where they end when propagated alone (ks_propagate_etrs), dipole and norm
-traces included; admission respects the slot count and the HBM budget."""
+traces included, and must match the CPU oracle's run of the same request
+(FP64: states, dipole and norms to 1e-10; mixed form: dipole to 1e-6 a.u.,
+states 1e-6 relative); admission respects the slot count and the HBM
+budget."""
 import numpy as np
 import pytest
 
@@ -103,3 +106,45 @@ def test_whole_axis_chunks_of_a_larger_grid(torch_cuda):
         assert np.array_equal(r.final_psi, p), r.rid
         assert np.array_equal(r.dipole, d), r.rid
         assert np.array_equal(r.norms, n), r.rid
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_served_requests_match_the_oracle(torch_cuda, oracle_mod,
+                                          precision):
+    """Requests that join a running batch, leave it and resume in rebuilt
+    batches (first_step > 0), served in FP64 and in the mixed form, against
+    the oracle's propagation of each request (kick, then ETRS with LDA
+    exchange and s+p projectors)."""
+    torch = torch_cuda
+    from paper_1912_07921_amd.serving import Server
+    arrivals = [0, 0, 2, 3, 5]
+    nsteps = [7, 4, 6, 5, 3]
+    reqs = make_requests(torch, arrivals, nsteps)
+    srv = Server(1 << 34, max_slots=3, clock="steps", keep_states=True,
+                 precision=precision)
+    st = srv.run(reqs)
+    assert st["requests"] == len(reqs) and st["rebuilds"] >= 3
+    worst = dict(psi=0.0, dip=0.0, norm=0.0)
+    for r in reqs:
+        o = oracle_mod.Oracle(r.spec)
+        p0 = o.kick(r.psi.numpy(), r.kick)
+        want, wd, wn = o.propagate_etrs(p0, r.vion.numpy(), r.nsteps, r.dt)
+        got = r.final_psi.reshape(want.shape)
+        e_psi = max(float(np.linalg.norm(got[0, s] - want[0, s]) /
+                          np.linalg.norm(want[0, s]))
+                    for s in range(r.spec.nstates))
+        e_dip = float(np.abs(r.dipole - wd).max())
+        e_nrm = float(np.abs(r.norms - wn).max())
+        if precision == 0:
+            e_dip /= float(np.abs(wd).max())
+        worst = dict(psi=max(worst["psi"], e_psi),
+                     dip=max(worst["dip"], e_dip),
+                     norm=max(worst["norm"], e_nrm))
+    print(f"served vs oracle, precision {precision}: " +
+          ", ".join(f"{k} {v:.2e}" for k, v in worst.items()), flush=True)
+    if precision == 0:
+        assert worst["psi"] < 1e-10 and worst["dip"] < 1e-10
+        assert worst["norm"] < 1e-10
+    else:
+        assert worst["dip"] < 1e-6 and worst["psi"] < 1e-6
+        assert worst["norm"] < 1e-7

@@ -196,7 +196,7 @@ def test_nonlocal_part_has_projector_rank_and_algebra(oracle_mod):
     idx, p = o.atom_table(0)
     P = np.zeros((nproj, o.N))
     P[:, idx] = p
-    assert np.allclose((P * P).sum(1) * h3, 1.0, atol=1e-13)
+    assert np.allclose((P * P).sum(1) * h3, 1.0, rtol=0, atol=1e-13)
     G = (P @ P.T) * h3
     Ej = np.array([spec.E[0, 0]] + [spec.E[0, 1]] * 3 + [spec.E[0, 2]] * 5)
     lhs = (P @ V @ P.T) * h3
@@ -306,16 +306,39 @@ def test_time_reversal_and_k_shift(oracle_mod):
 # harmonic oscillator: textbook energies, Taylor/ETRS closed form, Kohn
 # --------------------------------------------------------------------------
 def test_harmonic_oscillator_energies(oracle_mod):
-    """Rayleigh quotients of the sampled HO states on a converged box equal
-    the textbook E = (n + 3/2) w."""
-    spec = _spec((40, 40, 40), (0.3, 0.3, 0.3), nstates=4)
+    """Rayleigh quotients of the sampled HO states on a converged box (56^3
+    at h = 0.3: |psi|^2 ~ e^-34 at the faces) equal the textbook
+    E = (n + 3/2) w up to the finite-difference error, and equal exactly
+    (to rounding) the energy the stencil's symbol gives: per axis the
+    kinetic part is the mean of T(k) = -(c_0 + 2 sum c_m cos(m k h)) / 2h^2
+    over the state's momentum density (exp(-k^2/w)/sqrt(pi w) for the
+    ground factor, 2 k^2 exp(-k^2/w)/(w sqrt(pi w)) for the first excited
+    one), the potential part is the continuum virial value (the sampled
+    Gaussian sums are exact to e^-200 at this spacing)."""
+    h = 0.3
+    spec = _spec((56, 56, 56), (h, h, h), nstates=4)
     w = 0.5
     v = W.vion_harmonic(spec, w)
     psi = W.ho_states(spec, w, np.random.default_rng(0))
     o = oracle_mod.Oracle(spec)
     hp = o.apply_h(v, psi)
-    E = np.real(np.sum(psi.conj() * hp, axis=1)) * 0.027
-    assert np.allclose(E, [1.5 * w, 2.5 * w, 2.5 * w, 2.5 * w], atol=1e-7)
+    E = np.real(np.sum(psi.conj() * hp, axis=1)) * h ** 3
+    textbook = np.array([1.5 * w, 2.5 * w, 2.5 * w, 2.5 * w])
+    assert np.abs(E - textbook).max() < 2e-7
+    # closed form of the discrete kinetic energy (Fornberg's weights,
+    # typed from the published table, not from the oracle)
+    c = [-205 / 72, 8 / 5, -1 / 5, 8 / 315, -1 / 560]
+    k = np.linspace(-np.pi / h, np.pi / h, 40001)
+    T = -(c[0] + 2 * sum(c[m] * np.cos(m * k * h) for m in range(1, 5))) \
+        / (2 * h * h)
+    g0 = np.exp(-k * k / w) / np.sqrt(np.pi * w)
+    g1 = 2 * k * k * np.exp(-k * k / w) / (w * np.sqrt(np.pi * w))
+    t0 = np.trapezoid(g0 * T, k)
+    t1 = np.trapezoid(g1 * T, k)
+    # the 8th-order stencil under-counts the kinetic energy slightly
+    assert 0 < w / 4 - t0 < 1e-7 and 0 < 3 * w / 4 - t1 < 1e-6
+    pred = np.array([3 * t0 + 0.75 * w] + [t1 + 2 * t0 + 1.25 * w] * 3)
+    assert np.abs(E - pred).max() < 1e-12
 
 
 def _t4(z):
@@ -437,7 +460,7 @@ def test_lda_exchange_uniform_gas_constants(oracle_mod):
     n0 = 3.0 / (4.0 * np.pi)
     rho = np.full(spec.npoints, n0)
     v = o.vlocal(np.zeros(spec.npoints), rho)
-    assert np.allclose(v, -0.610887, atol=1e-6)
+    assert np.allclose(v, -0.610887, rtol=0, atol=1e-6)
     ex = o.exchange_energy(rho) / (n0 * spec.npoints * 0.125)
     assert abs(ex + 0.458165) < 1e-6
     # the potential is the functional derivative of the energy
@@ -473,7 +496,7 @@ def test_density_norms_and_gram(oracle_mod):
     h3 = 0.45 ** 3
     assert rho.min() >= 0
     nrm = o.norms(w.psi0)
-    assert np.allclose(nrm, 1.0, atol=1e-12)
+    assert np.allclose(nrm, 1.0, rtol=0, atol=1e-12)
     want = np.sum(np.repeat(w.spec.kw, w.spec.nstates) *
                   np.tile(w.spec.occ, w.spec.nk) * nrm)
     assert abs(rho.sum() * h3 - want) < 1e-12 * want
@@ -481,15 +504,46 @@ def test_density_norms_and_gram(oracle_mod):
     assert np.abs(G - np.eye(6)[None]).max() < 1e-12
 
 
+def test_gram_conjugation_and_index_order(oracle_mod):
+    """<psi_i|psi_j> conjugates its left state and is indexed [k][i][j]:
+    for psi_j = e^{i theta} psi_i the entry (i, j) is e^{i theta} |psi_i|^2
+    and (j, i) its conjugate (a swapped conjugation or transposed index
+    gives e^{-i theta} at (i, j)); states of the second k-point land in the
+    second block only."""
+    spec = _spec((7, 6, 5), (0.4, 0.4, 0.4), periodic=(1, 1, 1),
+                 kpts=np.zeros((2, 3)), kw=np.full(2, 0.5), nstates=3)
+    o = oracle_mod.Oracle(spec)
+    rng = np.random.default_rng(11)
+    N = spec.npoints
+    a = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    b = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    th = 0.7
+    psi = np.array([[a, np.exp(1j * th) * a, b],
+                    [b, 3.0 * a, (1 + 2j) * b]])
+    G = o.gram(psi)
+    h3 = 0.4 ** 3
+    na = h3 * np.sum(np.abs(a) ** 2)
+    nb = h3 * np.sum(np.abs(b) ** 2)
+    assert abs(G[0, 0, 1] - np.exp(1j * th) * na) < 1e-13 * na
+    assert abs(G[0, 1, 0] - np.exp(-1j * th) * na) < 1e-13 * na
+    assert abs(G[0, 1, 1] - na) < 1e-13 * na
+    assert abs(G[1, 0, 2] - (1 + 2j) * nb) < 1e-13 * nb
+    assert abs(G[1, 2, 0] - (1 - 2j) * nb) < 1e-13 * nb
+    assert abs(G[1, 1, 1] - 9.0 * na) < 1e-13 * na
+    assert abs(G[1, 2, 2] - 5.0 * nb) < 1e-13 * nb
+    # Hermitian in (i, j) within each k-point block
+    assert np.abs(G - np.conj(np.transpose(G, (0, 2, 1)))).max() < 1e-13 * nb
+
+
 def test_kick_is_unitary_phase(oracle_mod):
     spec, v, psi = W.tiny(nstates=2)
     o = oracle_mod.Oracle(spec)
     k = o.kick(psi, 0.3)
-    assert np.allclose(np.abs(k), np.abs(psi), atol=1e-14)
+    assert np.allclose(np.abs(k), np.abs(psi), rtol=0, atol=1e-14)
     z = W.axis_coords(spec.n[2], spec.h[2], 0)
     ratio = (k / psi).reshape(1, 2, spec.n[2], -1)
     assert np.allclose(ratio, np.exp(0.3j * z)[None, None, :, None],
-                       atol=1e-13)
+                       rtol=0, atol=1e-13)
 
 
 # --------------------------------------------------------------------------
@@ -623,7 +677,7 @@ def test_laser_vector_potential_envelope(oracle_mod):
     for t in (-0.5, T + 1e-9, T + 3.0):
         assert np.all(np.asarray(o.laser_A(t)) == 0.0), t
     assert np.allclose(o.laser_A(T / 2), A0 * np.cos(w0 * T / 2) * pol,
-                       atol=1e-15)
+                       rtol=0, atol=1e-15)
     for t in (0.3, 1.7, 2.9):
         a1 = np.asarray(o.laser_A(t)) / np.cos(w0 * t)
         a2 = np.asarray(o.laser_A(T - t)) / np.cos(w0 * (T - t))
