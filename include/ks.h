@@ -152,6 +152,20 @@ int ks_hartree(ks_grid *g, const double *d_rho, double *d_vh);
 int ks_apply_h(ks_grid *g, const void *d_psi, void *d_hpsi, int k, int s0,
                int ns, double t);
 
+/* ks_apply_h for callers that cannot allocate device memory or lend a
+ * workspace (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc): same arguments, layout, results and errors as
+ * ks_apply_h, but the projector scratch (coefficients, their partial sums
+ * and the terms on the projector rows) lives in a static device array of
+ * 64 MiB that the library holds on each GPU it runs on until the process
+ * ends; the call needs no workspace and allocates nothing.  KS_E_ARG when
+ * the ns states need more than 64 MiB of scratch (then apply H to fewer
+ * states per call), or when the current device is not the grid's.  All
+ * calls on one GPU share its array: calls that overlap on one GPU (other
+ * streams, other threads) race and must be ordered by the caller. */
+int ks_apply_h_noalloc(ks_grid *g, const void *d_psi, void *d_hpsi, int k,
+                       int s0, int ns, double t);
+
 /* Propagate all nk*nstates states in d_psi, in place, by nsteps ETRS steps
  * of dt from t0.  Each step: H_t^j psi, j = 1..4 (Taylor-4, H frozen);
  * psi_half = sum (-i dt/2)^j H^j psi / j!; predictor

@@ -18,7 +18,8 @@ SOURCES = [("ks_hpsi.hip", ["-DKS_HPSI_PART=0"]),
            ("ks_batch.hip", ["-DKS_HPSI_PART=0"]),
            ("ks_batch.hip", ["-DKS_HPSI_PART=1"]),
            ("ks_kernels.hip", []), ("ks_poisson.hip", []),
-           ("ks_observe.hip", []), ("ks_api.cpp", [])]
+           ("ks_observe.hip", []), ("ks_noalloc.hip", []),
+           ("ks_api.cpp", [])]
 # sources whose text determines the device code of the H.psi path
 KERNEL_SOURCES = ["ks_device.h", "ks_internal.h", "ks_hpsi.hip",
                   "ks_batch.hip", "ks_kernels.hip"]

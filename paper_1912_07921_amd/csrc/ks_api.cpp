@@ -763,7 +763,94 @@ int taylor_exponential(ks_grid *g, const double2 *in, double2 *out,
     return KS_OK;
 }
 
+// Argument checks of ks_apply_h and its allocation-free variant.
+int apply_h_check(const ks_grid *g, const void *d_psi, const void *d_hpsi,
+                  int k, int s0, int ns)
+{
+    if (!g || !d_psi || !d_hpsi)
+        return fail(KS_E_ARG, "NULL argument");
+    if (k < 0 || k >= g->nk || s0 < 0 || ns < 0 || s0 + ns > g->ns)
+        return fail(KS_E_ARG, "k=%d s0=%d ns=%d out of range", k, s0, ns);
+    if (d_psi == d_hpsi)
+        return fail(KS_E_ARG, "d_psi and d_hpsi must not overlap");
+    if (!g->vloc_set)
+        return fail(KS_E_STATE, "no local potential (ks_update_vlocal)");
+    return KS_OK;
+}
+
+// d_hpsi = H(t) d_psi for ns states of k-point k, with the projector
+// coefficients D, their chunk partials and the hull-row terms W at the
+// given device addresses (each indexed from the call's first state).
+int apply_h_core(ks_grid *g, const void *d_psi, void *d_hpsi, int k, int s0,
+                 int ns, double t, void *D, void *Dpart, void *W)
+{
+    double A[3];
+    laser_A(g, t, A);
+    GArgs ga = base_gargs(g);
+    ga.in = d_psi;
+    ga.D = D;
+    ga.Dpart = Dpart;
+    ga.W = W;
+    ga.sg0 = k * g->ns + s0;
+    if (g->natoms > 0) {
+        Timed tm(g, 1);
+        KS_HIP(launch_gather(g->mixed, true, ga, ns, g->stream));
+        KS_HIP(launch_kbapply(g->mixed, ga, ns, g->stream));
+    }
+    HArgs a = base_hargs(g);
+    a.in = d_psi;
+    a.out = d_hpsi;
+    a.v = g->d_v;
+    if (a.rowinfo)
+        a.W = W;
+    a.A[0] = A[0];
+    a.A[1] = A[1];
+    a.A[2] = A[2];
+    a.a2half = 0.5 * (A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+
+    a.sg0 = k * g->ns + s0;
+    {
+        Timed tm(g, 0);
+        KS_HIP(launch_hpsi(kApply, g->mixed, true, a, ns, g->stream));
+    }
+    return KS_OK;
+}
+
 }  // namespace
+
+// ks_apply_h on the projector scratch at `base` (cap bytes of device
+// memory) instead of the workspace: the allocation-free entry point.  The
+// scratch holds, for the call's ns states, the coefficients, their chunk
+// partials and the hull-row terms, each 256-byte aligned; every one of
+// them is written by the call before it is read.
+int ks::apply_h_scratch(ks_grid *g, const void *d_psi, void *d_hpsi, int k,
+                        int s0, int ns, double t, char *base, size_t cap,
+                        int device)
+{
+    int rc = apply_h_check(g, d_psi, d_hpsi, k, s0, ns);
+    if (rc)
+        return rc;
+    if (device != g->device)
+        return fail(KS_E_ARG, "the grid lives on device %d, the current "
+                    "device is %d", g->device, device);
+    const size_t vs = g->mixed ? 8 : 16;
+    const size_t na = std::max(1, g->natoms);
+    const size_t nD = align256((size_t)ns * na * kMaxProj * vs);
+    const size_t nP = align256((size_t)ns * na * g->nchunk * kMaxProj * vs);
+    const size_t nW = align256((size_t)ns * std::max<long>(1, g->nhull) * vs);
+    const size_t need = g->natoms > 0 ? nD + nP + nW : 0;
+    if (need > cap)
+        return fail(KS_E_ARG, "%d states need %zu bytes of projector scratch "
+                    "and the static scratch holds %zu: apply H to fewer "
+                    "states per call", ns, need, cap);
+    return apply_h_core(g, d_psi, d_hpsi, k, s0, ns, t, base, base + nD,
+                        base + nD + nP);
+}
+
+int ks::set_error(int code, const char *msg)
+{
+    return fail(code, "%s", msg);
+}
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -1004,44 +1091,13 @@ int ks_update_vlocal(ks_grid *g, const double *d_vion, const double *d_rho)
 int ks_apply_h(ks_grid *g, const void *d_psi, void *d_hpsi, int k, int s0,
                int ns, double t)
 {
-    if (!g || !d_psi || !d_hpsi)
-        return fail(KS_E_ARG, "NULL argument");
-    if (k < 0 || k >= g->nk || s0 < 0 || ns < 0 || s0 + ns > g->ns)
-        return fail(KS_E_ARG, "k=%d s0=%d ns=%d out of range", k, s0, ns);
-    if (d_psi == d_hpsi)
-        return fail(KS_E_ARG, "d_psi and d_hpsi must not overlap");
-    if (!g->vloc_set)
-        return fail(KS_E_STATE, "no local potential (ks_update_vlocal)");
-    int rc = need_ws(g);
+    int rc = apply_h_check(g, d_psi, d_hpsi, k, s0, ns);
     if (rc)
         return rc;
-    double A[3];
-    laser_A(g, t, A);
-    void *D = g->ws + g->lay.D;
-    GArgs ga = base_gargs(g);
-    ga.in = d_psi;
-    ga.D = D;
-    ga.sg0 = k * g->ns + s0;
-    if (g->natoms > 0) {
-        Timed tm(g, 1);
-        KS_HIP(launch_gather(g->mixed, true, ga, ns, g->stream));
-        KS_HIP(launch_kbapply(g->mixed, ga, ns, g->stream));
-    }
-    HArgs a = base_hargs(g);
-    a.in = d_psi;
-    a.out = d_hpsi;
-    a.v = g->d_v;
-    a.A[0] = A[0];
-    a.A[1] = A[1];
-    a.A[2] = A[2];
-    a.a2half = 0.5 * (A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
-
-    a.sg0 = k * g->ns + s0;
-    {
-        Timed tm(g, 0);
-        KS_HIP(launch_hpsi(kApply, g->mixed, true, a, ns, g->stream));
-    }
-    return KS_OK;
+    if ((rc = need_ws(g)))
+        return rc;
+    return apply_h_core(g, d_psi, d_hpsi, k, s0, ns, t, g->ws + g->lay.D,
+                        g->ws + g->lay.Dpart, g->ws + g->lay.W);
 }
 
 int ks_hartree(ks_grid *g, const double *d_rho, double *d_vh)

@@ -7,6 +7,8 @@
 #include <cstddef>
 #include <cstdint>
 
+struct ks_grid;   // the C ABI's grid object (ks_api.cpp)
+
 namespace ks {
 
 constexpr int kHalf = 4;      // stencil half-width (25-point star)
@@ -132,6 +134,15 @@ struct DArgs {
     int xc = 0;
     double *dpart = nullptr;       // optional [nblocks][3] dipole partials
 };
+
+// ks_apply_h with the projector scratch at `base` (cap bytes of device
+// memory on `device`) instead of the grid's workspace; KS_E_ARG when the
+// call's states need more than cap bytes.  Defined in ks_api.cpp.
+int apply_h_scratch(ks_grid *g, const void *d_psi, void *d_hpsi, int k,
+                    int s0, int ns, double t, char *base, size_t cap,
+                    int device);
+// Record an error message for ks_last_error(); returns code.
+int set_error(int code, const char *msg);
 
 // Launch shape of the H.psi kernel.
 int hpsi_threads(int nx, int TY, int rpt);

@@ -78,6 +78,8 @@ EXPORTS = {
     "ks_hartree": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ks_apply_h": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                              C.c_int, C.c_int, C.c_double]),
+    "ks_apply_h_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_int, C.c_int, C.c_int, C.c_double]),
     "ks_propagate_etrs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_int, C.c_double, C.c_double,
                                     C.c_void_p, C.c_void_p]),
@@ -237,6 +239,11 @@ def ks_hartree(h, rho, vh):
 
 def ks_apply_h(h, psi, hpsi, k, s0, ns, t):
     return _check(lib().ks_apply_h(h, _ptr(psi), _ptr(hpsi), k, s0, ns, t))
+
+
+def ks_apply_h_noalloc(h, psi, hpsi, k, s0, ns, t):
+    return _check(lib().ks_apply_h_noalloc(h, _ptr(psi), _ptr(hpsi), k, s0,
+                                           ns, t))
 
 
 def ks_propagate_etrs(h, psi, vion, nsteps, dt, t0, dipole, norms):
