@@ -889,8 +889,10 @@ int ks_grid_create(const ks_grid_desc *d, ks_grid **out)
         return fail(KS_E_UNSUPPORTED, "fd_half_width %d (only 4)",
                     d->fd_half_width);
     const long N = (long)d->n[0] * d->n[1] * d->n[2];
-    if (N >= (1L << 31))
-        return fail(KS_E_UNSUPPORTED, "grid of %ld points exceeds 2^31", N);
+    // one state's bytes are addressed by 32-bit buffer offsets
+    if (N >= (1L << 27))
+        return fail(KS_E_UNSUPPORTED, "grid of %ld points: at most 2^27 - 1 "
+                    "points", N);
     if (d->nk < 1 || d->nstates < 1 || d->natoms < 0)
         return fail(KS_E_ARG, "nk, nstates must be >= 1, natoms >= 0");
     if ((long)d->nk * d->nstates > 65535)

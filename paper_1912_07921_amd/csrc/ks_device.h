@@ -28,8 +28,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace ks {
+
+// Planes of lead of the H.psi kernel's loads (1 or 2, see hpsi_item).
+#ifndef KS_HPSI_PF
+#define KS_HPSI_PF 2
+#endif
 
 // Half-width-4 central weights: Laplacian (c0..c4) and gradient (d1..d4).
 static __constant__ double kLap[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0,
@@ -205,6 +211,75 @@ __device__ __forceinline__ float2 ld_stream(const float2 *p)
 #else
     return gld(p);
 #endif
+}
+
+// Raw buffer accesses (gfx9 buffer descriptor, no stride): an offset at or
+// beyond the buffer's size reads zero and drops a store, so an access with
+// nothing to move needs no branch around it.
+typedef __amdgpu_buffer_rsrc_t BufRes;
+__device__ __forceinline__ BufRes buf_res(const void *p, size_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<void *>(p), (short)0,
+        (int)(bytes < 0x7fffffffUL ? bytes : 0x7fffffffUL), 0x00020000);
+}
+template <class T> __device__ __forceinline__ T bld_raw(BufRes r, unsigned off);
+template <> __device__ __forceinline__ double2 bld_raw<double2>(BufRes r,
+                                                                unsigned off)
+{
+    return __builtin_bit_cast(double2,
+                              __builtin_amdgcn_raw_buffer_load_b128(r, off, 0,
+                                                                    0));
+}
+template <> __device__ __forceinline__ float2 bld_raw<float2>(BufRes r,
+                                                              unsigned off)
+{
+    return __builtin_bit_cast(float2,
+                              __builtin_amdgcn_raw_buffer_load_b64(r, off, 0,
+                                                                   0));
+}
+// complex value of storage type T at byte offset off, in precision R
+template <class R, class T>
+__device__ __forceinline__ typename Cplx<R>::T bld(BufRes r, unsigned off)
+{
+    const T v = bld_raw<T>(r, off);
+    typename Cplx<R>::T o;
+    o.x = (R)v.x;
+    o.y = (R)v.y;
+    return o;
+}
+__device__ __forceinline__ double bld_d(BufRes r, unsigned off)
+{
+    return __builtin_bit_cast(double,
+                              __builtin_amdgcn_raw_buffer_load_b64(r, off, 0,
+                                                                   0));
+}
+// non-temporal stores (the outputs are read by the next pass only)
+template <class T>
+__device__ __forceinline__ void bst(BufRes r, unsigned off, double x,
+                                    double y);
+template <>
+__device__ __forceinline__ void bst<double2>(BufRes r, unsigned off,
+                                             double x, double y)
+{
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(
+        __builtin_bit_cast(i4, make_double2(x, y)), r, off, 0, 2);
+}
+template <>
+__device__ __forceinline__ void bst<float2>(BufRes r, unsigned off, double x,
+                                            double y)
+{
+    typedef int i2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(
+        __builtin_bit_cast(i2, make_float2((float)x, (float)y)), r, off, 0,
+        2);
+}
+__device__ __forceinline__ void bst_d(BufRes r, unsigned off, double v)
+{
+    typedef int i2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(i2, v), r, off,
+                                          0, 2);
 }
 
 __device__ __forceinline__ int floordiv(int a, int n)
@@ -469,70 +544,118 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
     }
     __syncthreads();   // zeroed buffers, phase tables and hull rows ready
 
-    // halo entry i of plane zq (in range)
-    auto halo_val = [&](int i, int zq) -> V {
-        V v = ldc<R>(in, (long)zq * P + hoff[i]);
-        const int pid = hpk[i] >> 20;
-        if (pid != 40)
-            v = cmul(v, sPh[pid]);
-        return v;
-    };
-    // own column value of row r at plane zq (any integer)
-    auto col_val = [&](int r, int zq) -> V {
-        if (zq >= 0 && zq < nz)
-            return ldc<R>(in, (long)zq * P + po[r]);
-        if (!perz)
-            return czero<V>();
-        const int wz = floordiv(zq, nz);
-        return cmul(ldc<R>(in, (long)(zq - wz * nz) * P + po[r]),
-                    sPz[wz + 4]);
-    };
-    // projector term at this point of row r, plane zq (z0 <= zq < z1)
-    auto kb_val = [&](int r, int zq) -> V {
-        V v = czero<V>();
-        if (proj && act[r]) {
-            const int4 ri = sRow[(zq - z0) * TY + ylr[r]];
-            if (x >= ri.x && x <= ri.y)
-                v = gld(Wst + ri.z + x - ri.x);
+    // ---- loads and stores.  Every per-plane access is a raw buffer access
+    // whose offset is out of range where there is nothing to move (the
+    // hardware then returns zero, or drops the store), so no memory
+    // instruction sits behind a branch and the compiler knows exactly how
+    // many are in flight; the loads of plane z+2 are issued at the start of
+    // plane z into one of two register sets that alternate with the parity
+    // of z, so no register that a load is still filling is ever moved.
+    // Bloch phases are applied where a value is consumed. ----
+    constexpr unsigned kOOB = 0x80000000u;
+    const BufRes rin = buf_res(in, (size_t)N * sizeof(InT));
+    const BufRes rv = buf_res(MODE == kCurrent ? nullptr : a.v,
+                              MODE == kCurrent ? 0 : (size_t)N * 8);
+    const BufRes rw = buf_res(Wst, proj ? (size_t)a.nhull * sizeof(V) : 0);
+    constexpr bool FIN = MODE == kFinal || MODE == kFinalPred;
+    const size_t sN = (size_t)sl * N;
+    const BufRes rbase = buf_res(FIN ? a.base + sN : nullptr,
+                                 FIN ? (size_t)N * 16 : 0);
+    const BufRes rt1 = buf_res(FIN ? reinterpret_cast<const TT *>(a.t1) + sN
+                                   : nullptr,
+                               FIN ? (size_t)N * sizeof(TT) : 0);
+    const BufRes rt2 = buf_res(FIN ? reinterpret_cast<const TT *>(a.t2) + sN
+                                   : nullptr,
+                               FIN ? (size_t)N * sizeof(TT) : 0);
+    using OutT = typename std::conditional<MODE == kTerm, TT, double2>::type;
+    const BufRes rout = buf_res(MODE == kCurrent
+                                    ? nullptr
+                                    : reinterpret_cast<OutT *>(a.out) + sN,
+                                MODE == kCurrent ? 0
+                                                 : (size_t)N * sizeof(OutT));
+    const BufRes rnp = buf_res(FIN && a.npart ? a.npart + sN : nullptr,
+                               FIN && a.npart ? (size_t)N * 8 : 0);
+
+    // byte offsets of plane zq (any integer for the own column)
+    auto col_off = [&](int r, int zq) -> unsigned {
+        int zz = zq;
+        if (zq < 0 || zq >= nz) {
+            if (!perz)
+                return kOOB;
+            zz = zq - floordiv(zq, nz) * nz;
         }
+        return act[r] ? (unsigned)(zz * P + po[r]) * (unsigned)sizeof(InT)
+                      : kOOB;
+    };
+    // the own column of plane zq as loaded, with its Bloch phase
+    auto col_fix = [&](V v, int zq) -> V {
+        if (perz && (zq < 0 || zq >= nz))
+            v = cmul(v, sPz[floordiv(zq, nz) + 4]);
         return v;
     };
-    auto v_val = [&](int r, int zq) -> double {
-        if constexpr (MODE == kCurrent)
-            return 0.0;   // the local potential commutes with r
-        return act[r] ? gp(a.v)[(long)zq * P + po[r]] : 0.0;
+    auto halo_off = [&](int i, int zq) -> unsigned {
+        return (hoff[i] >= 0 && zq < nz)
+                   ? (unsigned)(zq * P + hoff[i]) * (unsigned)sizeof(InT)
+                   : kOOB;
+    };
+    auto halo_fix = [&](int i, V v) -> V {
+        const int pid = hpk[i] >> 20;
+        return pid != 40 ? cmul(v, sPh[pid]) : v;
+    };
+    auto v_off = [&](int r, int zq) -> unsigned {
+        return (act[r] && zq < nz) ? (unsigned)(zq * P + po[r]) * 8u : kOOB;
+    };
+    auto kb_off = [&](int r, int zq) -> unsigned {
+        if (!proj || !act[r] || zq >= z1)
+            return kOOB;
+        const int4 ri = sRow[(zq - z0) * TY + ylr[r]];
+        return (x >= ri.x && x <= ri.y)
+                   ? (unsigned)(ri.z + x - ri.x) * (unsigned)sizeof(V)
+                   : kOOB;
     };
 
-    // ---- prologue ----
+    // ---- prologue: the 9-deep columns around z0, plane z0 in LDS, and
+    // the register sets: S[1] holds plane z0+1 (halo, potential, KB term)
+    // and the own column of plane z0+1+kHalf, S[0] the potential and KB
+    // term of plane z0 ----
     V q[RPT][2 * kHalf + 1];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
 #pragma unroll
         for (int m = 0; m <= 2 * kHalf; ++m)
-            q[r][m] = act[r] ? col_val(r, z0 - kHalf + m) : czero<V>();
+            q[r][m] = col_fix(bld<R, InT>(rin, col_off(r, z0 - kHalf + m)),
+                              z0 - kHalf + m);
         if (act[r])
             buf0[own[r]] = q[r][kHalf];
     }
 #pragma unroll
-    for (int i = 0; i < HM; ++i)
+    for (int i = 0; i < HM; ++i) {
+        const V hv0 = bld<R, InT>(rin, halo_off(i, z0));
         if (hoff[i] >= 0)
-            buf0[hpk[i] & 0xfffff] = halo_val(i, z0);
-    // streams one and two planes ahead
-    V hvA[HM];
+            buf0[hpk[i] & 0xfffff] = halo_fix(i, hv0);
+    }
+    V shv[2][HM], snq[2][RPT], skb[2][RPT];
+    double sv[2][RPT];
 #pragma unroll
-    for (int i = 0; i < HM; ++i)
-        hvA[i] = (z0 + 1 < z1 && hoff[i] >= 0) ? halo_val(i, z0 + 1)
-                                               : czero<V>();
-    V nqA[RPT], kb[RPT], kbA[RPT];
-    double vc[RPT], vA[RPT];
+    for (int i = 0; i < HM; ++i) {
+        shv[1][i] = bld<R, InT>(rin, halo_off(i, z0 + 1));
+        shv[0][i] = czero<V>();
+    }
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        nqA[r] = (z0 + 1 < z1 && act[r]) ? col_val(r, z0 + kHalf + 1)
-                                         : czero<V>();
-        kb[r] = kb_val(r, z0);
-        kbA[r] = z0 + 1 < z1 ? kb_val(r, z0 + 1) : czero<V>();
-        vc[r] = v_val(r, z0);
-        vA[r] = z0 + 1 < z1 ? v_val(r, z0 + 1) : 0.0;
+        snq[1][r] = bld<R, InT>(rin, col_off(r, z0 + kHalf + 1));
+        snq[0][r] = czero<V>();
+        if (KS_HPSI_PF == 2) {
+            sv[1][r] = bld_d(rv, v_off(r, z0 + 1));
+            sv[0][r] = bld_d(rv, v_off(r, z0));
+            skb[1][r] = bld<R, V>(rw, kb_off(r, z0 + 1));
+            skb[0][r] = bld<R, V>(rw, kb_off(r, z0));
+        } else {
+            sv[1][r] = bld_d(rv, v_off(r, z0));
+            sv[0][r] = 0.0;
+            skb[1][r] = bld<R, V>(rw, kb_off(r, z0));
+            skb[0][r] = czero<V>();
+        }
     }
 
     R LC[5], GD[5];
@@ -548,125 +671,161 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
     const R Ax = (R)(Avec.x / a.geo.h[0]), Ay = (R)(Avec.y / a.geo.h[1]),
             Az = (R)(Avec.z / a.geo.h[2]);
     const V cs = cmk<V>(a.cre, a.cim);
-    const double w_occ = (MODE == kFinal || MODE == kFinalPred)
-                             ? gp(a.wocc)[sg] : 0.0;
+    const double w_occ = FIN ? gp(a.wocc)[sg] : 0.0;
     double nrm = 0.0;
     double jc[3] = {0.0, 0.0, 0.0};   // kCurrent: Im(conj psi [H, r_a] psi)
-    V *cur = buf0, *nxt = buf1;
-    for (int z = z0; z < z1; ++z) {
-        const bool more2 = z + 2 < z1;
-        // two planes ahead: in flight during this plane and the next one
-        V hvB[HM];
-#pragma unroll
-        for (int i = 0; i < HM; ++i)
-            hvB[i] = (more2 && hoff[i] >= 0) ? halo_val(i, z + 2)
-                                             : czero<V>();
-        V nqB[RPT], kbB[RPT];
-        double vB[RPT];
+
+    // one plane; PH = (z - z0) & 1 selects the LDS buffer holding plane z
+    // and, with two register sets (PF = 2), the set the loads of plane
+    // z+2 go to (the other set holds plane z+1).  With one set (PF = 1)
+    // the loads of plane z+1 are issued at the start of plane z and used
+    // at its end, so no load is in flight across planes.
+    constexpr int PF = KS_HPSI_PF;
+    static_assert(PF == 1 || PF == 2, "pipeline depth of one or two planes");
+    auto plane_step = [&](auto Pc, const int z) {
+        constexpr int PH = decltype(Pc)::value;
+        constexpr int LS = PF == 2 ? PH : 0;       // set loaded now
+        constexpr int CS = PF == 2 ? 1 - PH : 0;   // set used at the end
+        V *cur = PH == 0 ? buf0 : buf1;
+        V *nxt = PH == 0 ? buf1 : buf0;
+        // potential and KB term of plane z (loaded two planes ago into
+        // this set) before the set is refilled
+        double vc[RPT];
+        V kbc[RPT];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            nqB[r] = (z + 1 < z1 && act[r]) ? col_val(r, z + kHalf + 2)
-                                            : czero<V>();
-            kbB[r] = more2 ? kb_val(r, z + 2) : czero<V>();
-            vB[r] = more2 ? v_val(r, z + 2) : 0.0;
+            vc[r] = sv[PF == 2 ? PH : 1][r];
+            kbc[r] = skb[PF == 2 ? PH : 1][r];
+        }
+        // keep the refills below the reads of the set's previous values
+        // (no load may be scheduled above them: its register would then
+        // still hold a live value and need a copy, i.e. a wait)
+        __builtin_amdgcn_sched_barrier(0);
+        // the final pass's other inputs at plane z, then plane z+2 of
+        // every stream (in flight during this plane and the next)
+        double2 fb[RPT];
+        TT f1[RPT], f2[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            if constexpr (FIN) {
+                const unsigned gi = (unsigned)(z * P + po[r]);
+                fb[r] = bld_raw<double2>(rbase, act[r] ? gi * 16u : kOOB);
+                f1[r] = bld_raw<TT>(rt1,
+                                    act[r] ? gi * (unsigned)sizeof(TT) : kOOB);
+                f2[r] = bld_raw<TT>(rt2,
+                                    act[r] ? gi * (unsigned)sizeof(TT) : kOOB);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < HM; ++i)
+            shv[LS][i] = bld<R, InT>(rin, halo_off(i, z + PF));
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            snq[LS][r] = bld<R, InT>(rin, col_off(r, z + kHalf + PF));
+            sv[LS][r] = bld_d(rv, v_off(r, z + PF));
+            skb[LS][r] = bld<R, V>(rw, kb_off(r, z + PF));
         }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            if (!act[r])
-                continue;
             const V c = q[r][kHalf];
             const V *rp = cur + own[r];
-            V sx = czero<V>(), sy = czero<V>(), sz = czero<V>();
-            V gx = czero<V>(), gy = czero<V>(), gz = czero<V>();
-            V ux = czero<V>(), uy = czero<V>(), uz = czero<V>();
+            V hp = czero<V>();
+            if (act[r]) {
+                V sx = czero<V>(), sy = czero<V>(), sz = czero<V>();
+                V gx = czero<V>(), gy = czero<V>(), gz = czero<V>();
+                V ux = czero<V>(), uy = czero<V>(), uz = czero<V>();
 #pragma unroll
-            for (int m = 1; m <= kHalf; ++m) {
-                const V xp = rp[m], xn = rp[-m];
-                const V yp = rp[m * RS], yn = rp[-m * RS];
-                const V zp = q[r][kHalf + m], zn = q[r][kHalf - m];
-                sx = cadd(sx, cscale(cadd(xp, xn), LC[m]));
-                sy = cadd(sy, cscale(cadd(yp, yn), LC[m]));
-                sz = cadd(sz, cscale(cadd(zp, zn), LC[m]));
-                if constexpr (GRAD) {
-                    gx = cadd(gx, cscale(csub(xp, xn), GD[m]));
-                    gy = cadd(gy, cscale(csub(yp, yn), GD[m]));
-                    gz = cadd(gz, cscale(csub(zp, zn), GD[m]));
+                for (int m = 1; m <= kHalf; ++m) {
+                    const V xp = rp[m], xn = rp[-m];
+                    const V yp = rp[m * RS], yn = rp[-m * RS];
+                    const V zp = q[r][kHalf + m], zn = q[r][kHalf - m];
+                    sx = cadd(sx, cscale(cadd(xp, xn), LC[m]));
+                    sy = cadd(sy, cscale(cadd(yp, yn), LC[m]));
+                    sz = cadd(sz, cscale(cadd(zp, zn), LC[m]));
+                    if constexpr (GRAD) {
+                        gx = cadd(gx, cscale(csub(xp, xn), GD[m]));
+                        gy = cadd(gy, cscale(csub(yp, yn), GD[m]));
+                        gz = cadd(gz, cscale(csub(zp, zn), GD[m]));
+                    }
+                    if constexpr (MODE == kCurrent) {
+                        // taps of the gauge term weighted by their
+                        // displacement: sum m d_m (psi_+m + psi_-m)
+                        const R wm = (R)m * GD[m];
+                        ux = cadd(ux, cscale(cadd(xp, xn), wm));
+                        uy = cadd(uy, cscale(cadd(yp, yn), wm));
+                        uz = cadd(uz, cscale(cadd(zp, zn), wm));
+                    }
                 }
                 if constexpr (MODE == kCurrent) {
-                    // taps of the gauge term weighted by their
-                    // displacement: sum m d_m (psi_+m + psi_-m)
-                    const R wm = (R)m * GD[m];
-                    ux = cadd(ux, cscale(cadd(xp, xn), wm));
-                    uy = cadd(uy, cscale(cadd(yp, yn), wm));
-                    uz = cadd(uz, cscale(cadd(zp, zn), wm));
-                }
-            }
-            if constexpr (MODE == kCurrent) {
-                // [H, r_a] psi = -grad_a psi - i A_a sum m d_m (psi_+ +
-                // psi_-): the kinetic taps -c_m/(2h^2) at displacement m h
-                // give -d_m/h (m c_m = 2 d_m for these weights)
-                const V gg[3] = {gx, gy, gz}, uu[3] = {ux, uy, uz};
+                    // [H, r_a] psi = -grad_a psi - i A_a sum m d_m (psi_+ +
+                    // psi_-): the kinetic taps -c_m/(2h^2) at displacement
+                    // m h give -d_m/h (m c_m = 2 d_m for these weights)
+                    const V gg[3] = {gx, gy, gz}, uu[3] = {ux, uy, uz};
 #pragma unroll
-                for (int ax = 0; ax < 3; ++ax) {
-                    const double ih = 1.0 / a.geo.h[ax];
-                    const double A = ax == 0 ? Avec.x
-                                             : (ax == 1 ? Avec.y : Avec.z);
-                    const double tx = -gg[ax].x * ih + A * uu[ax].y;
-                    const double ty = -gg[ax].y * ih - A * uu[ax].x;
-                    jc[ax] += c.x * ty - c.y * tx;
-                }
-                continue;
-            }
-            const long g = (long)z * P + po[r];
-            V lap = cadd(cadd(cscale(sx, ih2x), cscale(sy, ih2y)),
-                         cscale(sz, ih2z));
-            lap = cadd(lap, cscale(c, c0sum));
-            const R vv = (R)(vc[r] + Avec.w);
-            V hp = cadd(cscale(lap, (R)-0.5), cscale(c, vv));
-            if constexpr (GRAD) {
-                // -i A.grad
-                const V gr = cadd(cadd(cscale(gx, Ax), cscale(gy, Ay)),
-                                  cscale(gz, Az));
-                hp.x += gr.y;
-                hp.y -= gr.x;
-            }
-            hp = cadd(hp, kb[r]);
-            if constexpr (MODE == kApply) {
-                st_stream(reinterpret_cast<double2 *>(a.out) +
-                              (size_t)sl * N + g, (double)hp.x, (double)hp.y);
-            } else if constexpr (MODE == kTerm) {
-                const V t = cmul(cs, hp);
-                st_stream(reinterpret_cast<TT *>(a.out) + (size_t)sl * N + g,
-                          t.x, t.y);
-            } else {
-                const V t4 = cmul(cs, hp);
-                const size_t i = (size_t)sl * N + g;
-                const double2 bb = ld_stream(a.base + i);
-                const TT u1 = ld_stream(reinterpret_cast<const TT *>(a.t1) + i);
-                const TT u2 = ld_stream(reinterpret_cast<const TT *>(a.t2) + i);
-                const double re = bb.x + (double)u1.x + (double)u2.x +
-                                  (double)c.x + (double)t4.x;
-                const double im = bb.y + (double)u1.y + (double)u2.y +
-                                  (double)c.y + (double)t4.y;
-                st_stream(reinterpret_cast<double2 *>(a.out) + i, re, im);
-                if constexpr (MODE == kFinalPred) {
-                    const double pr = bb.x + 2.0 * u1.x + 4.0 * u2.x +
-                                      8.0 * c.x + 16.0 * (double)t4.x;
-                    const double pi = bb.y + 2.0 * u1.y + 4.0 * u2.y +
-                                      8.0 * c.y + 16.0 * (double)t4.y;
-                    if (a.npart)
-                        st_stream(a.npart + i, w_occ * (pr * pr + pi * pi));
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const double ih = 1.0 / a.geo.h[ax];
+                        const double A = ax == 0 ? Avec.x
+                                                 : (ax == 1 ? Avec.y : Avec.z);
+                        const double tx = -gg[ax].x * ih + A * uu[ax].y;
+                        const double ty = -gg[ax].y * ih - A * uu[ax].x;
+                        jc[ax] += c.x * ty - c.y * tx;
+                    }
                 } else {
-                    const double sq = re * re + im * im;
-                    if (a.npart)
-                        st_stream(a.npart + i, w_occ * sq);
-                    nrm += sq;
+                    V lap = cadd(cadd(cscale(sx, ih2x), cscale(sy, ih2y)),
+                                 cscale(sz, ih2z));
+                    lap = cadd(lap, cscale(c, c0sum));
+                    const R vv = (R)(vc[r] + Avec.w);
+                    hp = cadd(cscale(lap, (R)-0.5), cscale(c, vv));
+                    if constexpr (GRAD) {
+                        // -i A.grad
+                        const V gr = cadd(cadd(cscale(gx, Ax),
+                                               cscale(gy, Ay)),
+                                          cscale(gz, Az));
+                        hp.x += gr.y;
+                        hp.y -= gr.x;
+                    }
+                    hp = cadd(hp, kbc[r]);
+                }
+            }
+            if constexpr (MODE != kCurrent) {
+                const unsigned gi = (unsigned)(z * P + po[r]);
+                if constexpr (MODE == kApply) {
+                    bst<double2>(rout, act[r] ? gi * 16u : kOOB,
+                                 (double)hp.x, (double)hp.y);
+                } else if constexpr (MODE == kTerm) {
+                    const V t = cmul(cs, hp);
+                    bst<TT>(rout, act[r] ? gi * (unsigned)sizeof(TT) : kOOB,
+                            t.x, t.y);
+                } else {
+                    const V t4 = cmul(cs, hp);
+                    const double2 bb = fb[r];
+                    const TT u1 = f1[r], u2 = f2[r];
+                    const double re = bb.x + (double)u1.x + (double)u2.x +
+                                      (double)c.x + (double)t4.x;
+                    const double im = bb.y + (double)u1.y + (double)u2.y +
+                                      (double)c.y + (double)t4.y;
+                    bst<double2>(rout, act[r] ? gi * 16u : kOOB, re, im);
+                    double part;
+                    if constexpr (MODE == kFinalPred) {
+                        const double pr = bb.x + 2.0 * u1.x + 4.0 * u2.x +
+                                          8.0 * c.x + 16.0 * (double)t4.x;
+                        const double pi = bb.y + 2.0 * u1.y + 4.0 * u2.y +
+                                          8.0 * c.y + 16.0 * (double)t4.y;
+                        part = w_occ * (pr * pr + pi * pi);
+                    } else {
+                        const double sq = re * re + im * im;
+                        part = w_occ * sq;
+                        if (act[r])
+                            nrm += sq;
+                    }
+                    bst_d(rnp, act[r] ? gi * 8u : kOOB, part);
                 }
             }
         }
         // plane z+1 into the other buffer (free: its last readers passed
-        // this iteration's barrier)
+        // this plane's barrier): own values from the columns, the halo from
+        // the other register set (loaded during the previous plane)
         if (z + 1 < z1) {
 #pragma unroll
             for (int r = 0; r < RPT; ++r)
@@ -675,27 +834,27 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
 #pragma unroll
             for (int i = 0; i < HM; ++i)
                 if (hoff[i] >= 0)
-                    nxt[hpk[i] & 0xfffff] = hvA[i];
+                    nxt[hpk[i] & 0xfffff] = halo_fix(i, shv[CS][i]);
         }
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
 #pragma unroll
             for (int m = 0; m < 2 * kHalf; ++m)
                 q[r][m] = q[r][m + 1];
-            q[r][2 * kHalf] = nqA[r];
-            nqA[r] = nqB[r];
-            kb[r] = kbA[r];
-            kbA[r] = kbB[r];
-            vc[r] = vA[r];
-            vA[r] = vB[r];
+            q[r][2 * kHalf] = col_fix(snq[CS][r], z + kHalf + 1);
+            if constexpr (PF == 1) {
+                sv[1][r] = sv[0][r];     // potential and KB term of z + 1
+                skb[1][r] = skb[0][r];
+            }
         }
-#pragma unroll
-        for (int i = 0; i < HM; ++i)
-            hvA[i] = hvB[i];
-        V *t = cur;
-        cur = nxt;
-        nxt = t;
+    };
+    int z = z0;
+    for (; z + 1 < z1; z += 2) {
+        plane_step(std::integral_constant<int, 0>{}, z);
+        plane_step(std::integral_constant<int, 1>{}, z + 1);
     }
+    if (z < z1)
+        plane_step(std::integral_constant<int, 0>{}, z);
     if constexpr (MODE == kFinal) {
         if (!a.normpart)
             return;

@@ -2,6 +2,12 @@
 #ifndef KS_HPSI_PART
 #define KS_HPSI_PART 0
 #endif
+// Planes the H.psi kernel's loads run ahead: the FP64 kernels (part 0)
+// keep one register set (fewer registers; measured faster at 64^3, 48^3
+// and 128^3), the mixed ones two alternating sets.
+#ifndef KS_HPSI_PF
+#define KS_HPSI_PF (KS_HPSI_PART == 0 ? 1 : 2)
+#endif
 
 #include "ks_device.h"
 
