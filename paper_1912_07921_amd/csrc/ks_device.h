@@ -1071,10 +1071,14 @@ constexpr int kApplySPW = KS_APPLY_SPW;
 constexpr int kApplyStates = 4 * kApplySPW;
 constexpr int kApplyAtoms = 12;
 
+// The coefficients of each atom take kApplyStates * kMaxProj values plus
+// one of padding, so that lanes reading different atoms at the same
+// (state, projector) fall in different LDS banks (an unpadded atom stride
+// is a multiple of the bank count).
 template <class R> struct ApplyLds {
     using V = typename Cplx<R>::T;
     int np[kApplyAtoms];
-    V D[kApplyAtoms][kApplyStates][kMaxProj];
+    V D[kApplyAtoms][kApplyStates * kMaxProj + 1];
 };
 
 template <class R>
@@ -1113,7 +1117,7 @@ __device__ __forceinline__ void kbapply_item(const GArgs &a, const int chunk,
             if (sl < a.ns)
                 d = gld(reinterpret_cast<const V *>(a.D) +
                         ((size_t)sl * a.pj.natoms + at) * kMaxProj + j);
-            sh.D[i][q][j] = d;
+            sh.D[i][q * kMaxProj + j] = d;
         }
         __syncthreads();
         for (int e = e0; e < e1; ++e) {
@@ -1131,7 +1135,7 @@ __device__ __forceinline__ void kbapply_item(const GArgs &a, const int chunk,
                 const int sl = s0 + q;
                 if (sl >= a.ns)
                     break;
-                const V *D = sh.D[i][wave * kApplySPW + q];
+                const V *D = &sh.D[i][(wave * kApplySPW + q) * kMaxProj];
                 V t = czero<V>();
                 for (int j = 0; j < np; ++j)
                     t = cadd(t, cscale(D[j], p[j]));

@@ -12,8 +12,13 @@ as a HIP graph).  When a job joins or leaves, the batch is rebuilt and every job
 resumes where it stopped; the trajectory of each request is bitwise the
 one it has when propagated alone.
 
-Latency of a (request, step) pair is the wall time from the launch of the
-batch step that advanced it to that step's completion on the GPU.
+Latency of a (request, step) pair is the wall time from the moment the
+request was ready for that step (the completion of its previous step, or
+its admission) to the completion of the batch step that advanced it: the
+rebuild of the batch and the admissions that delay a step are charged to
+it.  Newly arrived requests join at the next departure (when the batch is
+rebuilt anyway) unless that is more than `join_lag` steps away, which
+halves the rebuilds of a mix whose requests leave every few steps.
 """
 from __future__ import annotations
 
@@ -68,6 +73,7 @@ class _Active:
     def __init__(self, req, grid, job):
         self.req, self.grid, self.job = req, grid, job
         self.fp = 0
+        self.t_ready = 0.0     # wall time the request became ready to step
 
 
 class Server:
@@ -79,11 +85,14 @@ class Server:
         (arrivals in batch steps taken: a deterministic schedule).
     keep_states: copy each request's final states to the host.
     tune: run the launch-shape autotuner on each admitted grid.
+    join_lag: a request that could be admitted while a batch runs waits
+        for the next departure (which rebuilds the batch anyway) when that
+        is at most this many steps away.
     """
 
     def __init__(self, hbm_budget, max_slots=64, precision=ks.KS_FP64,
                  clock="wall", keep_states=False, tune=False,
-                 device="cuda"):
+                 device="cuda", join_lag=4):
         import torch
         self.torch = torch
         self.budget = int(hbm_budget)
@@ -93,6 +102,7 @@ class Server:
         self.keep_states = keep_states
         self.tune = tune
         self.device = torch.device(device)
+        self.join_lag = int(join_lag)
         self.stats = {}
 
     # ---- footprint ----
@@ -114,6 +124,7 @@ class Server:
         req.t_admit = now
         a = _Active(req, grid, job)
         a.fp = self._footprint(req, grid)
+        a.t_ready = time.perf_counter()
         return a
 
     def _retire(self, a, now):
@@ -139,6 +150,7 @@ class Server:
         batch = None
         steps_taken = 0
         rebuilds = 0
+        rebuild_s = 0.0
         max_active = 0
         lat = []
         work = 0.0
@@ -165,7 +177,12 @@ class Server:
                                      f"more than the budget {self.budget}")
                 waiting.append((r, g, fp))
             changed = False
-            while (waiting and len(active) < self.max_slots and
+            # while a batch runs, newly arrived requests join at the next
+            # departure unless it is more than join_lag steps away
+            join_now = batch is None or not active or min(
+                a.req.nsteps - batch.steps_done(i)
+                for i, a in enumerate(active)) > self.join_lag
+            while (join_now and waiting and len(active) < self.max_slots and
                    used + waiting[0][2] <= self.budget):
                 r, g, fp = waiting.popleft()
                 active.append(self._admit(r, g, tnow))
@@ -178,26 +195,30 @@ class Server:
                     time.sleep(max(0.0, min(pending[0].arrival - now(),
                                             0.001)))
                 continue
+            if t_first is None:
+                t_first = time.perf_counter()
             if changed or batch is None:
+                t_rb = time.perf_counter()
                 if batch is not None:
                     batch.close()
                 batch = ks.Batch([a.job for a in active])
                 rebuilds += 1
+                rebuild_s += time.perf_counter() - t_rb
             max_active = max(max_active, len(active))
-            if t_first is None:
-                t_first = time.perf_counter()
             t0 = time.perf_counter()
             batch.step(1)
             torch.cuda.current_stream().synchronize()
-            dt_step = time.perf_counter() - t0
-            busy += dt_step
+            t1 = time.perf_counter()
+            busy += t1 - t0
             steps_taken += 1
             done = []
-            for a in active:
+            for i, a in enumerate(active):
+                dt_step = t1 - a.t_ready
+                a.t_ready = t1
                 a.req.step_latency.append(dt_step)
                 lat.append(dt_step)
                 work += 8.0 * a.req.pts_states
-                if batch.steps_done(active.index(a)) >= a.req.nsteps:
+                if batch.steps_done(i) >= a.req.nsteps:
                     done.append(a)
             if done:
                 batch.close()
@@ -219,6 +240,7 @@ class Server:
             request_steps=len(lat),
             batch_steps=int(steps_taken),
             rebuilds=rebuilds,
+            rebuild_ms_mean=1e3 * rebuild_s / max(rebuilds, 1),
             max_concurrent=max_active,
             p50_step_ms=float(np.percentile(lat_ms, 50)),
             p99_step_ms=float(np.percentile(lat_ms, 99)),
