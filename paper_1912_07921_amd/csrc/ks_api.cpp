@@ -82,7 +82,7 @@ struct ks_grid {
     struct {
         size_t t1, t2, t3, half, npart, normpart, D, W, Dpart, rho, vpred,
             dpart, gpart, dotpart, xpart, step, vhist, veff, pwork, vh, cpart,
-            cnl, normchk, total;
+            cnl, normchk, v32, total;
     } lay{};
     int ntiles_max = 64;
     int nchunk = 1;
@@ -505,6 +505,7 @@ void layout(ks_grid *g)
     g->lay.cpart = take(S * (size_t)g->geo.ny * g->geo.nz * 3 * 8);
     g->lay.cnl = take(S * std::max(1, g->natoms) * 3 * 8);
     g->lay.normchk = take(S * 8);
+    g->lay.v32 = take(g->mixed ? N * 4 : 0);
     g->lay.total = off;
 }
 
@@ -658,6 +659,8 @@ int exp_chain(ks_grid *g, hipStream_t st, int s0, int ns, const double2 *in,
     HArgs a = base_hargs(g);
     a.sg0 = s0;
     a.v = v;
+    if (mx)
+        a.v32 = wsp<float>(g, g->lay.v32);   // filled by taylor_exponential
     a.A[0] = A[0];
     a.A[1] = A[1];
     a.A[2] = A[2];
@@ -744,6 +747,10 @@ int taylor_exponential(ks_grid *g, const double2 *in, double2 *out,
                        double *normpart)
 {
     const int S = g->stot;
+    // the FP32 kernels read an FP32 copy of the potential
+    if (g->mixed)
+        KS_HIP(launch_to_f32(v, wsp<float>(g, g->lay.v32), g->geo.N,
+                             g->stream));
     if (g->halves < 2 || S < 2 || g->natoms == 0 || g->profiling)
         return exp_chain(g, g->stream, 0, S, in, out, v, A, a2half, tau,
                          final_mode, npart, normpart);
@@ -782,8 +789,10 @@ int apply_h_check(const ks_grid *g, const void *d_psi, const void *d_hpsi,
 // coefficients D, their chunk partials and the hull-row terms W at the
 // given device addresses (each indexed from the call's first state).
 int apply_h_core(ks_grid *g, const void *d_psi, void *d_hpsi, int k, int s0,
-                 int ns, double t, void *D, void *Dpart, void *W)
+                 int ns, double t, void *D, void *Dpart, void *W, float *v32)
 {
+    if (g->mixed)
+        KS_HIP(launch_to_f32(g->d_v, v32, g->geo.N, g->stream));
     double A[3];
     laser_A(g, t, A);
     GArgs ga = base_gargs(g);
@@ -801,6 +810,7 @@ int apply_h_core(ks_grid *g, const void *d_psi, void *d_hpsi, int k, int s0,
     a.in = d_psi;
     a.out = d_hpsi;
     a.v = g->d_v;
+    a.v32 = v32;
     if (a.rowinfo)
         a.W = W;
     a.A[0] = A[0];
@@ -838,13 +848,15 @@ int ks::apply_h_scratch(ks_grid *g, const void *d_psi, void *d_hpsi, int k,
     const size_t nD = align256((size_t)ns * na * kMaxProj * vs);
     const size_t nP = align256((size_t)ns * na * g->nchunk * kMaxProj * vs);
     const size_t nW = align256((size_t)ns * std::max<long>(1, g->nhull) * vs);
-    const size_t need = g->natoms > 0 ? nD + nP + nW : 0;
+    const size_t nV = g->mixed ? align256((size_t)g->geo.N * 4) : 0;
+    const size_t need = (g->natoms > 0 ? nD + nP + nW : 0) + nV;
     if (need > cap)
         return fail(KS_E_ARG, "%d states need %zu bytes of projector scratch "
                     "and the static scratch holds %zu: apply H to fewer "
                     "states per call", ns, need, cap);
+    char *pv = base + (g->natoms > 0 ? nD + nP + nW : 0);
     return apply_h_core(g, d_psi, d_hpsi, k, s0, ns, t, base, base + nD,
-                        base + nD + nP);
+                        base + nD + nP, reinterpret_cast<float *>(pv));
 }
 
 int ks::set_error(int code, const char *msg)
@@ -1099,7 +1111,8 @@ int ks_apply_h(ks_grid *g, const void *d_psi, void *d_hpsi, int k, int s0,
     if ((rc = need_ws(g)))
         return rc;
     return apply_h_core(g, d_psi, d_hpsi, k, s0, ns, t, g->ws + g->lay.D,
-                        g->ws + g->lay.Dpart, g->ws + g->lay.W);
+                        g->ws + g->lay.Dpart, g->ws + g->lay.W,
+                        wsp<float>(g, g->lay.v32));
 }
 
 int ks_hartree(ks_grid *g, const double *d_rho, double *d_vh)
@@ -1477,6 +1490,9 @@ int ks_autotune(ks_grid *g, const void *d_psi, int reps, int out_shape[3],
         KS_HIP(launch_gather(mx, true, ga, S, g->stream));
         KS_HIP(launch_kbapply(mx, ga, S, g->stream));
     }
+    if (mx)
+        KS_HIP(launch_to_f32(g->d_v, wsp<float>(g, g->lay.v32), G.N,
+                             g->stream));
     hipEvent_t e0, e1;
     KS_HIP(hipEventCreate(&e0));
     KS_HIP(hipEventCreate(&e1));
@@ -1495,6 +1511,7 @@ int ks_autotune(ks_grid *g, const void *d_psi, int reps, int out_shape[3],
         // final sum into psi_half), the mix of passes a step runs
         HArgs a = base_hargs(g);
         a.v = g->d_v;
+        a.v32 = wsp<float>(g, g->lay.v32);
         a.cre = 0.0;
         // a grid with a laser runs the passes with the gradient term: time
         // that kernel, at the pulse's amplitude
@@ -1924,6 +1941,11 @@ struct ks_batch {
     bool use_graph = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // FP32 copies of each job's potential before each exponential (mixed
+    // batches): copy tables and block offsets for exponentials 0 and 1
+    F32Copy *d_conv[2] = {nullptr, nullptr};
+    int *d_conv_off = nullptr;
+    int conv_blocks = 0;
     // per-job sticky flags of a NaN / Inf norm (device), their copy after
     // the latest ks_batch_step (pinned host) and its completion event
     int *d_flags = nullptr;
@@ -1986,6 +2008,11 @@ int batch_enqueue_step(ks_batch *b)
 {
     const hipStream_t st = b->stream;
     for (int e = 0; e < 2; ++e) {
+        // the FP32 kernels read an FP32 copy of the exponential's potential
+        if (b->mixed)
+            KS_HIP(launch_to_f32_batch(b->d_conv[e], b->d_conv_off,
+                                       (int)b->grids.size(), b->conv_blocks,
+                                       st));
         for (int j = 1; j <= 4; ++j) {
             const int p = 4 * e + j;
             KS_HIP(launch_projectors_batch(b->mixed,
@@ -2188,6 +2215,8 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
                                     : (const void *)J.half)
                           : J.t[j - 2];
             a.v = e == 0 ? J.vcur : (J.nonlin ? J.vpred : J.vion);
+            a.v32 = mixed ? wsp<float>(b->grids[i], b->grids[i]->lay.v32)
+                          : nullptr;
             a.cre = 0.0;
             a.cim = -0.5 * J.dt / j;
             if (j < 4) {
@@ -2227,6 +2256,32 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
             hipSuccess) {
         ks_batch_destroy(b);
         return rc ? rc : fail(KS_E_HIP, "batch flag buffers");
+    }
+    // FP32 potential copies of the mixed jobs, per exponential
+    if (mixed) {
+        std::vector<F32Copy> c0(njobs), c1(njobs);
+        std::vector<int> off(njobs + 1, 0);
+        for (int i = 0; i < njobs; ++i) {
+            ks_grid *g = b->grids[i];
+            const JobDev &J = b->hjobs[i];
+            float *dst = wsp<float>(g, g->lay.v32);
+            c0[i] = F32Copy{J.vcur, dst, g->geo.N};
+            c1[i] = F32Copy{J.nonlin ? J.vpred : J.vion, dst, g->geo.N};
+            off[i + 1] = off[i] + (int)((g->geo.N + 255) / 256);
+        }
+        b->conv_blocks = off[njobs];
+        if ((rc = batch_alloc(b, &b->d_conv[0], njobs)) ||
+            (rc = batch_alloc(b, &b->d_conv[1], njobs)) ||
+            (rc = batch_alloc(b, &b->d_conv_off, njobs + 1)) ||
+            hipMemcpy(b->d_conv[0], c0.data(), njobs * sizeof(F32Copy),
+                      hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(b->d_conv[1], c1.data(), njobs * sizeof(F32Copy),
+                      hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(b->d_conv_off, off.data(), (njobs + 1) * sizeof(int),
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            ks_batch_destroy(b);
+            return rc ? rc : fail(KS_E_HIP, "upload of the FP32 copy tables");
+        }
     }
     // tables of the batched reductions (the same arguments the single-job
     // propagator passes)

@@ -554,8 +554,15 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
     // Bloch phases are applied where a value is consumed. ----
     constexpr unsigned kOOB = 0x80000000u;
     const BufRes rin = buf_res(in, (size_t)N * sizeof(InT));
-    const BufRes rv = buf_res(MODE == kCurrent ? nullptr : a.v,
-                              MODE == kCurrent ? 0 : (size_t)N * 8);
+    // the potential: FP64, or its FP32 copy in the FP32 kernels (half the
+    // bytes of the stream every state re-reads)
+    constexpr bool V32 = sizeof(R) == 4;
+    constexpr unsigned VB = V32 ? 4u : 8u;
+    const BufRes rv = buf_res(MODE == kCurrent
+                                  ? nullptr
+                                  : (V32 ? (const void *)a.v32
+                                         : (const void *)a.v),
+                              MODE == kCurrent ? 0 : (size_t)N * VB);
     const BufRes rw = buf_res(Wst, proj ? (size_t)a.nhull * sizeof(V) : 0);
     constexpr bool FIN = MODE == kFinal || MODE == kFinalPred;
     const size_t sN = (size_t)sl * N;
@@ -603,7 +610,14 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
         return pid != 40 ? cmul(v, sPh[pid]) : v;
     };
     auto v_off = [&](int r, int zq) -> unsigned {
-        return (act[r] && zq < nz) ? (unsigned)(zq * P + po[r]) * 8u : kOOB;
+        return (act[r] && zq < nz) ? (unsigned)(zq * P + po[r]) * VB : kOOB;
+    };
+    auto v_ld = [&](unsigned off) -> double {
+        if constexpr (V32)
+            return (double)__builtin_bit_cast(
+                float, __builtin_amdgcn_raw_buffer_load_b32(rv, off, 0, 0));
+        else
+            return bld_d(rv, off);
     };
     auto kb_off = [&](int r, int zq) -> unsigned {
         if (!proj || !act[r] || zq >= z1)
@@ -646,12 +660,12 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
         snq[1][r] = bld<R, InT>(rin, col_off(r, z0 + kHalf + 1));
         snq[0][r] = czero<V>();
         if (KS_HPSI_PF == 2) {
-            sv[1][r] = bld_d(rv, v_off(r, z0 + 1));
-            sv[0][r] = bld_d(rv, v_off(r, z0));
+            sv[1][r] = v_ld(v_off(r, z0 + 1));
+            sv[0][r] = v_ld(v_off(r, z0));
             skb[1][r] = bld<R, V>(rw, kb_off(r, z0 + 1));
             skb[0][r] = bld<R, V>(rw, kb_off(r, z0));
         } else {
-            sv[1][r] = bld_d(rv, v_off(r, z0));
+            sv[1][r] = v_ld(v_off(r, z0));
             sv[0][r] = 0.0;
             skb[1][r] = bld<R, V>(rw, kb_off(r, z0));
             skb[0][r] = czero<V>();
@@ -722,7 +736,7 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             snq[LS][r] = bld<R, InT>(rin, col_off(r, z + kHalf + PF));
-            sv[LS][r] = bld_d(rv, v_off(r, z + PF));
+            sv[LS][r] = v_ld(v_off(r, z + PF));
             skb[LS][r] = bld<R, V>(rw, kb_off(r, z + PF));
         }
         __syncthreads();

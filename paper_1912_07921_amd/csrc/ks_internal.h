@@ -84,6 +84,7 @@ struct HArgs {
     const void *t1 = nullptr;
     const void *t2 = nullptr;
     const double *v = nullptr;     // local potential
+    const float *v32 = nullptr;    // its FP32 copy (read by the FP32 kernels)
     double a2half = 0.0;           // |A|^2 / 2
     double A[3] = {0.0, 0.0, 0.0};
     double cre = 1.0, cim = 0.0;   // complex scale of H.in
@@ -178,6 +179,19 @@ hipError_t launch_norm_finalize(const double *normpart, int ns, int ntiles,
                                 const int *step = nullptr);
 hipError_t launch_kick(const Geo &g, double2 *psi, int ns, double kappa,
                        hipStream_t st);
+// out[i] = (float)in[i], i < n (the FP32 copy of a potential)
+hipError_t launch_to_f32(const double *in, float *out, long n,
+                         hipStream_t st);
+// the same for several potentials in one launch: copy j converts
+// src[j][0 .. n[j]) into dst[j]; blocks of 256 points, blk_off[j] the first
+// block of copy j
+struct F32Copy {
+    const double *src = nullptr;
+    float *dst = nullptr;
+    long n = 0;
+};
+hipError_t launch_to_f32_batch(const F32Copy *copies, const int *blk_off,
+                               int ncopies, int nblocks, hipStream_t st);
 
 // Reductions of several grids in one launch each (the batched form).  The
 // tables are device arrays; every entry is computed exactly as the

@@ -553,6 +553,47 @@ hipError_t launch_norm_finalize(const double *normpart, int ns, int ntiles,
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_to_f32(const double *in, float *out,
+                                               long n)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        out[i] = (float)in[i];
+}
+
+hipError_t launch_to_f32(const double *in, float *out, long n,
+                         hipStream_t st)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256),
+                       0, st, in, out, n);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_to_f32_batch(const F32Copy *copies,
+                                                     const int *blk_off,
+                                                     int ncopies)
+{
+    int j = 0;
+    while (j + 1 < ncopies && (int)blockIdx.x >= blk_off[j + 1])
+        ++j;
+    const F32Copy c = copies[j];
+    const long i = (long)(blockIdx.x - blk_off[j]) * blockDim.x + threadIdx.x;
+    if (i < c.n)
+        c.dst[i] = (float)c.src[i];
+}
+
+hipError_t launch_to_f32_batch(const F32Copy *copies, const int *blk_off,
+                               int ncopies, int nblocks, hipStream_t st)
+{
+    if (ncopies <= 0 || nblocks <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_to_f32_batch, dim3((unsigned)nblocks), dim3(256), 0,
+                       st, copies, blk_off, ncopies);
+    return hipGetLastError();
+}
+
 hipError_t launch_kick(const Geo &g, double2 *psi, int ns, double kappa,
                        hipStream_t st)
 {
