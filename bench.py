@@ -507,6 +507,8 @@ def main():
     ap.add_argument("--shape", default="",
                     help="FP64 launch shape 'tile_rows,zchunk,rows_per_thread'"
                          " instead of the autotuner's (profiling runs)")
+    ap.add_argument("--mixed-shape", default="",
+                    help="the same for the mixed-precision leg")
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-steps", type=int, default=200,
@@ -617,9 +619,11 @@ def main():
 
     if not args.no_mixed:
         log(f"mixed: {args.warmup} warmup + {args.steps} timed steps")
+        mfixed = (tuple(int(v) for v in args.mixed_shape.split(","))
+                  if args.mixed_shape else None)
         msec, dipm, nrmm, mprof, _, mshape = run_gpu(w, 1, args.steps,
                                                      args.warmup, torch,
-                                                     not args.no_tune)
+                                                     not args.no_tune, mfixed)
         mh_ms, mh_n = mprof["hpsi"]
         mavg = mh_ms / max(mh_n, 1)
         mach = STEP_BYTES[1] / 8.0 * N * S / (mavg / 1e3) / 1e9

@@ -83,9 +83,12 @@ typedef enum {
 } ks_precision;
 
 typedef struct {
-    int n[3];            /* nx, ny, nz >= 1; nx <= 192; with atoms also
-                            ny <= 1024 and nz <= 2048 (else
-                            KS_E_UNSUPPORTED) */
+    int n[3];            /* nx, ny, nz >= 1; nx <= 512 (one x-row of a
+                            tile is one thread per point, at most 512
+                            threads); nx * ny * nz < 2^27 (one state's
+                            bytes take 32-bit buffer offsets); with atoms
+                            also ny <= 1024 and nz <= 2048 (packed point
+                            coordinates); else KS_E_UNSUPPORTED */
     double h[3];         /* grid spacing per axis (bohr), > 0 */
     int periodic[3];     /* 1: Bloch-periodic axis, 0: zero boundary */
     int fd_half_width;   /* must be 4 (25-point star); else KS_E_UNSUPPORTED */

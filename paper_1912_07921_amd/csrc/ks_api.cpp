@@ -418,15 +418,28 @@ bool tile_ok(const ks_grid *g, int TY, int rpt)
 int set_tiles(ks_grid *g, int TY, int zchunk, int rpt)
 {
     const Geo &G = g->geo;
-    if (rpt <= 0)
+    const bool auto_rpt = rpt <= 0, auto_ty = TY <= 0;
+    if (auto_rpt)
         rpt = (TY > 0 && G.nx * TY <= kRowThreads) ? 1 : (g->mixed ? 1 : 2);
-    if (TY <= 0) {
-        // the tallest tile that fits the threads and the default LDS share:
-        // the 8 halo rows are then the smallest fraction of what it loads
-        TY = std::max(1, std::min(G.ny, rpt * kRowThreads / G.nx));
-        while (TY > 1 && (!tile_ok(g, TY, rpt) ||
-                          lds_for(g, TY, std::min(G.nz, 16)) > kLdsDefault))
-            --TY;
+    for (;;) {
+        if (auto_ty) {
+            // the tallest tile that fits the threads and the default LDS
+            // share: the 8 halo rows are then the smallest fraction of what
+            // it loads
+            TY = std::max(1, std::min(G.ny, rpt * kRowThreads / G.nx));
+            while (TY > 1 &&
+                   (!tile_ok(g, TY, rpt) ||
+                    lds_for(g, TY, std::min(G.nz, 16)) > kLdsDefault))
+                --TY;
+        }
+        // two rows per thread allow 8 halo loads per thread and plane:
+        // the wrapped columns of a wide periodic row exceed that at any
+        // height, and one row per thread then takes it
+        if (auto_rpt && rpt == 2 && !tile_ok(g, TY, rpt)) {
+            rpt = 1;
+            continue;
+        }
+        break;
     }
     if (!tile_ok(g, TY, rpt))
         return fail(KS_E_ARG, "tile height %d with %d rows per thread "
@@ -440,7 +453,13 @@ int set_tiles(ks_grid *g, int TY, int zchunk, int rpt)
                                                                   g->stot));
         nzc = std::min(nzc, std::max(1, G.nz / 32));
         zchunk = (G.nz + nzc - 1) / nzc;
-        while (zchunk > 1 && lds_for(g, TY, zchunk) > kLdsDefault)
+        // keep the default LDS share where a one-plane chunk would meet it;
+        // wider rows (nx above ~300 in FP64) exceed it at any chunk, and
+        // then only the LDS of the CU bounds the chunk (shorter chunks
+        // would only re-read more z-halo planes)
+        const size_t cap = lds_for(g, TY, 1) <= kLdsDefault ? kLdsDefault
+                                                             : kLdsBudget;
+        while (zchunk > 1 && lds_for(g, TY, zchunk) > cap)
             zchunk = (zchunk + 1) / 2;
     }
     zchunk = std::min(zchunk, G.nz);
@@ -895,8 +914,9 @@ int ks_grid_create(const ks_grid_desc *d, ks_grid **out)
         if (!(d->h[a] > 0.0))
             return fail(KS_E_ARG, "h[%d] must be > 0", a);
     }
-    if (d->n[0] > 192)
-        return fail(KS_E_UNSUPPORTED, "nx = %d > 192", d->n[0]);
+    // a tile row of x points is one thread each, at most 512 threads
+    if (d->n[0] > kRowThreads)
+        return fail(KS_E_UNSUPPORTED, "nx = %d > %d", d->n[0], kRowThreads);
     if (d->fd_half_width != 4)
         return fail(KS_E_UNSUPPORTED, "fd_half_width %d (only 4)",
                     d->fd_half_width);
@@ -1150,7 +1170,8 @@ int ks_current(ks_grid *g, const void *d_psi, double t, double out_host[3])
                       hpsi_lds_bytes(G.nx, TY, g->zchunk, false) >
                           kLdsDefault))
         --TY;
-    if (!tile_ok(g, TY, 1))
+    if (!tile_ok(g, TY, 1) ||
+        hpsi_lds_bytes(G.nx, TY, g->zchunk, false) > kLdsBudget)
         return fail(KS_E_UNSUPPORTED, "no tile shape for the current");
     HArgs h = base_hargs(g);
     h.rowinfo = nullptr;
@@ -2176,7 +2197,7 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
         std::vector<int> off(njobs + 1, 0);
         long sum = 0;
         for (int i = 0; i < njobs; ++i) {
-            const long n = batch_items(kind, b->hjobs[i]);
+            const long n = batch_items(kind, b->hjobs[i], b->mixed);
             // H.psi: every job's launch range starts at a multiple of 8
             // (the kernel's per-job XCD remap)
             sum += kind == kItemHpsi ? (n + 7) / 8 * 8 : n;

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_gather_finalize_batch(BArgs b)
 }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_kbapply_batch(BArgs b)
+__global__ __launch_bounds__(kApplyThreads) void k_kbapply_batch(BArgs b)
 {
     const int total = cp(b.off)[b.njobs];
     for (int L = blockIdx.x; L < total; L += gridDim.x) {
@@ -151,7 +151,7 @@ __global__ void k_step_set(int *const *steps, int njobs, const int *values)
         *steps[j] = values[j];
 }
 
-int batch_items(int kind, const JobDev &J)
+int batch_items(int kind, const JobDev &J, bool mixed)
 {
     switch (kind) {
     case kItemHpsi:
@@ -169,8 +169,7 @@ int batch_items(int kind, const JobDev &J)
                    : 0;
     case kItemApply:
         return (J.g.pj.natoms > 0 && J.g.pj.nhull > 0)
-                   ? J.g.pj.nhchunk *
-                         ((J.stot + kApplyStates - 1) / kApplyStates)
+                   ? J.g.pj.nhchunk * apply_groups(J.stot, mixed)
                    : 0;
     }
     return 0;
@@ -303,10 +302,10 @@ hipError_t launch_projectors_batch(bool mixed, const BArgs &bg,
     if (ba.off_total > 0) {
         if (!mixed)
             hipLaunchKernelGGL((k_kbapply_batch<double>), dim3(grid),
-                               dim3(256), 0, st, ba);
+                               dim3(kApplyThreads), 0, st, ba);
         else
             hipLaunchKernelGGL((k_kbapply_batch<float>), dim3(grid),
-                               dim3(256), 0, st, ba);
+                               dim3(kApplyThreads), 0, st, ba);
         return hipGetLastError();
     }
     return hipSuccess;

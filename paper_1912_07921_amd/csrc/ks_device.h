@@ -388,11 +388,12 @@ __device__ __forceinline__ int xcd_remap(int L, int nblk)
 // boundary; written once) or Bloch-wrapped values.  The stencil reads its x
 // and y neighbours there without branches; the z neighbours come from a
 // per-thread register queue.  Per z-plane: one barrier, two plane buffers
-// alternating.  Every stream is fetched two planes ahead of its use: the
-// halo of plane z+2, the own column of plane z+6, the potential and the KB
-// term of plane z+2 are in flight while plane z is computed.  The KB term
-// V_NL in is precomputed on the hull rows (k_kbapply) and added with one
-// coalesced read.
+// alternating.  Every stream is fetched PF planes ahead of its use (PF = 1
+// in the FP64 kernels, 2 in the FP32 ones, whose registers allow a second
+// set): the halo of plane z+PF, the own column of plane z+4+PF, the
+// potential and the KB term of plane z+PF are in flight while plane z is
+// computed.  The KB term V_NL in is precomputed on the hull rows
+// (k_kbapply) and added with one coalesced read.
 // ---------------------------------------------------------------------------
 extern __shared__ double2 smem_d2[];
 
@@ -927,9 +928,6 @@ __device__ __forceinline__ void proj_shape(double dx, double dy, double dz,
 #ifndef KS_GATHER_SPW
 #define KS_GATHER_SPW 2
 #endif
-#ifndef KS_APPLY_SPW
-#define KS_APPLY_SPW 4
-#endif
 constexpr int kGatherChunk = KS_GATHER_CHUNK;
 constexpr int kGatherSPW = KS_GATHER_SPW;   // states per wavefront
 constexpr int kGatherStates = 4 * kGatherSPW;
@@ -1074,85 +1072,89 @@ __device__ __forceinline__ void gather_finalize_item(const GArgs &a,
 
 // V_NL in on the hull: W[s][h] = sum over atoms a whose sphere holds hull
 // point h of sum_j P_j(r) rad(r) D[s][a][j] exp(-i k.T).  A workgroup takes
-// a chunk of 64 hull points and 4 * kApplySPW states (kApplySPW per
-// wavefront).  The coefficients of the chunk's atoms for the workgroup's
-// states are staged in LDS, kApplyAtoms at a time, with one round of
-// coalesced loads; each lane then walks only the spheres that contain its
-// point (the hull entries, in atom order: deterministic), with projector
-// values tabulated once per grid, so no lane works on an atom whose sphere
-// misses its point and no shape is evaluated per pass.
-constexpr int kApplySPW = KS_APPLY_SPW;
-constexpr int kApplyStates = 4 * kApplySPW;
-constexpr int kApplyAtoms = 12;
-
-// The coefficients of each atom take kApplyStates * kMaxProj values plus
-// one of padding, so that lanes reading different atoms at the same
-// (state, projector) fall in different LDS banks (an unpadded atom stride
-// is a multiple of the bank count).
-template <class R> struct ApplyLds {
-    using V = typename Cplx<R>::T;
-    int np[kApplyAtoms];
-    V D[kApplyAtoms][kApplyStates * kMaxProj + 1];
-};
+// a chunk of 64 hull points (one per lane) and kApplyWaves * SPW states
+// (SPW per wavefront).  The wavefront walks the chunk's atoms in a uniform
+// loop; for atom i every lane whose hull point lies in its sphere (the
+// lane's next hull entry has slot i: entries are in atom order, so each
+// lane still adds its terms in atom order, deterministically) adds the
+// atom's term.  The projector values come from a per-grid table of the
+// entries (evaluated once at creation), the coefficients of the atom and
+// the wavefront's states through scalar loads (one address for the whole
+// wavefront): no LDS staging, no barrier, no per-lane coefficient read.
+// (Staging the coefficients in LDS and reading them per lane cost 23 %
+// more at 128^3 x 256, 26 % more in the FP32 kernels.)
+#ifndef KS_APPLY_SPW
+#define KS_APPLY_SPW 4        // states per wavefront, FP64
+#endif
+#ifndef KS_APPLY_SPW32
+#define KS_APPLY_SPW32 8      // states per wavefront, FP32
+#endif
+#ifndef KS_APPLY_WAVES
+#define KS_APPLY_WAVES 4
+#endif
+constexpr int kApplyWaves = KS_APPLY_WAVES;
+constexpr int kApplyThreads = 64 * kApplyWaves;
+template <class R> constexpr int apply_spw()
+{
+    return sizeof(R) == 8 ? KS_APPLY_SPW : KS_APPLY_SPW32;
+}
+// state groups of the apply for ns states
+__host__ __device__ constexpr int apply_groups(int ns, bool mixed)
+{
+    return (ns + kApplyWaves * (mixed ? KS_APPLY_SPW32 : KS_APPLY_SPW) - 1) /
+           (kApplyWaves * (mixed ? KS_APPLY_SPW32 : KS_APPLY_SPW));
+}
+template <class T> using kptr_t = __attribute__((address_space(4))) const T *;
 
 template <class R>
 __device__ __forceinline__ void kbapply_item(const GArgs &a, const int chunk,
                                              const int grp)
 {
     using V = typename Cplx<R>::T;
-    __shared__ ApplyLds<R> sh;
+    constexpr int SPW = apply_spw<R>();
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int sb = grp * kApplyStates;               // first state of the WG
-    const int s0 = sb + wave * kApplySPW;
+    const int s0 = (grp * kApplyWaves + wave) * SPW;
     const int h = chunk * kHullChunk + lane;
     const bool valid = h < a.pj.nhull;
-    // the spheres containing this hull point (entries in atom order)
-    const int e0 = valid ? gp(a.pj.he_off)[h] : 0;
+    int e = valid ? gp(a.pj.he_off)[h] : 0;
     const int e1 = valid ? gp(a.pj.he_off)[h + 1] : 0;
-    V acc[kApplySPW];
+    const int c0 = __builtin_amdgcn_readfirstlane(gp(a.pj.hc_off)[chunk]);
+    const int c1 =
+        __builtin_amdgcn_readfirstlane(gp(a.pj.hc_off)[chunk + 1]);
+    V acc[SPW];
 #pragma unroll
-    for (int q = 0; q < kApplySPW; ++q)
+    for (int q = 0; q < SPW; ++q)
         acc[q] = czero<V>();
-    const int c0 = gp(a.pj.hc_off)[chunk], c1 = gp(a.pj.hc_off)[chunk + 1];
-    for (int b0 = c0; b0 < c1; b0 += kApplyAtoms) {
-        const int nb = min(kApplyAtoms, c1 - b0);
-        __syncthreads();              // the previous batch has been read
-        if (tid < nb)
-            sh.np[tid] = gp(a.pj.nproj)[gp(a.pj.hc_atoms)[b0 + tid]];
-        for (int t = tid; t < nb * kApplyStates * kMaxProj; t += blockDim.x) {
-            const int i = t / (kApplyStates * kMaxProj);
-            const int r = t - i * (kApplyStates * kMaxProj);
-            const int q = r / kMaxProj, j = r - q * kMaxProj;
-            const int at = gp(a.pj.hc_atoms)[b0 + i];
-            const int sl = sb + q;
-            V d = czero<V>();
-            if (sl < a.ns)
-                d = gld(reinterpret_cast<const V *>(a.D) +
-                        ((size_t)sl * a.pj.natoms + at) * kMaxProj + j);
-            sh.D[i][q * kMaxProj + j] = d;
-        }
-        __syncthreads();
-        for (int e = e0; e < e1; ++e) {
-            const int i = gp(a.pj.he_slot)[e] - (b0 - c0);
-            if (i < 0 || i >= nb)
-                continue;                 // an atom of another batch
-            const int np = sh.np[i];
-            const int code = gp(a.pj.he_code)[e];
-            R p[kMaxProj];
+    int slot = e < e1 ? gp(a.pj.he_slot)[e] : -1;
+    const kptr_t<R> Dall = (kptr_t<R>)reinterpret_cast<const R *>(a.D);
+    for (int i = 0; i < c1 - c0; ++i) {
+        const int at =
+            __builtin_amdgcn_readfirstlane(gp(a.pj.hc_atoms)[c0 + i]);
+        if (slot != i)
+            continue;
+        const int code = gp(a.pj.he_code)[e];
+        R p[kMaxProj];
 #pragma unroll
-            for (int j = 0; j < kMaxProj; ++j)
-                p[j] = (R)gp(a.pj.he_p)[(size_t)e * kMaxProj + j];
+        for (int j = 0; j < kMaxProj; ++j)
+            p[j] = (R)gp(a.pj.he_p)[(size_t)e * kMaxProj + j];
+        // all 9 projectors: past the atom's count both the coefficients
+        // and the tabulated values are zero
 #pragma unroll
-            for (int q = 0; q < kApplySPW; ++q) {
-                const int sl = s0 + q;
-                if (sl >= a.ns)
-                    break;
-                const V *D = &sh.D[i][(wave * kApplySPW + q) * kMaxProj];
+        for (int q = 0; q < SPW; ++q) {
+            const int sl = s0 + q;
+            if (sl < a.ns) {
+                const kptr_t<R> D =
+                    Dall + 2 * ((size_t)sl * a.pj.natoms + at) * kMaxProj;
+                R d[2 * kMaxProj];
+#pragma unroll
+                for (int j = 0; j < 2 * kMaxProj; ++j)
+                    d[j] = D[j];
                 V t = czero<V>();
-                for (int j = 0; j < np; ++j)
-                    t = cadd(t, cscale(D[j], p[j]));
+#pragma unroll
+                for (int j = 0; j < kMaxProj; ++j)
+                    t = cadd(t, cscale(cmk<V>(d[2 * j], d[2 * j + 1]), p[j]));
                 if (code) {
                     const int kk = (a.sg0 + sl) / a.nstates;
                     t = cmul(t, shift_phase<V>(a.kph + 3 * kk, code));
@@ -1160,10 +1162,12 @@ __device__ __forceinline__ void kbapply_item(const GArgs &a, const int chunk,
                 acc[q] = cadd(acc[q], t);
             }
         }
+        ++e;
+        slot = e < e1 ? gp(a.pj.he_slot)[e] : -1;
     }
     if (valid)
 #pragma unroll
-        for (int q = 0; q < kApplySPW; ++q) {
+        for (int q = 0; q < SPW; ++q) {
             const int sl = s0 + q;
             if (sl < a.ns)
                 gst(reinterpret_cast<V *>(a.W) + (size_t)sl * a.pj.nhull + h,

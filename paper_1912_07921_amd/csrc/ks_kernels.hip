@@ -19,7 +19,7 @@ __global__ __launch_bounds__(256) void k_gather_finalize(GArgs a)
 }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_kbapply(GArgs a)
+__global__ __launch_bounds__(kApplyThreads) void k_kbapply(GArgs a)
 {
     kbapply_item<R>(a, blockIdx.x, blockIdx.y);
 }
@@ -393,11 +393,13 @@ hipError_t launch_kbapply(bool mixed, const GArgs &a, int ns, hipStream_t st)
         return hipSuccess;
     GArgs b = a;
     b.ns = ns;
-    dim3 grid(a.pj.nhchunk, (ns + kApplyStates - 1) / kApplyStates);
+    dim3 grid(a.pj.nhchunk, apply_groups(ns, mixed));
     if (!mixed)
-        hipLaunchKernelGGL((k_kbapply<double>), grid, dim3(256), 0, st, b);
+        hipLaunchKernelGGL((k_kbapply<double>), grid, dim3(kApplyThreads), 0,
+                           st, b);
     else
-        hipLaunchKernelGGL((k_kbapply<float>), grid, dim3(256), 0, st, b);
+        hipLaunchKernelGGL((k_kbapply<float>), grid, dim3(kApplyThreads), 0,
+                           st, b);
     return hipGetLastError();
 }
 

@@ -74,14 +74,16 @@ def test_grid_description_errors_need_no_gpu():
 
 def test_grid_size_limits_need_no_gpu():
     """Axis lengths the kernels cannot index are refused before any device
-    call: nx above 192 (tile rows of at most 512 threads), and with atoms
-    ny above 1024 or nz above 2048 (packed point coordinates)."""
+    call: nx above 512 (tile rows of at most 512 threads), 2^27 points or
+    more (32-bit byte offsets of a state), and with atoms ny above 1024 or
+    nz above 2048 (packed point coordinates)."""
     from types import SimpleNamespace
     from paper_1912_07921_amd import ks
     null_stream = SimpleNamespace(cuda_stream=0)
     atom = dict(pos=[[0.0, 0.0, 0.0]], Z=[1.0], lmax=[1], rc=[1.0],
                 sigma=[0.5], E=[[1.0, -1.0, 0.0]])
-    for n, kw, word in [((193, 4, 4), {}, b"nx"),
+    for n, kw, word in [((513, 4, 4), {}, b"nx"),
+                        ((512, 512, 512), {}, b"2^27"),
                         ((8, 1025, 4), atom, b"ny"),
                         ((8, 4, 2049), atom, b"nz")]:
         spec = W.SystemSpec(n=n, h=(0.4,) * 3, nstates=1, **kw)

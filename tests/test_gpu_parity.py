@@ -95,15 +95,38 @@ def test_apply_h_degenerate_grids(torch_cuda, oracle_mod, n, periodic):
     apply_parity(torch_cuda, oracle_mod, spec, v, psi)
 
 
-@pytest.mark.parametrize("periodic", [(0, 0, 0), (1, 1, 0)])
-def test_apply_h_widest_rows(torch_cuda, oracle_mod, periodic):
-    """The widest x-row the kernel takes (nx = 192, so one row fills three
-    wavefronts and a tile is two rows), with projectors and Bloch wraps."""
-    spec, v, psi = W.tiny(n=(192, 7, 9), h=(0.15, 0.4, 0.4),
+@pytest.mark.parametrize("nx,periodic", [(192, (0, 0, 0)), (192, (1, 1, 0)),
+                                         (256, (0, 0, 0)), (256, (1, 1, 1)),
+                                         (320, (0, 0, 0)), (300, (1, 0, 0)),
+                                         (512, (0, 0, 0)), (512, (1, 1, 0))])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_apply_h_wide_rows(torch_cuda, oracle_mod, nx, periodic, prec):
+    """Wide x-rows up to the widest the kernel takes (nx = 512: one row is
+    a tile of 512 threads, and in FP64 the LDS planes alone exceed the
+    default share, so the z-chunk is bounded by the CU's LDS only), rows
+    that are not a multiple of the wavefront (300, 320), with projectors,
+    Bloch wraps and the gauge term."""
+    spec, v, psi = W.tiny(n=(nx, 7, 9), h=(0.15, 0.4, 0.4),
                           periodic=periodic, nk=1, nstates=2, natoms=2,
                           lmax=2, rc=1.1, sigma=0.35,
                           laser=(0.3, 0.8, 4.0, 0.6, 0.0, 0.8))
-    apply_parity(torch_cuda, oracle_mod, spec, v, psi, A_t=1.1)
+    apply_parity(torch_cuda, oracle_mod, spec, v, psi, A_t=1.1, prec=prec,
+                 tol=1e-12 if prec == 0 else 1e-5)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_propagate_widest_rows(torch_cuda, oracle_mod, prec):
+    """ETRS (every pass type, the density, exchange and dipole) on a grid
+    of 512-point rows."""
+    spec, v, psi = W.tiny(n=(512, 6, 7), h=(0.12, 0.4, 0.4), nk=1,
+                          nstates=2, natoms=2, lmax=2, rc=1.1, sigma=0.35,
+                          xc=1, laser=(0.3, 0.8, 3.0, 0.2, 0.1, 0.9))
+    h3 = np.prod(spec.h)
+    psi = psi / np.sqrt(np.sum(np.abs(psi) ** 2, axis=2, keepdims=True) * h3)
+    res = propagate_parity(torch_cuda, oracle_mod, spec, 0.3 * v, psi, 3,
+                           0.01, t0=0.2, kick=0.05, prec=prec, dip_tol=1e-6)
+    if prec:
+        assert res["psi"] < 1e-5, res
 
 
 def test_apply_h_no_states_and_sub_ranges(torch_cuda, oracle_mod):
