@@ -59,16 +59,17 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(workload):
+def recorded_traffic(workload, key="traffic_bytes_per_launch"):
     """HBM bytes per H.psi launch recorded from rocprofv3 FETCH_SIZE and
     WRITE_SIZE runs (scaled by the copy-kernel calibration), if the kernel
-    source has not changed since; else None."""
+    source has not changed since; else None.  key: the FP64 kernel's line,
+    or "mixed_traffic_bytes_per_launch" for the FP32 one."""
     path = os.path.join(PROFILES, f"hpsi_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)\s+"
-                  r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    m = re.search(r"^" + key + r":\s*([0-9.eE+]+)\s+"
+                  r"kernel_source_sha256_16:\s*([0-9a-f]+)", text, re.M)
     if not m or m.group(2) != kernel_source_hash():
         return None
     return float(m.group(1))
@@ -636,7 +637,9 @@ def main():
                                      (msec / args.steps) / 1e9 /
                                      HBM_PEAK_GBS, 4),
                      norm_drift_max=float(abs(nrmm - nrm64).max()),
-                     launch_shape=mshape)
+                     launch_shape=mshape,
+                     traffic=recorded_traffic(
+                         args.workload, "mixed_traffic_bytes_per_launch"))
         if dip64 is not None:
             mixed["dipole_err_vs_fp64"] = float(abs(dipm - dip64).max())
         out["mixed"] = mixed
