@@ -129,6 +129,14 @@ int ks_set_stream(ks_grid *g, void *stream);
  * the half-step state, density partials, projector coefficients). */
 size_t ks_workspace_bytes(const ks_grid *g);
 
+/* Device memory the grid holds itself since ks_grid_create: the potential,
+ * phase and weight tables, the projector sphere and hull tables, and the
+ * Hartree plan (twiddles and kernel), in bytes, into *out (host).  The
+ * caller-lent workspace is not included.  For admission control by a
+ * caller that budgets HBM (the serving loop counts it in a request's
+ * footprint).  KS_E_ARG on NULL arguments. */
+int ks_grid_device_bytes(const ks_grid *g, size_t *out);
+
 /* Lend the object a caller-owned device workspace of at least
  * ks_workspace_bytes() bytes, 256-byte aligned; KS_E_OOM if too small. */
 int ks_set_workspace(ks_grid *g, void *d_ws, size_t bytes);

@@ -76,6 +76,9 @@ struct ks_grid {
     // launch shape
     int TY = 1, zchunk = 1, ntile_y = 1, nzc = 1, rpt = 1;
 
+    // device bytes of the tables allocated by dev_alloc
+    size_t owned_bytes = 0;
+
     // workspace
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -118,6 +121,7 @@ template <class T> int dev_alloc(ks_grid *g, T **p, size_t count)
         return fail(KS_E_OOM, "hipMalloc(%zu): %s", bytes,
                     hipGetErrorString(e));
     g->owned.push_back(q);
+    g->owned_bytes += bytes;
     *p = static_cast<T *>(q);
     return KS_OK;
 }
@@ -1059,6 +1063,22 @@ int ks_grid_destroy(ks_grid *g)
         (void)hipHostFree(g->h_norms);
     poisson_plan_destroy(&g->pp);
     delete g;
+    return KS_OK;
+}
+
+int ks_grid_device_bytes(const ks_grid *g, size_t *out)
+{
+    if (!g || !out)
+        return fail(KS_E_ARG, "grid or output is NULL");
+    size_t b = g->owned_bytes;
+    // the Hartree plan: twiddles per axis and the kernel's octant
+    if (g->pp.K) {
+        for (int d = 0; d < 3; ++d)
+            b += sizeof(double2) * g->pp.ax[d].M;
+        b += sizeof(double) * (size_t)(g->pp.ax[0].M / 2 + 1) *
+             (g->pp.ax[1].M / 2 + 1) * (g->pp.ax[2].M / 2 + 1);
+    }
+    *out = b;
     return KS_OK;
 }
 

@@ -120,6 +120,8 @@ EXPORTS = {
                                       C.POINTER(C.c_int)]),
     "ks_batch_destroy": (C.c_int, [C.c_void_p]),
     "ks_check_finite": (C.c_int, [C.c_void_p, C.c_long]),
+    "ks_grid_device_bytes": (C.c_int, [C.c_void_p,
+                                       C.POINTER(C.c_size_t)]),
     "ks_last_error": (C.c_char_p, []),
 }
 
@@ -223,6 +225,12 @@ def ks_set_stream(h, stream):
 
 def ks_workspace_bytes(h):
     return int(lib().ks_workspace_bytes(h))
+
+
+def ks_grid_device_bytes(h):
+    out = C.c_size_t(0)
+    _check(lib().ks_grid_device_bytes(h, C.byref(out)))
+    return int(out.value)
 
 
 def ks_set_workspace(h, ws):
@@ -476,6 +484,12 @@ class Grid:
     @property
     def workspace_bytes(self):
         return ks_workspace_bytes(self.h)
+
+    @property
+    def device_bytes(self):
+        """Device memory the grid holds itself (tables, potential, Hartree
+        plan; not the workspace)."""
+        return ks_grid_device_bytes(self.h)
 
     def set_stream(self, stream):
         ks_set_stream(self.h, stream)

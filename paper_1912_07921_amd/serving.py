@@ -107,9 +107,27 @@ class Server:
 
     # ---- footprint ----
     def _footprint(self, req, grid):
+        """HBM a resident request holds: its states, the grid's workspace
+        and own tables, v_ion, the dipole and norm traces."""
         N, S = req.spec.npoints, req.spec.nk * req.spec.nstates
-        return (16 * N * S + grid.workspace_bytes + 8 * N +
-                8 * (req.nsteps + 1) * (3 + S) + 4096)
+        return (16 * N * S + grid.workspace_bytes + grid.device_bytes +
+                8 * N + 8 * (req.nsteps + 1) * (3 + S) + 4096)
+
+    def _head_grid(self, waiting):
+        """Give the request at the head of the queue its grid and
+        footprint (the grid's tables are allocated here)."""
+        if not waiting or waiting[0][1] is not None:
+            return
+        r = waiting[0][0]
+        g = ks.Grid(r.spec, precision=self.precision, device=self.device,
+                    workspace=False)
+        set_serving_launch(g, r.spec)
+        fp = self._footprint(r, g)
+        if fp > self.budget:
+            g.close()
+            raise ValueError(f"request {r.rid} needs {fp} bytes, more than "
+                             f"the budget {self.budget}")
+        waiting[0][1:] = [g, fp]
 
     def _admit(self, req, grid, now):
         grid.ensure_workspace()
@@ -141,10 +159,18 @@ class Server:
     # ---- main loop ----
     def run(self, requests):
         """Serve `requests` (sorted by arrival) to completion; returns the
-        statistics dict (also in self.stats)."""
+        statistics dict (also in self.stats).
+
+        One batch step stays in flight: the next step is enqueued before
+        the host waits for the previous one, unless a job leaves or joins
+        after it (membership changes need the batch drained), so the GPU
+        does not idle while the host does its per-step bookkeeping."""
         torch = self.torch
         pending = deque(sorted(requests, key=lambda r: r.arrival))
-        waiting = deque()        # (request, grid) arrived, not admitted
+        # [request, grid, footprint] arrived, not admitted; only the head
+        # holds a grid (created when it is next to be admitted), so device
+        # memory outside the budget is at most one grid's tables
+        waiting = deque()
         active = []
         used = 0
         batch = None
@@ -155,6 +181,7 @@ class Server:
         lat = []
         work = 0.0
         busy = 0.0
+        inflight = None          # (start event, end event, members)
         t_start = time.perf_counter()
 
         def now():
@@ -162,32 +189,59 @@ class Server:
                 return float(steps_taken)
             return time.perf_counter() - t_start
 
+        def finish(rec):
+            """Wait for an enqueued step and charge it to its members."""
+            nonlocal busy, work
+            ev0, ev1, members = rec
+            ev1.synchronize()
+            t1 = time.perf_counter()
+            busy += ev0.elapsed_time(ev1) / 1e3
+            for a in members:
+                dt_step = t1 - a.t_ready
+                a.t_ready = t1
+                a.req.step_latency.append(dt_step)
+                lat.append(dt_step)
+                work += 8.0 * a.req.pts_states
+
         t_first = None
         while pending or waiting or active:
             tnow = now()
             while pending and pending[0].arrival <= tnow:
-                r = pending.popleft()
-                g = ks.Grid(r.spec, precision=self.precision,
-                            device=self.device, workspace=False)
-                set_serving_launch(g, r.spec)
-                fp = self._footprint(r, g)
-                if fp > self.budget:
-                    g.close()
-                    raise ValueError(f"request {r.rid} needs {fp} bytes, "
-                                     f"more than the budget {self.budget}")
-                waiting.append((r, g, fp))
-            changed = False
+                waiting.append([pending.popleft(), None, 0])
+            self._head_grid(waiting)
+            # jobs whose last step has been enqueued leave: drain the batch
+            done = [a for i, a in enumerate(active)
+                    if batch is not None and
+                    batch.steps_done(i) >= a.req.nsteps]
+            if done:
+                if inflight is not None:
+                    finish(inflight)
+                    inflight = None
+                batch.close()
+                batch = None
+                tn = now()
+                for a in done:
+                    self._retire(a, tn)
+                    used -= a.fp
+                    active.remove(a)
             # while a batch runs, newly arrived requests join at the next
             # departure unless it is more than join_lag steps away
             join_now = batch is None or not active or min(
                 a.req.nsteps - batch.steps_done(i)
                 for i, a in enumerate(active)) > self.join_lag
+            admit = (join_now and waiting and len(active) < self.max_slots
+                     and used + waiting[0][2] <= self.budget)
+            if admit and inflight is not None:
+                finish(inflight)
+                inflight = None
+            changed = False
             while (join_now and waiting and len(active) < self.max_slots and
                    used + waiting[0][2] <= self.budget):
                 r, g, fp = waiting.popleft()
                 active.append(self._admit(r, g, tnow))
                 used += active[-1].fp
                 changed = True
+                self._head_grid(waiting)
             if not active:
                 if self.clock == "steps":
                     steps_taken += 1      # idle tick
@@ -205,29 +259,18 @@ class Server:
                 rebuilds += 1
                 rebuild_s += time.perf_counter() - t_rb
             max_active = max(max_active, len(active))
-            t0 = time.perf_counter()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record()
             batch.step(1)
-            torch.cuda.current_stream().synchronize()
-            t1 = time.perf_counter()
-            busy += t1 - t0
+            ev1.record()
             steps_taken += 1
-            done = []
-            for i, a in enumerate(active):
-                dt_step = t1 - a.t_ready
-                a.t_ready = t1
-                a.req.step_latency.append(dt_step)
-                lat.append(dt_step)
-                work += 8.0 * a.req.pts_states
-                if batch.steps_done(i) >= a.req.nsteps:
-                    done.append(a)
-            if done:
-                batch.close()
-                batch = None
-                tn = now()
-                for a in done:
-                    self._retire(a, tn)
-                    used -= a.fp
-                    active.remove(a)
+            rec = (ev0, ev1, list(active))
+            if inflight is not None:
+                finish(inflight)
+            inflight = rec
+        if inflight is not None:
+            finish(inflight)
         if batch is not None:
             batch.close()
         t_end = time.perf_counter()

@@ -148,3 +148,17 @@ def test_served_requests_match_the_oracle(torch_cuda, oracle_mod,
     else:
         assert worst["dip"] < 1e-6 and worst["psi"] < 1e-6
         assert worst["norm"] < 1e-7
+
+
+def test_grid_device_bytes_count_its_tables(torch_cuda):
+    """The bytes a grid reports holding (counted in a request's footprint)
+    cover its potential and grow with its projector tables."""
+    from paper_1912_07921_amd import ks
+    spec0, _, _ = W.tiny(n=(24, 20, 22), natoms=0)
+    spec1, _, _ = W.tiny(n=(24, 20, 22), natoms=3, lmax=2, rc=1.6)
+    g0, g1 = ks.Grid(spec0, workspace=False), ks.Grid(spec1, workspace=False)
+    b0, b1 = g0.device_bytes, g1.device_bytes
+    assert b0 >= 8 * spec0.npoints
+    assert b1 > b0 + 9 * 8 * 100     # at least 100 sphere points' values
+    g0.close()
+    g1.close()
