@@ -1165,13 +1165,16 @@ __device__ __forceinline__ void kbapply_item(const GArgs &a, const int chunk,
         ++e;
         slot = e < e1 ? gp(a.pj.he_slot)[e] : -1;
     }
+    // W is read once, by the next H.psi pass, and is larger than the MALL:
+    // non-temporal stores
     if (valid)
 #pragma unroll
         for (int q = 0; q < SPW; ++q) {
             const int sl = s0 + q;
             if (sl < a.ns)
-                gst(reinterpret_cast<V *>(a.W) + (size_t)sl * a.pj.nhull + h,
-                    acc[q]);
+                st_stream(reinterpret_cast<V *>(a.W) +
+                              (size_t)sl * a.pj.nhull + h,
+                          acc[q].x, acc[q].y);
         }
 }
 
