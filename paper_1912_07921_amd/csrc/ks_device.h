@@ -238,11 +238,40 @@ template <> __device__ __forceinline__ float2 bld_raw<float2>(BufRes r,
                               __builtin_amdgcn_raw_buffer_load_b64(r, off, 0,
                                                                    0));
 }
+// the same with the non-temporal hint (streams read once)
+#ifndef KS_NT_ONCE
+#define KS_NT_ONCE 1
+#endif
+template <class T>
+__device__ __forceinline__ T bld_raw_nt(BufRes r, unsigned off);
+template <>
+__device__ __forceinline__ double2 bld_raw_nt<double2>(BufRes r, unsigned off)
+{
+    return __builtin_bit_cast(
+        double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0,
+                                                       KS_NT_ONCE ? 2 : 0));
+}
+template <>
+__device__ __forceinline__ float2 bld_raw_nt<float2>(BufRes r, unsigned off)
+{
+    return __builtin_bit_cast(
+        float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0,
+                                                     KS_NT_ONCE ? 2 : 0));
+}
 // complex value of storage type T at byte offset off, in precision R
 template <class R, class T>
 __device__ __forceinline__ typename Cplx<R>::T bld(BufRes r, unsigned off)
 {
     const T v = bld_raw<T>(r, off);
+    typename Cplx<R>::T o;
+    o.x = (R)v.x;
+    o.y = (R)v.y;
+    return o;
+}
+template <class R, class T>
+__device__ __forceinline__ typename Cplx<R>::T bld_nt(BufRes r, unsigned off)
+{
+    const T v = bld_raw_nt<T>(r, off);
     typename Cplx<R>::T o;
     o.x = (R)v.x;
     o.y = (R)v.y;
@@ -663,12 +692,12 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
         if (KS_HPSI_PF == 2) {
             sv[1][r] = v_ld(v_off(r, z0 + 1));
             sv[0][r] = v_ld(v_off(r, z0));
-            skb[1][r] = bld<R, V>(rw, kb_off(r, z0 + 1));
-            skb[0][r] = bld<R, V>(rw, kb_off(r, z0));
+            skb[1][r] = bld_nt<R, V>(rw, kb_off(r, z0 + 1));
+            skb[0][r] = bld_nt<R, V>(rw, kb_off(r, z0));
         } else {
             sv[1][r] = v_ld(v_off(r, z0));
             sv[0][r] = 0.0;
-            skb[1][r] = bld<R, V>(rw, kb_off(r, z0));
+            skb[1][r] = bld_nt<R, V>(rw, kb_off(r, z0));
             skb[0][r] = czero<V>();
         }
     }
@@ -724,11 +753,12 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
         for (int r = 0; r < RPT; ++r) {
             if constexpr (FIN) {
                 const unsigned gi = (unsigned)(z * P + po[r]);
-                fb[r] = bld_raw<double2>(rbase, act[r] ? gi * 16u : kOOB);
-                f1[r] = bld_raw<TT>(rt1,
-                                    act[r] ? gi * (unsigned)sizeof(TT) : kOOB);
-                f2[r] = bld_raw<TT>(rt2,
-                                    act[r] ? gi * (unsigned)sizeof(TT) : kOOB);
+                fb[r] = bld_raw_nt<double2>(rbase,
+                                            act[r] ? gi * 16u : kOOB);
+                f1[r] = bld_raw_nt<TT>(
+                    rt1, act[r] ? gi * (unsigned)sizeof(TT) : kOOB);
+                f2[r] = bld_raw_nt<TT>(
+                    rt2, act[r] ? gi * (unsigned)sizeof(TT) : kOOB);
             }
         }
 #pragma unroll
@@ -738,7 +768,7 @@ __device__ __forceinline__ void hpsi_item(const HArgs &a, const int w,
         for (int r = 0; r < RPT; ++r) {
             snq[LS][r] = bld<R, InT>(rin, col_off(r, z + kHalf + PF));
             sv[LS][r] = v_ld(v_off(r, z + PF));
-            skb[LS][r] = bld<R, V>(rw, kb_off(r, z + PF));
+            skb[LS][r] = bld_nt<R, V>(rw, kb_off(r, z + PF));
         }
         __syncthreads();
 #pragma unroll

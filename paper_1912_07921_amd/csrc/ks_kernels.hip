@@ -29,6 +29,12 @@ __global__ __launch_bounds__(kApplyThreads) void k_kbapply(GArgs a)
 // weighted |psi|^2); optional v = v_ion + v_x(rho); optional dipole partials
 // ---------------------------------------------------------------------------
 constexpr int kDensThreads = 256;
+#ifndef KS_DENS_U
+#define KS_DENS_U 8
+#endif
+#ifndef KS_DENS_NT
+#define KS_DENS_NT 1
+#endif
 
 // block blk of the density launch of `a` (sbuf: 3 doubles per wavefront)
 __device__ __forceinline__ void density_block(const DArgs &a, long blk,
@@ -38,8 +44,9 @@ __device__ __forceinline__ void density_block(const DArgs &a, long blk,
     const long g = blk * kDensThreads + threadIdx.x;
     double rho = 0.0;
     if (g < G.N) {
-        // sources in order; eight loads issued before their adds
-        constexpr int U = 8;
+        // sources in order; U loads issued before their adds (the
+        // partials are read once: non-temporal)
+        constexpr int U = KS_DENS_U;
         int s = 0;
         if (a.npart) {
             const double *p = a.npart + g;
@@ -47,7 +54,9 @@ __device__ __forceinline__ void density_block(const DArgs &a, long blk,
                 double v[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    v[u] = p[(size_t)(s + u) * G.N];
+                    v[u] = KS_DENS_NT ? __builtin_nontemporal_load(
+                                            gp(p + (size_t)(s + u) * G.N))
+                                      : p[(size_t)(s + u) * G.N];
 #pragma unroll
                 for (int u = 0; u < U; ++u)
                     rho += v[u];
