@@ -2217,7 +2217,7 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
         std::vector<int> off(njobs + 1, 0);
         long sum = 0;
         for (int i = 0; i < njobs; ++i) {
-            const long n = batch_items(kind, b->hjobs[i], b->mixed);
+            const long n = batch_items(kind, b->hjobs[i]);
             // H.psi: every job's launch range starts at a multiple of 8
             // (the kernel's per-job XCD remap)
             sum += kind == kItemHpsi ? (n + 7) / 8 * 8 : n;

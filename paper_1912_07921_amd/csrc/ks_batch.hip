@@ -132,7 +132,8 @@ __global__ __launch_bounds__(kApplyThreads) void k_kbapply_batch(BArgs b)
         const int jb = find_job(b.off, b.njobs, L);
         const GArgs a = cload<GArgs>(&(cp(b.jobs) + jb)->g);
         const int r = L - cp(b.off)[jb];
-        kbapply_item<R>(a, r % a.pj.nhchunk, r / a.pj.nhchunk);
+        kbapply_item<R, KS_APPLY_SPW_SMALL>(a, r % a.pj.nhchunk,
+                                            r / a.pj.nhchunk);
     }
 }
 
@@ -151,7 +152,7 @@ __global__ void k_step_set(int *const *steps, int njobs, const int *values)
         *steps[j] = values[j];
 }
 
-int batch_items(int kind, const JobDev &J, bool mixed)
+int batch_items(int kind, const JobDev &J)
 {
     switch (kind) {
     case kItemHpsi:
@@ -169,7 +170,8 @@ int batch_items(int kind, const JobDev &J, bool mixed)
                    : 0;
     case kItemApply:
         return (J.g.pj.natoms > 0 && J.g.pj.nhull > 0)
-                   ? J.g.pj.nhchunk * apply_groups(J.stot, mixed)
+                   ? J.g.pj.nhchunk *
+                         apply_groups(J.stot, KS_APPLY_SPW_SMALL)
                    : 0;
     }
     return 0;

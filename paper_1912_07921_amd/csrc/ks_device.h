@@ -213,6 +213,23 @@ __device__ __forceinline__ float2 ld_stream(const float2 *p)
 #endif
 }
 
+// a state value at a sphere point for the gather (non-temporal with
+// KS_GATHER_NT: the states are larger than the MALL and the next pass
+// streams them again anyway, while the point tables are re-read by every
+// state group)
+#ifndef KS_GATHER_NT
+#define KS_GATHER_NT 1
+#endif
+template <class R, class T>
+__device__ __forceinline__ typename Cplx<R>::T ldc_g(const T *p, long i)
+{
+    const T v = KS_GATHER_NT ? ld_stream(p + i) : gld(p + i);
+    typename Cplx<R>::T r;
+    r.x = (R)v.x;
+    r.y = (R)v.y;
+    return r;
+}
+
 // Raw buffer accesses (gfx9 buffer descriptor, no stride): an offset at or
 // beyond the buffer's size reads zero and drops a store, so an access with
 // nothing to move needs no branch around it.
@@ -999,7 +1016,7 @@ __device__ __forceinline__ void gather_item(const GArgs &a, const int at,
         for (int q = 0; q < kGatherSPW; ++q) {
             const int sl = s0 + q;
             val[u][q] = (gi[u] >= 0 && sl < a.ns)
-                            ? ldc<R>(reinterpret_cast<const InT *>(a.in) +
+                            ? ldc_g<R>(reinterpret_cast<const InT *>(a.in) +
                                          (size_t)sl * a.geo.N, gi[u])
                             : czero<V>();
         }
@@ -1113,35 +1130,41 @@ __device__ __forceinline__ void gather_finalize_item(const GArgs &a,
 // wavefront): no LDS staging, no barrier, no per-lane coefficient read.
 // (Staging the coefficients in LDS and reading them per lane cost 23 %
 // more at 128^3 x 256, 26 % more in the FP32 kernels.)
-#ifndef KS_APPLY_SPW
-#define KS_APPLY_SPW 4        // states per wavefront, FP64
+// States per wavefront: 8 for launches of many states (fewer hull-entry
+// walks and table reads per state), 4 for few (more workgroups): 128^3 x
+// 256 FP64 1.02 -> 0.92 ms with 8; 64^3 x 32 12.3 -> 16.6 us with 8.
+#ifndef KS_APPLY_SPW_SMALL
+#define KS_APPLY_SPW_SMALL 4
 #endif
-#ifndef KS_APPLY_SPW32
-#define KS_APPLY_SPW32 8      // states per wavefront, FP32
+#ifndef KS_APPLY_SPW_LARGE
+#define KS_APPLY_SPW_LARGE 8
+#endif
+#ifndef KS_APPLY_LARGE_NS
+#define KS_APPLY_LARGE_NS 128
 #endif
 #ifndef KS_APPLY_WAVES
 #define KS_APPLY_WAVES 4
 #endif
 constexpr int kApplyWaves = KS_APPLY_WAVES;
 constexpr int kApplyThreads = 64 * kApplyWaves;
-template <class R> constexpr int apply_spw()
+// states per wavefront of a single-grid launch of ns states (the batched
+// launch, whose jobs are small, takes the small count)
+__host__ __device__ constexpr int apply_spw(int ns)
 {
-    return sizeof(R) == 8 ? KS_APPLY_SPW : KS_APPLY_SPW32;
+    return ns >= KS_APPLY_LARGE_NS ? KS_APPLY_SPW_LARGE : KS_APPLY_SPW_SMALL;
 }
-// state groups of the apply for ns states
-__host__ __device__ constexpr int apply_groups(int ns, bool mixed)
+// state groups of the apply for ns states at spw states per wavefront
+__host__ __device__ constexpr int apply_groups(int ns, int spw)
 {
-    return (ns + kApplyWaves * (mixed ? KS_APPLY_SPW32 : KS_APPLY_SPW) - 1) /
-           (kApplyWaves * (mixed ? KS_APPLY_SPW32 : KS_APPLY_SPW));
+    return (ns + kApplyWaves * spw - 1) / (kApplyWaves * spw);
 }
 template <class T> using kptr_t = __attribute__((address_space(4))) const T *;
 
-template <class R>
+template <class R, int SPW>
 __device__ __forceinline__ void kbapply_item(const GArgs &a, const int chunk,
                                              const int grp)
 {
     using V = typename Cplx<R>::T;
-    constexpr int SPW = apply_spw<R>();
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);

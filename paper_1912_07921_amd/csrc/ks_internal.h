@@ -267,7 +267,7 @@ struct BArgs {
     int pass = 1;                  // Taylor pass 1..8 of the ETRS step
 };
 
-int batch_items(int kind, const JobDev &J, bool mixed);
+int batch_items(int kind, const JobDev &J);
 hipError_t launch_pass_batch(bool mixed, const BArgs &b, bool grad, int hm,
                              int rpt, int nthr, size_t lds, int grid,
                              hipStream_t st);

@@ -18,10 +18,10 @@ __global__ __launch_bounds__(256) void k_gather_finalize(GArgs a)
     gather_finalize_item<R>(a, (long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-template <class R>
+template <class R, int SPW>
 __global__ __launch_bounds__(kApplyThreads) void k_kbapply(GArgs a)
 {
-    kbapply_item<R>(a, blockIdx.x, blockIdx.y);
+    kbapply_item<R, SPW>(a, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -402,13 +402,21 @@ hipError_t launch_kbapply(bool mixed, const GArgs &a, int ns, hipStream_t st)
         return hipSuccess;
     GArgs b = a;
     b.ns = ns;
-    dim3 grid(a.pj.nhchunk, apply_groups(ns, mixed));
-    if (!mixed)
-        hipLaunchKernelGGL((k_kbapply<double>), grid, dim3(kApplyThreads), 0,
-                           st, b);
+    const int spw = apply_spw(ns);
+    dim3 grid(a.pj.nhchunk, apply_groups(ns, spw));
+    constexpr int SL = KS_APPLY_SPW_LARGE, SS = KS_APPLY_SPW_SMALL;
+    if (!mixed && spw == SL)
+        hipLaunchKernelGGL((k_kbapply<double, SL>), grid,
+                           dim3(kApplyThreads), 0, st, b);
+    else if (!mixed)
+        hipLaunchKernelGGL((k_kbapply<double, SS>), grid,
+                           dim3(kApplyThreads), 0, st, b);
+    else if (spw == SL)
+        hipLaunchKernelGGL((k_kbapply<float, SL>), grid, dim3(kApplyThreads),
+                           0, st, b);
     else
-        hipLaunchKernelGGL((k_kbapply<float>), grid, dim3(kApplyThreads), 0,
-                           st, b);
+        hipLaunchKernelGGL((k_kbapply<float, SS>), grid, dim3(kApplyThreads),
+                           0, st, b);
     return hipGetLastError();
 }
 

@@ -129,6 +129,19 @@ def test_propagate_widest_rows(torch_cuda, oracle_mod, prec):
         assert res["psi"] < 1e-5, res
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_apply_h_many_states(torch_cuda, oracle_mod, prec):
+    """A launch of 136 states (at least 128: the projector apply takes 8
+    states per wavefront instead of 4; 136 leaves a ragged state group),
+    periodic with k-points so the Bloch phases of the apply run too."""
+    spec, v, psi = W.tiny(n=(14, 13, 12), h=(0.35, 0.35, 0.35),
+                          periodic=(1, 1, 1), nk=2, nstates=136, natoms=3,
+                          lmax=2, rc=1.3, sigma=0.4,
+                          laser=(0.2, 0.9, 4.0, 0.0, 0.0, 1.0))
+    apply_parity(torch_cuda, oracle_mod, spec, v, psi, A_t=0.8, prec=prec,
+                 tol=1e-12 if prec == 0 else 1e-5)
+
+
 def test_apply_h_no_states_and_sub_ranges(torch_cuda, oracle_mod):
     """ns = 0 is a no-op; a state sub-range [s0, s0+ns) of a k-point gives
     the rows of the full application."""
