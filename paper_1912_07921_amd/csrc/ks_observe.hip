@@ -27,16 +27,19 @@ namespace {
 
 constexpr int kCurThreads = 256;
 
-// Projector part of atom blockIdx.x, state blockIdx.y and axis blockIdx.z:
+// Projector part of atom blockIdx.x and state blockIdx.y, all three axes
+// from one pass over the sphere (the state values and projector shapes are
+// loaded and evaluated once for C_j and the three D_ja):
 // nl[(sl * natoms + at) * 3 + a] = 2 h^3 sum_j N_j^2 h^3 E_j
 // Im(conj(C_j) D_ja).
 __global__ __launch_bounds__(kCurThreads) void k_current_nl(CurArgs a)
 {
-    constexpr int NV = 4 * kMaxProj;   // C_j and D_ja, re and im
+    // per projector: C_j, D_jx, D_jy, D_jz, re and im
+    constexpr int NV = 8 * kMaxProj;
     __shared__ double sbuf[(kCurThreads / 64) * NV];
     const Geo G = a.geo;
     const ProjDev &pj = a.pj;
-    const int at = blockIdx.x, sl = blockIdx.y, ax = blockIdx.z;
+    const int at = blockIdx.x, sl = blockIdx.y;
     const int kk = (a.sg0 + sl) / a.nstates;
     const double2 *psi = a.psi + (size_t)sl * G.N;
     const int np = gp(pj.nproj)[at];
@@ -67,17 +70,20 @@ __global__ __launch_bounds__(kCurThreads) void k_current_nl(CurArgs a)
         double2 v = gld(psi + gi);
         if (code)
             v = cmul(v, shift_phase<double2>(a.kph + 3 * kk, code));
-        const double da = ax == 0 ? d[0] : ax == 1 ? d[1] : d[2];
 #pragma unroll
         for (int j = 0; j < kMaxProj; ++j) {
-            acc[4 * j] += p[j] * v.x;
-            acc[4 * j + 1] += p[j] * v.y;
-            acc[4 * j + 2] += p[j] * da * v.x;
-            acc[4 * j + 3] += p[j] * da * v.y;
+            const double px = p[j] * v.x, py = p[j] * v.y;
+            acc[8 * j] += px;
+            acc[8 * j + 1] += py;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                acc[8 * j + 2 + 2 * ax] += d[ax] * px;
+                acc[8 * j + 3 + 2 * ax] += d[ax] * py;
+            }
         }
     }
     // sum over the workgroup: lanes by wave_sum, waves through LDS (fully
-    // unrolled so the 72 sums stay in registers)
+    // unrolled so the sums stay in registers)
     const int wave = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
@@ -86,23 +92,21 @@ __global__ __launch_bounds__(kCurThreads) void k_current_nl(CurArgs a)
             sbuf[wave * NV + i] = v;
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        double v = 0.0;
-#pragma unroll
-        for (int w = 0; w < kCurThreads / 64; ++w)
-            v += sbuf[w * NV + i];
-        acc[i] = v;
-    }
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 3) {
+        const int ax = threadIdx.x;
         const double h3 = G.h[0] * G.h[1] * G.h[2];
         double out = 0.0;
+        for (int j = 0; j < np; ++j) {
+            double s[4] = {0.0, 0.0, 0.0, 0.0};
+            const int c[4] = {8 * j, 8 * j + 1, 8 * j + 2 + 2 * ax,
+                              8 * j + 3 + 2 * ax};
+            for (int w = 0; w < kCurThreads / 64; ++w)
 #pragma unroll
-        for (int j = 0; j < kMaxProj; ++j)
-            if (j < np)
-                out += gp(pj.EjN2)[at * kMaxProj + j] *
-                       (acc[4 * j] * acc[4 * j + 3] -
-                        acc[4 * j + 1] * acc[4 * j + 2]);
+                for (int u = 0; u < 4; ++u)
+                    s[u] += sbuf[w * NV + c[u]];
+            out += gp(pj.EjN2)[at * kMaxProj + j] *
+                   (s[0] * s[3] - s[1] * s[2]);
+        }
         a.nl[((size_t)sl * pj.natoms + at) * 3 + ax] = 2.0 * h3 * out;
     }
 }
@@ -150,7 +154,7 @@ hipError_t launch_current_nl(const CurArgs &a, int ns, hipStream_t st)
 {
     if (ns <= 0 || a.pj.natoms == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_current_nl, dim3(a.pj.natoms, ns, 3),
+    hipLaunchKernelGGL(k_current_nl, dim3(a.pj.natoms, ns),
                        dim3(kCurThreads), 0, st, a);
     return hipGetLastError();
 }
