@@ -51,11 +51,16 @@ KERNEL_SOURCES = ["ks_device.h", "ks_internal.h", "ks_hpsi.hip",
 
 
 def kernel_source_hash():
-    """Hash of the sources that determine the device code."""
+    """Hash of the sources that determine the device code, with comments
+    and whitespace left out (an edited comment does not make recorded
+    counters stale; any change of code does)."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(CSRC, name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(CSRC, name)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -1,7 +1,7 @@
-// Device-side building blocks shared by the gfx950 kernel files: complex
-// helpers, streaming loads and stores, reductions, Bloch phases, the H.psi
-// work item and the projector gather / apply work items.
-// gfx950 kernels of the real-time TDDFT hot path.
+// Device-side building blocks shared by the gfx950 kernel files of the
+// real-time TDDFT hot path: complex helpers, streaming loads and stores,
+// reductions, Bloch phases, the H.psi work item and the projector gather /
+// apply work items.
 //
 // H.psi = -1/2 Lap psi + (v + |A|^2/2) psi - i A.grad psi + V_NL psi on a
 // uniform grid (section "Periodic systems": finite-difference Laplacian and
@@ -18,9 +18,11 @@
 //  - the current xy plane (with 4 halo rows on each side) is staged in LDS for
 //    the x and y neighbours; x-rows are read as consecutive 16-byte complex
 //    values across the wavefront (coalesced);
-//  - the KB scatter is fused into the single store of the output; the Taylor
-//    recurrence scale, the final Taylor sum, the ETRS predictor and the
-//    density/norm partial sums are fused into the epilogue.
+//  - the KB term V_NL psi, formed on the projector hull rows by the apply
+//    work item, is read at hull points and added before the single store
+//    of the output; the Taylor recurrence scale, the final Taylor sum, the
+//    ETRS predictor and the density/norm partial sums are fused into the
+//    epilogue.
 #pragma once
 
 #include "ks_internal.h"
