@@ -20,10 +20,10 @@ def torch_cuda():
     return torch
 
 
-def both(torch, spec, v, psi, t):
+def both(torch, spec, v, psi, t, precision=0):
     """(ks_apply_h, ks_apply_h_noalloc) of every k-point's states."""
     from paper_1912_07921_amd import ks
-    g = ks.Grid(spec)
+    g = ks.Grid(spec, precision=precision)
     g.update_vlocal(torch.from_numpy(v).cuda())
     outs = []
     for k in range(spec.nk):
@@ -58,6 +58,20 @@ def test_noalloc_matches_apply_h_twice_second_smaller(torch_cuda):
     spec, v, psi = W.tiny(n=(12, 10, 9), h=(0.35, 0.3, 0.3), nstates=2,
                           natoms=2, lmax=1, rc=1.0, sigma=0.3, seed=9)
     check(both(torch, spec, v, psi, 0.0))
+
+
+def test_noalloc_matches_apply_h_mixed_many_states(torch_cuda):
+    """A grid in the mixed form (FP32 kernels, the potential's FP32 copy
+    in the scratch too) with 136 states (the projector apply's wide state
+    groups), then a smaller one: the same bitwise agreement."""
+    torch = torch_cuda
+    spec, v, psi = W.tiny(n=(14, 13, 12), h=(0.35, 0.35, 0.35),
+                          periodic=(1, 1, 1), nk=1, nstates=136, natoms=3,
+                          lmax=2, rc=1.3, sigma=0.4)
+    check(both(torch, spec, v, psi, 0.0, precision=1))
+    spec, v, psi = W.tiny(n=(10, 9, 8), nstates=3, natoms=2, lmax=1,
+                          rc=1.0, sigma=0.3, seed=11)
+    check(both(torch, spec, v, psi, 0.0, precision=1))
 
 
 def test_noalloc_refuses_states_beyond_its_scratch(torch_cuda):
