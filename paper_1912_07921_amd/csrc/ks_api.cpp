@@ -10,6 +10,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -1954,6 +1957,63 @@ int ks_propagate_cfm4(ks_grid *g, void *d_psi, const double *d_vion,
 // graph once and replayed.  Time-dependent inputs (A(t), output slots) come
 // from per-job device step counters, so the replayed graph needs no change.
 // ---------------------------------------------------------------------------
+// Device and pinned host blocks of the batch tables, kept for reuse by
+// later batches: a serving loop rebuilds its batch whenever a job joins or
+// leaves, and would otherwise allocate and free some 2 njobs + 20 blocks
+// (and a pinned buffer) each time.  Blocks come in power-of-two sizes from
+// 256 bytes, per device; the pool holds what the most tables resident at
+// once needed until the process ends.
+namespace {
+
+struct PoolBlock {
+    void *p;
+    size_t bytes;     // size class
+    int dev;
+    int pinned;       // 1: pinned host memory
+};
+
+std::mutex g_pool_mu;
+std::map<std::tuple<int, int, size_t>, std::vector<void *>> g_pool;
+
+int pool_get(size_t bytes, bool pinned, PoolBlock *out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return fail(KS_E_HIP, "hipGetDevice failed");
+    size_t c = 256;
+    while (c < bytes)
+        c <<= 1;
+    *out = PoolBlock{nullptr, c, dev, pinned ? 1 : 0};
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        auto &v = g_pool[std::make_tuple(out->pinned, dev, c)];
+        if (!v.empty()) {
+            out->p = v.back();
+            v.pop_back();
+            return KS_OK;
+        }
+    }
+    hipError_t e = pinned ? hipHostMalloc(&out->p, c, hipHostMallocDefault)
+                          : hipMalloc(&out->p, c);
+    if (e != hipSuccess) {
+        out->p = nullptr;
+        return fail(KS_E_OOM, "%s(%zu): %s",
+                    pinned ? "hipHostMalloc" : "hipMalloc", c,
+                    hipGetErrorString(e));
+    }
+    return KS_OK;
+}
+
+void pool_put(const PoolBlock &b)
+{
+    if (!b.p)
+        return;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_pool[std::make_tuple(b.pinned, b.dev, b.bytes)].push_back(b.p);
+}
+
+}  // namespace
+
 struct ks_batch {
     std::vector<ks_grid *> grids;
     std::vector<ks_job> jobs;
@@ -1963,7 +2023,7 @@ struct ks_batch {
     int hm = 2, rpt = 1, nthr = 64;
     size_t lds = 0;
     int grid_hpsi = 0, grid_proj = 0;
-    std::vector<void *> owned;
+    std::vector<PoolBlock> owned;   // from the block pool
     JobDev *d_jobs = nullptr;
     HArgs *d_hargs = nullptr;
     int *d_off[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -1997,14 +2057,16 @@ struct ks_batch {
 
 namespace {
 
-template <class T> int batch_alloc(ks_batch *b, T **p, size_t count)
+template <class T> int batch_alloc(ks_batch *b, T **p, size_t count,
+                                    bool pinned = false)
 {
-    void *q = nullptr;
-    hipError_t e = hipMalloc(&q, std::max<size_t>(count * sizeof(T), 16));
-    if (e != hipSuccess)
-        return fail(KS_E_OOM, "hipMalloc: %s", hipGetErrorString(e));
-    b->owned.push_back(q);
-    *p = static_cast<T *>(q);
+    PoolBlock blk;
+    const int rc = pool_get(std::max<size_t>(count * sizeof(T), 16), pinned,
+                            &blk);
+    if (rc)
+        return rc;
+    b->owned.push_back(blk);
+    *p = static_cast<T *>(blk.p);
     return KS_OK;
 }
 
@@ -2290,14 +2352,13 @@ int ks_batch_create(const ks_job *jobs, int njobs, void *stream,
     // non-finite norm flags, cleared once (they stay set once raised)
     if ((rc = batch_alloc(b, &b->d_flags, njobs)) ||
         hipMemset(b->d_flags, 0, njobs * sizeof(int)) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void **>(&b->h_flags),
-                      njobs * sizeof(int), hipHostMallocDefault) !=
-            hipSuccess ||
+        (rc = batch_alloc(b, &b->h_flags, njobs, true)) ||
         hipEventCreateWithFlags(&b->flag_ev, hipEventDisableTiming) !=
             hipSuccess) {
         ks_batch_destroy(b);
         return rc ? rc : fail(KS_E_HIP, "batch flag buffers");
     }
+    std::memset(b->h_flags, 0, njobs * sizeof(int));   // a reused block
     // FP32 potential copies of the mixed jobs, per exponential
     if (mixed) {
         std::vector<F32Copy> c0(njobs), c1(njobs);
@@ -2560,10 +2621,8 @@ int ks_batch_destroy(ks_batch *b)
         (void)hipGraphExecDestroy(b->exec);
     if (b->graph)
         (void)hipGraphDestroy(b->graph);
-    for (void *p : b->owned)
-        (void)hipFree(p);
-    if (b->h_flags)
-        (void)hipHostFree(b->h_flags);
+    for (const PoolBlock &blk : b->owned)
+        pool_put(blk);
     if (b->flag_ev)
         (void)hipEventDestroy(b->flag_ev);
     delete b;
