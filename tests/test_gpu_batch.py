@@ -214,6 +214,33 @@ def test_batch_full_size_with_small_job(torch_cuda):
     b.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_with_a_wide_row_job(torch_cuda, prec):
+    """A job of 512-point rows (a tile row fills the 512-thread workgroup)
+    beside a small periodic one: the batch launches every job's items with
+    the widest workgroup, and each job still ends bitwise as alone (or the
+    batch refuses the mix cleanly)."""
+    torch = torch_cuda
+    from paper_1912_07921_amd import ks
+    s1, v1, p1 = W.tiny(n=(512, 6, 7), h=(0.12, 0.4, 0.4), nstates=2,
+                        natoms=2, lmax=2, rc=1.1, sigma=0.35, xc=1)
+    s2, v2, p2 = W.tiny(n=(12, 11, 10), periodic=(1, 1, 1), nk=2,
+                        nstates=3, natoms=2, lmax=1, rc=1.0, sigma=0.35,
+                        xc=1, seed=5)
+    specs = [(s1, 0.3 * v1, normalised(s1, p1), 0.01, 0.0),
+             (s2, 0.3 * v2, normalised(s2, p2), 0.01, 0.0)]
+    alone = run_alone(torch, specs, 3, prec)
+    try:
+        b, jobs = make_batch(torch, specs, 3, prec)
+    except ks.KSError as e:
+        assert e.code == -4, e      # KS_E_UNSUPPORTED, nothing launched
+        return
+    b.step(3)
+    torch.cuda.synchronize()
+    assert_same(results(jobs), alone, f"wide rows, precision {prec}")
+    b.close()
+
+
 def test_batch_error_paths(torch_cuda):
     torch = torch_cuda
     from paper_1912_07921_amd import ks
