@@ -129,6 +129,17 @@ def test_propagate_widest_rows(torch_cuda, oracle_mod, prec):
         assert res["psi"] < 1e-5, res
 
 
+def test_apply_h_largest_grid(torch_cuda, oracle_mod):
+    """The largest grid the library takes: 512 x 512 x 511 points (just
+    under 2^27, so a state's last bytes sit just under the 2^31 byte
+    offsets of the buffer accesses), 512-point rows, an atom with s+p+d
+    projectors; every point against the oracle."""
+    spec, v, psi = W.tiny(n=(512, 512, 511), h=(0.1, 0.1, 0.1), nstates=1,
+                          natoms=1, lmax=2, rc=0.45, sigma=0.15, seed=13)
+    assert spec.npoints < 2 ** 27 and spec.npoints * 16 > 2 ** 31 - 2 ** 23
+    apply_parity(torch_cuda, oracle_mod, spec, v, psi)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_apply_h_many_states(torch_cuda, oracle_mod, prec):
     """A launch of 136 states (at least 128: the projector apply takes 8
