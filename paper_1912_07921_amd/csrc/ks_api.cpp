@@ -512,10 +512,11 @@ void layout(ks_grid *g)
     g->lay.vpred = take(N * 8);
     g->lay.dpart = take(ndb * 3 * 8);
     // Gram: split the grid so that about 2048 workgroups share the work
-    // (32 x 32 state tiles per k-point), each slice at least 512 points
+    // (gram_tile x gram_tile state tiles per k-point), each slice at least
+    // 512 points
     {
-        const long tiles = (long)((g->ns + 31) / 32) * ((g->ns + 31) / 32) *
-                           g->nk;
+        const long nt = (g->ns + gram_tile(g->ns) - 1) / gram_tile(g->ns);
+        const long tiles = nt * nt * g->nk;
         const long want = std::max<long>(1, (2048 + tiles - 1) / tiles);
         const long most = std::max<long>(1, (long)N / 512);
         g->gram_ksplit = (int)std::max<long>(1, std::min(want, most));

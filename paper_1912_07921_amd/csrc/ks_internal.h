@@ -76,6 +76,10 @@ struct ProjDev {
 
 constexpr int kHullChunk = 64;
 
+// State tile of one Gram workgroup: 64 x 64 states, or 32 x 32 when there
+// are at most 32 (a larger tile would be mostly empty).
+inline int gram_tile(int ns) { return ns > 32 ? 64 : 32; }
+
 struct HArgs {
     Geo geo;
     const void *in = nullptr;      // input states of this launch

@@ -249,17 +249,29 @@ __global__ __launch_bounds__(256) void k_kick(Geo G, double2 *psi,
 }
 
 // ---------------------------------------------------------------------------
-// Gram matrix partials: part[ks][k][i][j] = sum over the ks-th slice of the
-// grid of conj(psi_ki) psi_kj; 32 x 32 state tiles staged through LDS.
+// Gram matrix partials on the FP64 matrix cores: part[ks][k][i][j] = sum
+// over the ks-th slice of the grid of conj(psi_ki) psi_kj.  A workgroup
+// (four wavefronts) owns a T x T tile of (i, j) (T = 64, or 32 for few
+// states), each wavefront a T/2 x T/2 quarter as blocks of 16 x 16
+// accumulated by
+// v_mfma_f64_16x16x4f64 (D[16][16] += A[16][4] B[4][16], four grid points
+// per instruction): Re G = Ar^T Ar + Ai^T Ai and Im G = Ar^T Ai - Ai^T Ar,
+// with A the states' values at the points.  32 points of the tile's T + T
+// states are staged through LDS per round (coalesced rows of 512 bytes).
+// Operand layout on gfx950: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; D[4 r + l / 16][l % 16] is element r of lane l's
+// accumulator.
 // ---------------------------------------------------------------------------
-constexpr int kGT = 32;   // state tile
-constexpr int kGK = 32;   // points per LDS stage
+constexpr int kGK = 32;          // points per LDS stage
+typedef double gd4_t __attribute__((ext_vector_type(4)));
 
+template <int kGT>
 __global__ __launch_bounds__(256) void k_gram_partial(Geo G,
                                                       const double2 *psi,
                                                       int ns, int ksplit,
                                                       double2 *part)
 {
+    constexpr int B = kGT / 32;      // 16 x 16 blocks per wavefront side
     __shared__ double2 sa[kGT][kGK + 1];
     __shared__ double2 sb[kGT][kGK + 1];
     const int ntile = (ns + kGT - 1) / kGT;
@@ -269,41 +281,66 @@ __global__ __launch_bounds__(256) void k_gram_partial(Geo G,
     const long slice = (G.N + ksplit - 1) / ksplit;
     const long gb = ks * slice, ge = min(G.N, gb + slice);
     const double2 *pk = psi + (size_t)kk * ns * G.N;
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double2 acc[2][2];
-    for (int u = 0; u < 2; ++u)
-        for (int w = 0; w < 2; ++w)
-            acc[u][w] = make_double2(0.0, 0.0);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int r0 = (wave >> 1) * (kGT / 2), c0 = (wave & 1) * (kGT / 2);
+    const int li = lane & 15, lk = lane >> 4;
+    gd4_t re[B][B], im[B][B];
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+#pragma unroll
+        for (int w = 0; w < B; ++w) {
+            re[u][w] = gd4_t{0.0, 0.0, 0.0, 0.0};
+            im[u][w] = gd4_t{0.0, 0.0, 0.0, 0.0};
+        }
     for (long g0 = gb; g0 < ge; g0 += kGK) {
-        for (int e = threadIdx.x; e < kGT * kGK; e += blockDim.x) {
-            int r = e / kGK, c = e % kGK;
-            long g = g0 + c;
-            int si = ti * kGT + r, sj = tj * kGT + r;
+#pragma unroll
+        for (int u = 0; u < kGT / 8; ++u) {
+            const int r = (tid >> 5) + 8 * u, c = tid & 31;   // kGK = 32
+            const long g = g0 + c;
+            const int si = ti * kGT + r, sj = tj * kGT + r;
             sa[r][c] = (si < ns && g < ge) ? pk[(size_t)si * G.N + g]
                                            : make_double2(0.0, 0.0);
             sb[r][c] = (sj < ns && g < ge) ? pk[(size_t)sj * G.N + g]
                                            : make_double2(0.0, 0.0);
         }
         __syncthreads();
-        for (int c = 0; c < kGK; ++c)
-            for (int u = 0; u < 2; ++u) {
-                double2 av = sa[ty + 16 * u][c];
-                for (int w = 0; w < 2; ++w) {
-                    double2 bv = sb[tx + 16 * w][c];
-                    // conj(a) * b
-                    acc[u][w].x += av.x * bv.x + av.y * bv.y;
-                    acc[u][w].y += av.x * bv.y - av.y * bv.x;
-                }
+#pragma unroll
+        for (int k4 = 0; k4 < kGK; k4 += 4) {
+            double2 a[B], b[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                a[u] = sa[r0 + 16 * u + li][k4 + lk];
+                b[u] = sb[c0 + 16 * u + li][k4 + lk];
             }
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+#pragma unroll
+                for (int w = 0; w < B; ++w) {
+                    re[u][w] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                        a[u].x, b[w].x, re[u][w], 0, 0, 0);
+                    re[u][w] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                        a[u].y, b[w].y, re[u][w], 0, 0, 0);
+                    im[u][w] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                        a[u].x, b[w].y, im[u][w], 0, 0, 0);
+                    im[u][w] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                        -a[u].y, b[w].x, im[u][w], 0, 0, 0);
+                }
+        }
         __syncthreads();
     }
-    for (int u = 0; u < 2; ++u)
-        for (int w = 0; w < 2; ++w) {
-            int i = ti * kGT + ty + 16 * u, j = tj * kGT + tx + 16 * w;
-            if (i < ns && j < ns)
-                part[(((size_t)ks * gridDim.y + kk) * ns + i) * ns + j] =
-                    acc[u][w];
-        }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+#pragma unroll
+        for (int w = 0; w < B; ++w)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = ti * kGT + r0 + 16 * u + 4 * r + lk;
+                const int j = tj * kGT + c0 + 16 * w + li;
+                if (i < ns && j < ns)
+                    part[(((size_t)ks * gridDim.y + kk) * ns + i) * ns + j] =
+                        make_double2(re[u][w][r], im[u][w][r]);
+            }
 }
 
 __global__ __launch_bounds__(256) void k_gram_finalize(const double2 *part,
@@ -627,10 +664,15 @@ hipError_t launch_gram(const Geo &g, const double2 *psi, int nk, int ns,
                        double2 *part, int ksplit, double2 *out,
                        hipStream_t st)
 {
-    const int ntile = (ns + kGT - 1) / kGT;
+    const int T = gram_tile(ns);
+    const int ntile = (ns + T - 1) / T;
     dim3 grid(ntile * ntile, nk, ksplit);
-    hipLaunchKernelGGL(k_gram_partial, grid, dim3(256), 0, st, g, psi, ns,
-                       ksplit, part);
+    if (T == 64)
+        hipLaunchKernelGGL((k_gram_partial<64>), grid, dim3(256), 0, st, g,
+                           psi, ns, ksplit, part);
+    else
+        hipLaunchKernelGGL((k_gram_partial<32>), grid, dim3(256), 0, st, g,
+                           psi, ns, ksplit, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
