@@ -263,7 +263,6 @@ __global__ __launch_bounds__(256) void k_kick(Geo G, double2 *psi,
 // accumulator.
 // ---------------------------------------------------------------------------
 constexpr int kGK = 32;          // points per LDS stage
-typedef double gd4_t __attribute__((ext_vector_type(4)));
 
 template <int kGT>
 __global__ __launch_bounds__(256) void k_gram_partial(Geo G,
