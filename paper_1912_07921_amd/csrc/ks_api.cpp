@@ -253,6 +253,18 @@ int build_projectors(ks_grid *g, const ks_grid_desc *d)
     }
     g->total_pts = (long)sidx.size();
     g->nchunk = gather_chunks(*std::max_element(npts.begin(), npts.end()));
+    // gather work items (atom, chunk), ordered by the first point's plane
+    std::vector<int2> gpairs;
+    {
+        const int cp = gather_chunk_points();
+        std::vector<std::tuple<int, int, int>> key;   // (plane, atom, chunk)
+        for (int a = 0; a < na; ++a)
+            for (int c = 0; (long)c * cp < npts[a]; ++c)
+                key.emplace_back(sxyz[ioff[a] + (long)c * cp] >> 20, a, c);
+        std::sort(key.begin(), key.end());
+        for (const auto &k : key)
+            gpairs.push_back(make_int2(std::get<1>(k), std::get<2>(k)));
+    }
     g->h_npts = npts;
     g->h_nproj = nproj;
 
@@ -343,7 +355,7 @@ int build_projectors(ks_grid *g, const ks_grid_desc *d)
 
     int *d_nproj, *d_npts, *d_sidx, *d_sxyz, *d_sshift, *d_hxyz, *d_hc_off,
         *d_hc_atoms, *d_he_off, *d_he_slot, *d_he_code;
-    int2 *d_ent;
+    int2 *d_ent, *d_gpairs = nullptr;
     double *d_he_p;
     long *d_ioff;
     double *d_EjN2;
@@ -368,12 +380,15 @@ int build_projectors(ks_grid *g, const ks_grid_desc *d)
         (rc = dev_upload(g, &d_he_slot, he_slot)) ||
         (rc = dev_upload(g, &d_he_code, he_code)) ||
         (rc = dev_upload(g, &d_ent, ent)) ||
+        (!gpairs.empty() && (rc = dev_upload(g, &d_gpairs, gpairs))) ||
         (rc = dev_alloc(g, &d_he_p, (size_t)nent * kMaxProj)))
         return rc;
     g->pj.nproj = d_nproj;
     g->pj.npts = d_npts;
     g->pj.ioff = d_ioff;
     g->pj.sidx = d_sidx;
+    g->pj.ngpairs = (int)gpairs.size();
+    g->pj.gpairs = d_gpairs;
     g->pj.sxyz = d_sxyz;
     g->pj.sshift = d_sshift;
     g->pj.EjN2 = d_EjN2;

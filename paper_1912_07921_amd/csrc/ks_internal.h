@@ -72,6 +72,12 @@ struct ProjDev {
     const int *he_slot = nullptr;
     const int *he_code = nullptr;
     const double *he_p = nullptr;
+    // the gather's (atom, chunk) work items in dispatch order: sorted by
+    // the z plane of the chunk's first point (sphere points are stored z
+    // major), so that chunks of overlapping spheres that cover the same
+    // planes run together and share the L2
+    int ngpairs = 0;
+    const int2 *gpairs = nullptr;
 };
 
 constexpr int kHullChunk = 64;
@@ -171,6 +177,7 @@ hipError_t launch_hull_table(const ProjDev &pj, const Geo &g,
                              const int2 *ent, long nent, double *he_p,
                              hipStream_t st);
 int gather_chunks(int max_npts);
+int gather_chunk_points();          // sphere points per gather chunk
 int density_blocks(long N);
 hipError_t launch_density(const DArgs &a, hipStream_t st);
 hipError_t launch_dipole_finalize(const double *dpart, int nblocks,
