@@ -123,6 +123,26 @@ def test_large_system_apply_h_sampled(torch_cuda, oracle_mod, c5_full):
     del hp
 
 
+def test_large_system_apply_h_sampled_mixed(torch_cuda, oracle_mod, c5_full):
+    """The FP32 form on all 256 states: its projector gather is a launch
+    large enough (45k workgroups) to run in plane order."""
+    from paper_1912_07921_amd import ks
+    w = c5_full.w
+    g = ks.Grid(w.spec, precision=ks.KS_MIXED)
+    try:
+        g.set_launch(*c5_full.shape)
+        g.update_vlocal(torch_cuda.from_numpy(w.vion).cuda())
+        hp = g.apply_h(c5_full.psi0[0])
+        o = oracle_mod.Oracle(sub_spec(w.spec, [0]))
+        for s in (0, 97, 255):
+            want = o.apply_h(w.vion, w.psi0[0, s][None])[0]
+            e = rel(hp[s].cpu().numpy(), want)
+            assert 1e-10 < e < 1e-5, (s, e)
+        del hp
+    finally:
+        g.close()
+
+
 # --------------------------------------------------------------------------
 # non-linear (LDA exchange on) at the full grids, fewer states
 # --------------------------------------------------------------------------
