@@ -200,6 +200,33 @@ def run_gpu(w, precision, steps, warmup, torch, tune=True, shape=None,
     return sec, dip, n.cpu().numpy(), prof, g, g.get_launch()
 
 
+def run_apply_h(g, w, torch, reps=5):
+    """Standalone H.psi (ks_apply_h: projector gather and apply, then one
+    stencil pass) over every state of the workload, one call per k-point;
+    HIP events around `reps` rounds on the grid's stream.  Algorithmic
+    bytes: 32 per point-state (read psi, write H psi)."""
+    nk, ns, N = w.spec.nk, w.spec.nstates, w.spec.npoints
+    psi = to_dev(torch, w.psi0).reshape(nk, ns * N)
+    out = torch.empty_like(psi[0])
+    for k in range(nk):
+        g.apply_h(psi[k], out, k=k)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        for k in range(nk):
+            g.apply_h(psi[k], out, k=k)
+    e1.record(st)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    gbs = 32.0 * N * nk * ns / sec / 1e9
+    return dict(value=N * nk * ns / sec, unit="grid-point·states/s",
+                ms_per_call=round(1e3 * sec, 3), achieved_GBs=round(gbs, 1),
+                frac=round(gbs / HBM_PEAK_GBS, 4))
+
+
 def fft_length(n, periodic):
     """Transform length of the Hartree solver along an axis of n points:
     n (periodic) or the smallest product of 2, 3, 5 >= 2 n - 1."""
@@ -559,9 +586,13 @@ def main():
     fixed = tuple(int(v) for v in args.shape.split(",")) if args.shape \
         else None
     dipc64 = None
-    sec, dip64, nrm64, prof, _, shape = run_gpu(w, 0, args.steps,
-                                                args.warmup, torch,
-                                                not args.no_tune, fixed)
+    sec, dip64, nrm64, prof, g64, shape = run_gpu(w, 0, args.steps,
+                                                  args.warmup, torch,
+                                                  not args.no_tune, fixed)
+    log("standalone H.psi (ks_apply_h) over every state")
+    apply_h = {"fp64": run_apply_h(g64, w, torch)}
+    g64.close()
+    del g64
     value = units * args.steps / sec
     hp_ms, hp_n = prof["hpsi"]
     avg_ms = hp_ms / max(hp_n, 1)
@@ -615,6 +646,7 @@ def main():
         "roofline": roofline,
         "step_roofline": step_roofline,
         "kernels": kernel_times,
+        "apply_h": apply_h,
         # the paper reports no H.psi rate or bandwidth, only relative
         # whole-run GPU speed-ups on other hardware (context, not a target)
         "paper_context": ("Octopus GPU port on NVIDIA V100: a full GPU node "
@@ -627,9 +659,12 @@ def main():
         log(f"mixed: {args.warmup} warmup + {args.steps} timed steps")
         mfixed = (tuple(int(v) for v in args.mixed_shape.split(","))
                   if args.mixed_shape else None)
-        msec, dipm, nrmm, mprof, _, mshape = run_gpu(w, 1, args.steps,
-                                                     args.warmup, torch,
-                                                     not args.no_tune, mfixed)
+        msec, dipm, nrmm, mprof, gm, mshape = run_gpu(w, 1, args.steps,
+                                                      args.warmup, torch,
+                                                      not args.no_tune, mfixed)
+        apply_h["mixed"] = run_apply_h(gm, w, torch)
+        gm.close()
+        del gm
         mh_ms, mh_n = mprof["hpsi"]
         mavg = mh_ms / max(mh_n, 1)
         mach = STEP_BYTES[1] / 8.0 * N * S / (mavg / 1e3) / 1e9
