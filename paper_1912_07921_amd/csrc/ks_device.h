@@ -1132,14 +1132,18 @@ __device__ __forceinline__ void gather_finalize_item(const GArgs &a,
 // wavefront): no LDS staging, no barrier, no per-lane coefficient read.
 // (Staging the coefficients in LDS and reading them per lane cost 23 %
 // more at 128^3 x 256, 26 % more in the FP32 kernels.)
-// States per wavefront: 8 for launches of many states (fewer hull-entry
-// walks and table reads per state), 4 for few (more workgroups): 128^3 x
-// 256 FP64 1.02 -> 0.92 ms with 8; 64^3 x 32 12.3 -> 16.6 us with 8.
+// States per wavefront: for launches of many states 8 in FP64 and 16 in
+// FP32 (fewer hull-entry walks and table reads per state), 4 for few (more
+// workgroups): 128^3 x 256 FP64 1.02 -> 0.92 ms with 8 (1.01 ms with 16),
+// FP32 0.74 -> 0.68 ms with 16; 64^3 x 32 12.3 -> 16.6 us with 8.
 #ifndef KS_APPLY_SPW_SMALL
 #define KS_APPLY_SPW_SMALL 4
 #endif
 #ifndef KS_APPLY_SPW_LARGE
 #define KS_APPLY_SPW_LARGE 8
+#endif
+#ifndef KS_APPLY_SPW_LARGE32
+#define KS_APPLY_SPW_LARGE32 16
 #endif
 #ifndef KS_APPLY_LARGE_NS
 #define KS_APPLY_LARGE_NS 128
@@ -1149,11 +1153,13 @@ __device__ __forceinline__ void gather_finalize_item(const GArgs &a,
 #endif
 constexpr int kApplyWaves = KS_APPLY_WAVES;
 constexpr int kApplyThreads = 64 * kApplyWaves;
-// states per wavefront of a single-grid launch of ns states (the batched
-// launch, whose jobs are small, takes the small count)
-__host__ __device__ constexpr int apply_spw(int ns)
+// states per wavefront of a single-grid launch of ns states in FP64 or
+// FP32 (the batched launch, whose jobs are small, takes the small count)
+__host__ __device__ constexpr int apply_spw(int ns, bool fp32)
 {
-    return ns >= KS_APPLY_LARGE_NS ? KS_APPLY_SPW_LARGE : KS_APPLY_SPW_SMALL;
+    return ns < KS_APPLY_LARGE_NS
+               ? KS_APPLY_SPW_SMALL
+               : (fp32 ? KS_APPLY_SPW_LARGE32 : KS_APPLY_SPW_LARGE);
 }
 // state groups of the apply for ns states at spw states per wavefront
 __host__ __device__ constexpr int apply_groups(int ns, int spw)

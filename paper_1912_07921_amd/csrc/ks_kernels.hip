@@ -476,18 +476,19 @@ hipError_t launch_kbapply(bool mixed, const GArgs &a, int ns, hipStream_t st)
         return hipSuccess;
     GArgs b = a;
     b.ns = ns;
-    const int spw = apply_spw(ns);
+    const int spw = apply_spw(ns, mixed);
     dim3 grid(a.pj.nhchunk, apply_groups(ns, spw));
-    constexpr int SL = KS_APPLY_SPW_LARGE, SS = KS_APPLY_SPW_SMALL;
+    constexpr int SL = KS_APPLY_SPW_LARGE, SS = KS_APPLY_SPW_SMALL,
+                  SL32 = KS_APPLY_SPW_LARGE32;
     if (!mixed && spw == SL)
         hipLaunchKernelGGL((k_kbapply<double, SL>), grid,
                            dim3(kApplyThreads), 0, st, b);
     else if (!mixed)
         hipLaunchKernelGGL((k_kbapply<double, SS>), grid,
                            dim3(kApplyThreads), 0, st, b);
-    else if (spw == SL)
-        hipLaunchKernelGGL((k_kbapply<float, SL>), grid, dim3(kApplyThreads),
-                           0, st, b);
+    else if (spw == SL32)
+        hipLaunchKernelGGL((k_kbapply<float, SL32>), grid,
+                           dim3(kApplyThreads), 0, st, b);
     else
         hipLaunchKernelGGL((k_kbapply<float, SS>), grid, dim3(kApplyThreads),
                            0, st, b);
