@@ -1067,6 +1067,7 @@ __device__ __forceinline__ void gather_item(const GArgs &a, const int at,
     // workgroup (wave, state, projector, re/im) gets the lanes' values as
     // rows; thread c then adds its column in lane order (deterministic)
     constexpr int kCols = 4 * kGatherSPW * 2 * kMaxProj;
+    static_assert(kCols <= 256, "one thread of the workgroup per column");
     __shared__ R red[kCols][65];
     __syncthreads();               // the previous item's reads are done
 #pragma unroll
