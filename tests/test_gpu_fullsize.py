@@ -105,6 +105,31 @@ def test_periodic_kpoints_laser_full_size(torch_cuda, oracle_mod, c3_full):
                               [(0, 3), (1, 40), (3, 63)], 3, t0)
 
 
+def test_periodic_many_states_gather_in_plane_order(torch_cuda, oracle_mod):
+    """The periodic grid with 4 k-points x 344 states: the projector gather
+    covers 8256 workgroups and runs in plane order (Bloch shift phases
+    included); sampled states of every k-point against the oracle."""
+    import copy
+    # 4 x 344 states (a gather of 48 work items x 172 state groups): 172
+    # smooth states and the same states times a phase (the smooth family
+    # has 343 modes); with exchange off each state evolves on its own
+    w = W.c3(nsteps=1, nstates=172)
+    w.spec = copy.copy(w.spec)
+    w.spec.nstates = 344
+    w.spec.occ = np.concatenate([w.spec.occ, w.spec.occ])
+    w.psi0 = np.concatenate([w.psi0, w.psi0 * np.exp(0.7j)], axis=1)
+    f = Full(torch_cuda, w)
+    try:
+        t0 = 0.5 * f.w.spec.laser[2]
+        linear_propagation_parity(torch_cuda, oracle_mod, f,
+                                  [(0, 0), (1, 117), (2, 343), (3, 200)], 1,
+                                  t0)
+    finally:
+        f.g.close()
+        del f.psi0
+        torch_cuda.cuda.empty_cache()
+
+
 def test_large_system_full_size(torch_cuda, oracle_mod, c5_full):
     linear_propagation_parity(torch_cuda, oracle_mod, c5_full,
                               [(0, 0), (0, 255)], 2, 0.0)
