@@ -243,6 +243,17 @@ def test_gram_tiles(torch_cuda, oracle_mod, nstates):
         assert np.abs(G - np.eye(nstates)[None]).max() < 1e-11
 
 
+def test_gram_ragged_grid(torch_cuda, oracle_mod):
+    """70 states (two 64-state tiles, the second ragged) on a 17^3 grid
+    (4913 points: the last 32-point stage of a slice is partly empty)."""
+    torch = torch_cuda
+    w = W.c3(nsteps=1, nstates=70, n=17, h=0.45)
+    o = oracle_mod.Oracle(w.spec)
+    G = grid(w.spec).gram(dev(torch, w.psi0)).cpu().numpy()
+    Go = o.gram(w.psi0)
+    assert np.abs(G - Go).max() < 1e-12 * np.abs(Go).max()
+
+
 # ---------------------------------------------------------------------------
 # ETRS propagation
 # ---------------------------------------------------------------------------
